@@ -1,0 +1,34 @@
+"""Small configurations for tests (a few thousand unknowns)."""
+import copy
+
+from workloads.configs import ARCMIN, _check, _layers, _wfs, ring_angles
+
+
+def tiny_config(tt=True, obstruction=0.2):
+    """4 m pupil, 8x8 Fried sensors; 2 LGS (tip/tilt removed), 1 high-order
+    NGS and optionally a 2x2 low-order NGS; 2 layers of 32x32, 3 levels."""
+    lgs = ring_angles(2, 1.0)
+    wfs = [_wfs(True, t, 8) for t in lgs]
+    wfs.append(_wfs(False, (0.2 * ARCMIN, -0.1 * ARCMIN), 8))
+    if tt:
+        wfs.append(_wfs(False, (-0.3 * ARCMIN, 0.25 * ARCMIN), 8, tt_aggregate=2))
+    return _check({
+        "name": "tiny", "cfg_id": 900,
+        "diameter": 4.0, "obstruction": obstruction,
+        "layers": _layers([0.0, 6e3], [0.7, 0.3], [32, 32]),
+        "levels": 3,
+        "wfs": wfs,
+        "alpha": 1.0, "r0": 0.15, "L0": 25.0,
+        "noise_frac": 0.1, "n_iter": 8, "warm": False,
+    })
+
+
+def tiny_ragged_config():
+    """Two layers of different, non-power-of-two sizes (40 and 48 = 5 and 6
+    tiles of 8) so that tiled kernels see ragged edges."""
+    cfg = tiny_config(tt=True)
+    cfg = copy.deepcopy(cfg)
+    cfg["name"] = "tiny-ragged"
+    cfg["cfg_id"] = 901
+    cfg["layers"] = _layers([0.0, 6e3], [0.7, 0.3], [40, 48])
+    return _check(cfg)
