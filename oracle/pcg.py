@@ -15,14 +15,16 @@ STATUS_OK, STATUS_CONVERGED, STATUS_BREAKDOWN = 0, 1, -1
 def pcg(apply_A, b, n_iter, x0=None, jacobi=None, true_residuals=False):
     """Returns (x, info).  ``jacobi`` is the preconditioner diagonal (None for
     plain CG).  info: rho history, step sizes, status and, if asked, the true
-    residual norms |b - A x_i| for i = 0..n_iter."""
+    residual norms |b - A x_i| for i = 0..n_iter; "rnorm" holds the recursive
+    residual norms |r_i|."""
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     r = b - apply_A(x) if x0 is not None else b.copy()
     z = r / jacobi if jacobi is not None else r.copy()
     p = z.copy()
     rho = float(r @ z)
-    info = {"rho": [rho], "alpha": [], "beta": [], "status": STATUS_OK, "iters": 0}
+    info = {"rho": [rho], "alpha": [], "beta": [], "status": STATUS_OK, "iters": 0,
+            "rnorm": [float(np.linalg.norm(r))]}
     if true_residuals:
         info["resid"] = [float(np.linalg.norm(b - apply_A(x)))]
     for i in range(n_iter):
@@ -45,6 +47,7 @@ def pcg(apply_A, b, n_iter, x0=None, jacobi=None, true_residuals=False):
         info["alpha"].append(a)
         info["beta"].append(beta)
         info["rho"].append(rho)
+        info["rnorm"].append(float(np.linalg.norm(r)))
         info["iters"] = i + 1
         if true_residuals:
             info["resid"].append(float(np.linalg.norm(b - apply_A(x))))

@@ -1,0 +1,150 @@
+// Internal structures shared by the plan builder and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wmcao.h"
+
+#define WM_MAXL 16        // layers per plan
+#define WM_MAXW 16        // sensors per plan
+#define WM_MAXLEV 8       // wavelet levels
+#define WM_MAXCELL 16     // cells of a low-order sensor (k <= 4)
+#define WM_MAXJP 8        // plans packed into one launch
+#define WM_QMAX 16        // elements per thread of the 1024-thread kernels
+#define WM_NSUB_MAX 127   // nodes per sensor <= 128^2
+
+namespace wm {
+
+// Kinds of per-frame vectors a kernel can read or write.
+enum Vec : int {
+    V_X = 0,      // caller's coefficients (x0 in, x out)
+    V_B,          // right side
+    V_R,          // residual
+    V_P,          // search direction
+    V_Q,          // A p
+    V_PHI,        // layer pixel fields (scratch)
+    V_LL,         // intermediate low-pass bands (scratch)
+    V_NODE,       // sensor node fields (scratch)
+    V_SLOPES,     // caller's slopes (in)
+    V_IN,         // caller's generic input
+    V_OUT,        // caller's generic output
+    NV
+};
+
+// Per-frame partial-sum segments (deterministic reductions, one slot per block).
+enum Part : int { PT_PQ = 0, PT_RZ0, PT_RZ1, PT_RR0, PT_RR1, NPT };
+
+struct LayerInfo {
+    int N;                          // pixels per side
+    int k0;                         // levels done by tiled kernels (0..levels-1)
+    int64_t coff;                   // offset in a coefficient / pixel frame vector
+    int64_t ll_off[WM_MAXLEV + 1];  // offset of LL_k (k = 1..k0) in a frame's LL scratch
+    double D[WM_MAXLEV];            // prior at scale index k (entry k-1), alpha not applied
+};
+
+struct WfsInfo {
+    int n_sub, nn;          // subapertures across, nodes across (n_sub + 1)
+    int S_fine;             // active fine subapertures
+    int S;                  // measurements (S_fine, or active cells)
+    int agg;                // 0 or k of a k x k low-order sensor
+    int remove_tt;
+    int in_precond;
+    int pad_;
+    int64_t soff;           // slope offset in a frame
+    int64_t node_off;       // node-field offset in a frame's node scratch
+    const int* act;         // [S_fine] packed i * n_sub + j (row-major)
+    const int* cell_of;     // [S_fine] measurement (cell) index of each fine subaperture
+    const int* cell_count;  // [S] fine subapertures per cell
+    const double* blocks;   // [S][3] (a, b, c) of the symmetric 2x2 block of C~^-1
+    const int* maskmap;     // [n_sub * n_sub] measurement index of a fine subaperture or -1
+};
+
+struct PlanDev {
+    int L, W, levels, dtype;
+    int precond;
+    int n_fdwt_slots;       // partial slots written by one wavelet-analysis pass per frame
+    int n_vec_slots;        // partial slots written by one vector pass per frame
+    int slots;              // stride of one partial segment
+    int64_t n, n_slopes, n_nodes, ll_size;
+    double alpha;
+    double h[6], g[6];      // db3 analysis filters
+    LayerInfo layer[WM_MAXL];
+    WfsInfo wfs[WM_MAXW];
+    // projection tables, per (sensor, layer): node_tab_off -> [nn] entries,
+    // pix_tab_off -> [N_l] entries.
+    const int* ix0;
+    const int* jy0;
+    const double* tx;       // bilinear weight of the right/upper pixel per node
+    const double* ty;
+    const int* pfx;         // first node touching pixel row p
+    const int* pcx;         // number of nodes touching pixel row p
+    const int* pfy;
+    const int* pcy;
+    int node_tab_off[WM_MAXW][WM_MAXL];
+    int pix_tab_off[WM_MAXW][WM_MAXL];
+    const void* jac;        // [n] Jacobi diagonal, plan dtype
+};
+
+struct JobPlan {
+    const PlanDev* P;       // device copy of the plan constants
+    void* vec[NV];          // frame-0 base pointer of each vector kind
+    int64_t stride[NV];     // frame stride (elements)
+    double* part;           // [frames][NPT * slots]
+    double* alpha;          // [frames] step size of the current iteration
+    int* status;            // [frames] WMCAO_FRAME_*
+    double* resid;          // optional [frames][resid_ld]
+    int resid_ld;
+    int nframes;
+};
+
+struct JobArgs {
+    int njp;
+    int pad_;
+    JobPlan jp[WM_MAXJP];
+};
+
+// One block's work: plan slot, frame, layer or sensor, tile or chunk, partial slot.
+struct Item {
+    int jp, frame, a, b, slot, pad0, pad1, pad2;
+};
+
+enum SrcMode : int { SRC_LL = 0, SRC_PIX = 1, SRC_PT = 2 };
+enum EpiMode : int { EPI_NONE = 0, EPI_APPLY = 1 };
+enum SensorMode : int { SM_APPLY = 0, SM_RHS = 1, SM_FWD = 2 };
+
+// ---- launchers (defined in wmcao_kernels.hip) --------------------------------
+template <class T>
+void launch_idwt_coarse(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
+                        int lds_bytes, hipStream_t s);
+template <class T>
+void launch_idwt_tile(const JobArgs& a, const Item* items, int n, int level, int in_vec,
+                      int out_vec, int tile, hipStream_t s);
+template <class T>
+void launch_fdwt_tile(const JobArgs& a, const Item* items, int n, int level, int src, int in_vec,
+                      int out_vec, int epi, int aux_vec, int tile, hipStream_t s);
+template <class T>
+void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int in_vec,
+                        int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s);
+template <class T>
+void launch_sensor(const JobArgs& a, const Item* items, int n, int mode, int in_vec, int out_vec,
+                   int lds_bytes, hipStream_t s);
+template <class T>
+void launch_init(const JobArgs& a, const Item* items, int n, int warm, hipStream_t s);
+template <class T>
+void launch_update_r(const JobArgs& a, const Item* items, int n, int iter, hipStream_t s);
+template <class T>
+void launch_update_p(const JobArgs& a, const Item* items, int n, int iter, hipStream_t s);
+template <class T>
+void launch_replace_r(const JobArgs& a, const Item* items, int n, int iter, hipStream_t s);
+void launch_jacobi(const PlanDev* P, const double* protos, const int* proto_off,
+                   const double* txd, const double* tyd, const double* blocksd,
+                   int64_t n, double* out, hipStream_t s);
+void configure_kernels();
+template <class T>
+void launch_cast_from_double(const double* in, T* out, int64_t n, hipStream_t s);
+
+constexpr int VEC_CHUNK = 2048;   // elements per block of the vector kernels
+
+}  // namespace wm

@@ -1,0 +1,1105 @@
+// HIP kernels of the wavelet-domain MCAO tomography solve, written for CDNA4
+// (gfx950, 64-wide wavefronts).  Every stage of one operator apply is here:
+//
+//   W^-1  : k_idwt_coarse (whole low-pass band in LDS) + k_idwt_tile (one
+//           level per launch, LDS tiles with a 2-coefficient halo)
+//   P, Gamma, C^-1, (I-T), Gamma^T : k_sensor (one block per sensor and frame,
+//           node field in LDS, deterministic block reductions for tip/tilt)
+//   P^T + W + alpha D + <p,Ap> : k_fdwt_tile (P^T gathered straight into the
+//           analysis tile, no atomics) + k_fdwt_coarse
+//   PCG vector updates with FP64 partial inner products: k_init, k_update_r,
+//           k_update_p, k_replace_r
+//   plan time: k_jacobi (separable closed form of the Jacobi diagonal)
+//
+// Storage type T (float or double) is what crosses HBM and LDS tiles; every
+// sum, product and filter tap is evaluated in FP64 registers (type Acc), so the
+// FP32 path pays single-precision rounding only where a value is stored.  All
+// inner products are accumulated in FP64 and reduced in a fixed order (one
+// partial per block, summed by the consumer), so a frame's result does not
+// depend on what else is in the batch.
+#include "wmcao_internal.hpp"
+
+namespace wm {
+
+using Acc = double;
+
+// ---------------------------------------------------------------- helpers ----
+template <class T>
+__device__ __forceinline__ T* vptr(const JobPlan& J, int v, int frame) {
+    return reinterpret_cast<T*>(J.vec[v]) + static_cast<int64_t>(frame) * J.stride[v];
+}
+
+__device__ __forceinline__ double* part_ptr(const JobPlan& J, int frame, int seg) {
+    const int slots = J.P->slots;
+    return J.part + static_cast<int64_t>(frame) * (NPT * slots) + seg * slots;
+}
+
+// Deterministic block sum (fixed shuffle tree, then wave partials in order).
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) s += red[i];
+        red[16] = s;
+    }
+    __syncthreads();
+    return red[16];
+}
+
+__device__ double sum_slots(const double* p, int n, double* red) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+    return block_sum(v, red);
+}
+
+// Scale index k (1 = finest details, levels = coarsest details and low-pass)
+// of the Mallat coefficient (x, y) of an N x N layer.
+__device__ __forceinline__ int level_of(int x, int y, int N, int levels) {
+    const int m = x > y ? x : y;
+    int k = levels;
+    for (int lev = levels; lev >= 1; --lev)
+        if (m >= (N >> lev)) k = lev;
+    return k;
+}
+
+__device__ __forceinline__ void load_filters(const PlanDev& P, Acc* hf, Acc* gf) {
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+        hf[n] = P.h[n];
+        gf[n] = P.g[n];
+    }
+}
+
+// One in-place periodic synthesis step on the leading M x M block of A (row
+// stride ld), along y (columns within a row) or along x, staged through
+// registers: x_i = sum over the 3 coarse k with 0 <= i - 2k < 6 of
+// h[i-2k] lo_k + g[i-2k] hi_k.
+template <class T>
+__device__ void syn_pass(T* A, int ld, int M, int along_y, const Acc* hf, const Acc* gf) {
+    const int H = M >> 1, cnt = M * M;
+    T reg[WM_QMAX];
+#pragma unroll
+    for (int r = 0; r < WM_QMAX; ++r) {
+        const int e = threadIdx.x + r * blockDim.x;
+        if (e < cnt) {
+            const int row = e / M, col = e - (e / M) * M;
+            const int i = along_y ? col : row;
+            const int base = i >> 1, par = i & 1;
+            Acc acc = 0;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                int k = base - t;
+                if (k < 0) k += H;
+                const int n = par + 2 * t;
+                const Acc lo = along_y ? A[row * ld + k] : A[k * ld + col];
+                const Acc hi = along_y ? A[row * ld + H + k] : A[(H + k) * ld + col];
+                acc += hf[n] * lo + gf[n] * hi;
+            }
+            reg[r] = static_cast<T>(acc);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < WM_QMAX; ++r) {
+        const int e = threadIdx.x + r * blockDim.x;
+        if (e < cnt) {
+            const int row = e / M, col = e - (e / M) * M;
+            A[row * ld + col] = reg[r];
+        }
+    }
+    __syncthreads();
+}
+
+// One in-place periodic analysis step: a_c = sum_n h_n x[(2c+n) mod M] into
+// the low half, d_c with g into the high half.
+template <class T>
+__device__ void ana_pass(T* A, int ld, int M, int along_y, const Acc* hf, const Acc* gf) {
+    const int H = M >> 1, cnt = M * M;
+    T reg[WM_QMAX];
+#pragma unroll
+    for (int r = 0; r < WM_QMAX; ++r) {
+        const int e = threadIdx.x + r * blockDim.x;
+        if (e < cnt) {
+            const int row = e / M, col = e - (e / M) * M;
+            const int c = along_y ? col : row;
+            const bool hi = c >= H;
+            const int cc = hi ? c - H : c;
+            Acc acc = 0;
+#pragma unroll
+            for (int n = 0; n < 6; ++n) {
+                int idx = 2 * cc + n;
+                if (idx >= M) idx -= M;
+                const Acc v = along_y ? A[row * ld + idx] : A[idx * ld + col];
+                acc += (hi ? gf[n] : hf[n]) * v;
+            }
+            reg[r] = static_cast<T>(acc);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < WM_QMAX; ++r) {
+        const int e = threadIdx.x + r * blockDim.x;
+        if (e < cnt) {
+            const int row = e / M, col = e - (e / M) * M;
+            A[row * ld + col] = reg[r];
+        }
+    }
+    __syncthreads();
+}
+
+// Adjoint projection of all sensors onto pixel (px, py) of layer l:
+// g = sum_m sum_{a,b} wx_m(a,px) wy_m(b,py) v_m[a][b], where node a of sensor m
+// touches pixel px with weight 1-t if its left pixel is px and t if it is
+// px-1 (the transpose of the bilinear samples, gathered without atomics).
+template <class T>
+__device__ Acc pt_gather(const PlanDev& P, const T* nodes, int l, int px, int py) {
+    const double* txp = P.tx;
+    const double* typ = P.ty;
+    Acc acc = 0;
+    for (int m = 0; m < P.W; ++m) {
+        const int po = P.pix_tab_off[m][l];
+        const int cx = P.pcx[po + px];
+        if (cx == 0) continue;
+        const int cy = P.pcy[po + py];
+        if (cy == 0) continue;
+        const int fx = P.pfx[po + px], fy = P.pfy[po + py];
+        const int no = P.node_tab_off[m][l];
+        const int nn = P.wfs[m].nn;
+        const T* vm = nodes + P.wfs[m].node_off;
+        for (int a = fx; a < fx + cx; ++a) {
+            const Acc t = txp[no + a];
+            const Acc wa = (P.ix0[no + a] == px) ? (1.0 - t) : t;
+            Acc row = 0;
+            for (int b = fy; b < fy + cy; ++b) {
+                const Acc s = typ[no + b];
+                const Acc wb = (P.jy0[no + b] == py) ? (1.0 - s) : s;
+                row += wb * static_cast<Acc>(vm[a * nn + b]);
+            }
+            acc += wa * row;
+        }
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------------ W^-1 ----
+// Levels J..k0+1 of the synthesis of one layer, with the whole M0 x M0
+// (M0 = N / 2^k0) low-pass block resident in LDS.
+template <class T>
+__global__ void __launch_bounds__(1024)
+k_idwt_coarse(const JobArgs args, const Item* __restrict__ items, int in_vec, int out_vec) {
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    const LayerInfo& Ly = P.layer[it.a];
+    const int N = Ly.N, k0 = Ly.k0, M0 = N >> k0;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* A = reinterpret_cast<T*>(smem_raw);
+    Acc hf[6], gf[6];
+    load_filters(P, hf, gf);
+    const T* src = vptr<T>(J, in_vec, it.frame) + Ly.coff;
+    for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x)
+        A[e] = src[static_cast<int64_t>(e / M0) * N + (e % M0)];
+    __syncthreads();
+    for (int lev = P.levels; lev > k0; --lev) {
+        const int M = N >> (lev - 1);
+        syn_pass<T>(A, M0, M, 0, hf, gf);   // undo the x step
+        syn_pass<T>(A, M0, M, 1, hf, gf);   // undo the y step
+    }
+    T* dst;
+    int ld;
+    if (k0 > 0) {
+        dst = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[k0];
+        ld = M0;
+    } else {
+        dst = vptr<T>(J, out_vec, it.frame) + Ly.coff;
+        ld = N;
+    }
+    for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x)
+        dst[static_cast<int64_t>(e / M0) * ld + (e % M0)] = A[e];
+}
+
+// One synthesis level k <= k0 over a TS x TS output tile: reads the low-pass
+// band LL_k (scratch) and the three level-k detail bands (Mallat regions of the
+// input coefficients) on a (TS/2+2)^2 window, writes LL_{k-1} (scratch) or, at
+// k = 1, the layer pixels.
+template <class T, int TS>
+__global__ void __launch_bounds__(256)
+k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int in_vec,
+            int out_vec) {
+    constexpr int CW = TS / 2 + 2;
+    __shared__ T sLL[CW][CW + 1], sLH[CW][CW + 1], sHL[CW][CW + 1], sHH[CW][CW + 1];
+    __shared__ T sAL[TS][CW + 1], sAH[TS][CW + 1];
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    const LayerInfo& Ly = P.layer[it.a];
+    const int N = Ly.N, M = N >> (level - 1), H = M >> 1;
+    const int ntx = (M + TS - 1) / TS;
+    const int x0 = (it.b % ntx) * TS, y0 = (it.b / ntx) * TS;
+    Acc hf[6], gf[6];
+    load_filters(P, hf, gf);
+    const T* src = vptr<T>(J, in_vec, it.frame) + Ly.coff;
+    const T* ll = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[level];
+    const int cx0 = (x0 >> 1) - 2, cy0 = (y0 >> 1) - 2;
+    for (int e = threadIdx.x; e < CW * CW; e += blockDim.x) {
+        const int a = e / CW, b = e % CW;
+        int gx = (cx0 + a) % H;
+        if (gx < 0) gx += H;
+        int gy = (cy0 + b) % H;
+        if (gy < 0) gy += H;
+        sLL[a][b] = ll[gx * H + gy];
+        sLH[a][b] = src[static_cast<int64_t>(gx) * N + H + gy];
+        sHL[a][b] = src[static_cast<int64_t>(H + gx) * N + gy];
+        sHH[a][b] = src[static_cast<int64_t>(H + gx) * N + H + gy];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS * CW; e += blockDim.x) {
+        const int li = e / CW, b = e % CW;
+        const int i = x0 + li;
+        const int base = (i >> 1) - cx0, par = i & 1;
+        Acc al = 0, ah = 0;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int k = base - t, n = par + 2 * t;
+            al += hf[n] * static_cast<Acc>(sLL[k][b]) + gf[n] * static_cast<Acc>(sHL[k][b]);
+            ah += hf[n] * static_cast<Acc>(sLH[k][b]) + gf[n] * static_cast<Acc>(sHH[k][b]);
+        }
+        sAL[li][b] = static_cast<T>(al);
+        sAH[li][b] = static_cast<T>(ah);
+    }
+    __syncthreads();
+    T* dst;
+    int ld;
+    if (level > 1) {
+        dst = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[level - 1];
+        ld = M;
+    } else {
+        dst = vptr<T>(J, out_vec, it.frame) + Ly.coff;
+        ld = N;
+    }
+    for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+        const int li = e / TS, lj = e % TS;
+        const int i = x0 + li, j = y0 + lj;
+        if (i >= M || j >= M) continue;
+        const int base = (j >> 1) - cy0, par = j & 1;
+        Acc v = 0;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int k = base - t, n = par + 2 * t;
+            v += hf[n] * static_cast<Acc>(sAL[li][k]) + gf[n] * static_cast<Acc>(sAH[li][k]);
+        }
+        dst[static_cast<int64_t>(i) * ld + j] = static_cast<T>(v);
+    }
+}
+
+// --------------------------------------------------------- W (+ P^T, D) ----
+// One analysis level k <= k0 over a (TS/2)^2 tile of each band.  The input
+// window of (TS+4)^2 values is LL_{k-1} (scratch) or, at k = 1, the layer
+// pixels: read from memory (SRC_PIX) or gathered from the sensor node fields
+// through P^T (SRC_PT).  LL_k goes to scratch; the three detail bands go to
+// the output with, under EPI_APPLY, + alpha D_k p and a partial <p, out>.
+template <class T, int TS>
+__global__ void __launch_bounds__(256)
+k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int src, int in_vec,
+            int out_vec, int epi, int aux_vec) {
+    constexpr int HT = TS / 2, PW = TS + 4;
+    __shared__ T sA[PW][PW + 1];
+    __shared__ T sL[PW][HT + 1], sH[PW][HT + 1];
+    __shared__ double red[17];
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    const LayerInfo& Ly = P.layer[it.a];
+    const int N = Ly.N, M = N >> (level - 1), H = M >> 1;
+    const int ntx = (H + HT - 1) / HT;
+    const int cx0 = (it.b % ntx) * HT, cy0 = (it.b / ntx) * HT;
+    const int px0 = 2 * cx0, py0 = 2 * cy0;
+    Acc hf[6], gf[6];
+    load_filters(P, hf, gf);
+    const T* in = nullptr;
+    int ld = N;
+    if (level > 1) {
+        in = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[level - 1];
+        ld = M;
+    } else if (src == SRC_PIX) {
+        in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
+    } else {
+        in = vptr<T>(J, in_vec, it.frame);   // node fields of this frame
+    }
+    for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) {
+        const int a = e / PW, b = e % PW;
+        const int gx = (px0 + a) % M, gy = (py0 + b) % M;
+        if (level == 1 && src == SRC_PT)
+            sA[a][b] = static_cast<T>(pt_gather<T>(P, in, it.a, gx, gy));
+        else
+            sA[a][b] = in[static_cast<int64_t>(gx) * ld + gy];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < PW * HT; e += blockDim.x) {
+        const int a = e / HT, c = e % HT;
+        Acc lo = 0, hi = 0;
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            const Acc v = sA[a][2 * c + n];
+            lo += hf[n] * v;
+            hi += gf[n] * v;
+        }
+        sL[a][c] = static_cast<T>(lo);
+        sH[a][c] = static_cast<T>(hi);
+    }
+    __syncthreads();
+    T* out = vptr<T>(J, out_vec, it.frame) + Ly.coff;
+    const T* pv = (epi == EPI_APPLY) ? vptr<T>(J, aux_vec, it.frame) + Ly.coff : nullptr;
+    const Acc aD = P.alpha * Ly.D[level - 1];
+    T* llo = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[level];
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < HT * HT; e += blockDim.x) {
+        const int c1 = e / HT, c2 = e % HT;
+        const int X = cx0 + c1, Y = cy0 + c2;
+        Acc ll = 0, hl = 0, lh = 0, hh = 0;
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            const Acc l = sL[2 * c1 + n][c2], h = sH[2 * c1 + n][c2];
+            ll += hf[n] * l;
+            hl += gf[n] * l;
+            lh += hf[n] * h;
+            hh += gf[n] * h;
+        }
+        if (X < H && Y < H) {
+            llo[X * H + Y] = static_cast<T>(ll);
+            const int64_t iLH = static_cast<int64_t>(X) * N + H + Y;
+            const int64_t iHL = static_cast<int64_t>(H + X) * N + Y;
+            const int64_t iHH = static_cast<int64_t>(H + X) * N + H + Y;
+            if (epi == EPI_APPLY) {
+                const Acc p1 = pv[iLH], p2 = pv[iHL], p3 = pv[iHH];
+                const T o1 = static_cast<T>(lh + aD * p1);
+                const T o2 = static_cast<T>(hl + aD * p2);
+                const T o3 = static_cast<T>(hh + aD * p3);
+                acc += p1 * static_cast<Acc>(o1) + p2 * static_cast<Acc>(o2) +
+                       p3 * static_cast<Acc>(o3);
+                out[iLH] = o1;
+                out[iHL] = o2;
+                out[iHH] = o3;
+            } else {
+                out[iLH] = static_cast<T>(lh);
+                out[iHL] = static_cast<T>(hl);
+                out[iHH] = static_cast<T>(hh);
+            }
+        }
+    }
+    if (epi == EPI_APPLY) {
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) part_ptr(J, it.frame, PT_PQ)[it.slot] = s;
+    }
+}
+
+// Levels k0+1..J of the analysis with the M0 x M0 block in LDS, then the
+// epilogue over every coefficient of that block.  At k0 = 0 the block is the
+// whole layer, read (SRC_PIX) or gathered through P^T (SRC_PT).
+template <class T>
+__global__ void __launch_bounds__(1024)
+k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int in_vec,
+              int out_vec, int epi, int aux_vec) {
+    __shared__ double red[17];
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    const LayerInfo& Ly = P.layer[it.a];
+    const int N = Ly.N, k0 = Ly.k0, M0 = N >> k0;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* A = reinterpret_cast<T*>(smem_raw);
+    Acc hf[6], gf[6];
+    load_filters(P, hf, gf);
+    if (k0 > 0) {
+        const T* ll = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[k0];
+        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = ll[e];
+    } else if (src == SRC_PIX) {
+        const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
+        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = in[e];
+    } else {
+        const T* nodes = vptr<T>(J, in_vec, it.frame);
+        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x)
+            A[e] = static_cast<T>(pt_gather<T>(P, nodes, it.a, e / M0, e % M0));
+    }
+    __syncthreads();
+    for (int lev = k0 + 1; lev <= P.levels; ++lev) {
+        const int M = N >> (lev - 1);
+        ana_pass<T>(A, M0, M, 1, hf, gf);   // along y first
+        ana_pass<T>(A, M0, M, 0, hf, gf);   // then along x
+    }
+    T* out = vptr<T>(J, out_vec, it.frame) + Ly.coff;
+    const T* pv = (epi == EPI_APPLY) ? vptr<T>(J, aux_vec, it.frame) + Ly.coff : nullptr;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) {
+        const int x = e / M0, y = e % M0;
+        const int64_t gi = static_cast<int64_t>(x) * N + y;
+        T v = A[e];
+        if (epi == EPI_APPLY) {
+            const int k = level_of(x, y, N, P.levels);
+            const Acc p = pv[gi];
+            v = static_cast<T>(static_cast<Acc>(v) + P.alpha * Ly.D[k - 1] * p);
+            acc += p * static_cast<Acc>(v);
+        }
+        out[gi] = v;
+    }
+    if (epi == EPI_APPLY) {
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) part_ptr(J, it.frame, PT_PQ)[it.slot] = s;
+    }
+}
+
+// ----------------------------------------------------------- one sensor ----
+// SM_APPLY: layer pixels -> node field u (bilinear, summed over layers) ->
+//           Fried slopes (aggregated for a low-order sensor) -> C^-1 with
+//           (I - T) for tip/tilt-removed sensors -> Gamma^T -> node field v.
+// SM_RHS:   input slopes -> C^-1 (and (I - T)) -> Gamma^T -> v.
+// SM_FWD:   layer pixels -> raw slopes to the output.
+// One block of 1024 threads per (frame, sensor); the node field and the
+// weighted-slope grids live in LDS in FP64; QM elements per thread.
+template <class T, int QM>
+__global__ void __launch_bounds__(1024)
+k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_vec, int out_vec) {
+    __shared__ double red[17];
+    __shared__ double cellx[WM_MAXCELL], celly[WM_MAXCELL];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Acc* U = reinterpret_cast<Acc*>(smem_raw);
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    const int m = it.a;
+    const WfsInfo& w = P.wfs[m];
+    const int ns = w.n_sub, nn = w.nn, Sf = w.S_fine, S = w.S;
+    const int tid = threadIdx.x, bd = blockDim.x;
+    Acc sx[QM], sy[QM];
+#pragma unroll
+    for (int r = 0; r < QM; ++r) sx[r] = sy[r] = 0;
+
+    if (mode != SM_RHS) {
+        const T* phi = vptr<T>(J, in_vec, it.frame);
+        for (int e = tid; e < nn * nn; e += bd) {
+            const int i = e / nn, j = e % nn;
+            Acc acc = 0;
+            for (int l = 0; l < P.L; ++l) {
+                const int no = P.node_tab_off[m][l];
+                const int i0 = P.ix0[no + i], j0 = P.jy0[no + j];
+                const Acc t = P.tx[no + i], s = P.ty[no + j];
+                const int N = P.layer[l].N;
+                const T* f = phi + P.layer[l].coff + static_cast<int64_t>(i0) * N + j0;
+                acc += (1.0 - t) * ((1.0 - s) * static_cast<Acc>(f[0]) + s * static_cast<Acc>(f[1])) +
+                       t * ((1.0 - s) * static_cast<Acc>(f[N]) + s * static_cast<Acc>(f[N + 1]));
+            }
+            U[e] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < QM; ++r) {
+            const int q = tid + r * bd;
+            if (q < Sf) {
+                const int pk = w.act[q];
+                const int i = pk / ns, j = pk % ns;
+                const Acc u00 = U[i * nn + j], u10 = U[(i + 1) * nn + j];
+                const Acc u01 = U[i * nn + j + 1], u11 = U[(i + 1) * nn + j + 1];
+                sx[r] = 0.5 * ((u10 - u00) + (u11 - u01));
+                sy[r] = 0.5 * ((u01 - u00) + (u11 - u10));
+            }
+        }
+    }
+    const double* blk = w.blocks;
+
+    if (w.agg) {
+        if (mode != SM_RHS) {
+            for (int c = 0; c < S; ++c) {
+                Acc px = 0.0, py = 0.0;
+#pragma unroll
+                for (int r = 0; r < QM; ++r) {
+                    const int q = tid + r * bd;
+                    if (q < Sf && w.cell_of[q] == c) {
+                        px += sx[r];
+                        py += sy[r];
+                    }
+                }
+                px = block_sum(px, red);
+                py = block_sum(py, red);
+                if (tid == 0) {
+                    cellx[c] = px / w.cell_count[c];
+                    celly[c] = py / w.cell_count[c];
+                }
+            }
+        } else if (tid < S) {
+            const T* in = vptr<T>(J, in_vec, it.frame) + w.soff;
+            cellx[tid] = static_cast<Acc>(in[tid]);
+            celly[tid] = static_cast<Acc>(in[S + tid]);
+        }
+        __syncthreads();
+        if (mode == SM_FWD) {
+            if (tid < S) {
+                T* out = vptr<T>(J, out_vec, it.frame) + w.soff;
+                out[tid] = static_cast<T>(cellx[tid]);
+                out[S + tid] = static_cast<T>(celly[tid]);
+            }
+            return;
+        }
+        if (tid == 0) {
+            Acc mx = 0.0, my = 0.0;
+            if (w.remove_tt) {
+                for (int c = 0; c < S; ++c) { mx += cellx[c]; my += celly[c]; }
+                mx /= S;
+                my /= S;
+            }
+            Acc wxs[WM_MAXCELL], wys[WM_MAXCELL];
+            Acc nx = 0.0, ny = 0.0;
+            for (int c = 0; c < S; ++c) {
+                const Acc ax = cellx[c] - mx, ay = celly[c] - my;
+                wxs[c] = blk[3 * c] * ax + blk[3 * c + 1] * ay;
+                wys[c] = blk[3 * c + 1] * ax + blk[3 * c + 2] * ay;
+                nx += wxs[c];
+                ny += wys[c];
+            }
+            if (w.remove_tt) { nx /= S; ny /= S; } else { nx = ny = 0.0; }
+            for (int c = 0; c < S; ++c) {
+                cellx[c] = (wxs[c] - nx) / w.cell_count[c];
+                celly[c] = (wys[c] - ny) / w.cell_count[c];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < QM; ++r) {
+            const int q = tid + r * bd;
+            if (q < Sf) {
+                const int c = w.cell_of[q];
+                sx[r] = cellx[c];
+                sy[r] = celly[c];
+            }
+        }
+    } else {
+        if (mode == SM_RHS) {
+            const T* in = vptr<T>(J, in_vec, it.frame) + w.soff;
+#pragma unroll
+            for (int r = 0; r < QM; ++r) {
+                const int q = tid + r * bd;
+                if (q < Sf) { sx[r] = in[q]; sy[r] = in[Sf + q]; }
+            }
+        }
+        if (mode == SM_FWD) {
+            T* out = vptr<T>(J, out_vec, it.frame) + w.soff;
+#pragma unroll
+            for (int r = 0; r < QM; ++r) {
+                const int q = tid + r * bd;
+                if (q < Sf) { out[q] = static_cast<T>(sx[r]); out[Sf + q] = static_cast<T>(sy[r]); }
+            }
+            return;
+        }
+        if (w.remove_tt) {
+            Acc px = 0.0, py = 0.0;
+#pragma unroll
+            for (int r = 0; r < QM; ++r) { px += sx[r]; py += sy[r]; }
+            const Acc mx = block_sum(px, red) / Sf;
+            const Acc my = block_sum(py, red) / Sf;
+#pragma unroll
+            for (int r = 0; r < QM; ++r)
+                if (tid + r * bd < Sf) { sx[r] -= mx; sy[r] -= my; }
+        }
+#pragma unroll
+        for (int r = 0; r < QM; ++r) {
+            const int q = tid + r * bd;
+            if (q < Sf) {
+                const Acc a = blk[3 * q], b = blk[3 * q + 1], c = blk[3 * q + 2];
+                const Acc vx = a * sx[r] + b * sy[r];
+                const Acc vy = b * sx[r] + c * sy[r];
+                sx[r] = vx;
+                sy[r] = vy;
+            }
+        }
+        if (w.remove_tt) {
+            Acc px = 0.0, py = 0.0;
+#pragma unroll
+            for (int r = 0; r < QM; ++r) { px += sx[r]; py += sy[r]; }
+            const Acc mx = block_sum(px, red) / Sf;
+            const Acc my = block_sum(py, red) / Sf;
+#pragma unroll
+            for (int r = 0; r < QM; ++r)
+                if (tid + r * bd < Sf) { sx[r] -= mx; sy[r] -= my; }
+        }
+    }
+
+    // Gamma^T: weighted slopes -> node field, x part then y part through LDS.
+    Acc vacc[QM];
+    __syncthreads();
+    for (int e = tid; e < ns * ns; e += bd) U[e] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < QM; ++r) {
+        const int q = tid + r * bd;
+        if (q < Sf) U[w.act[q]] = sx[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < QM; ++r) {
+        const int e = tid + r * bd;
+        Acc v = 0;
+        if (e < nn * nn) {
+            const int a = e / nn, b = e % nn;
+            if (a >= 1 && b < ns) v += U[(a - 1) * ns + b];
+            if (a < ns && b < ns) v -= U[a * ns + b];
+            if (a >= 1 && b >= 1) v += U[(a - 1) * ns + b - 1];
+            if (a < ns && b >= 1) v -= U[a * ns + b - 1];
+        }
+        vacc[r] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < ns * ns; e += bd) U[e] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < QM; ++r) {
+        const int q = tid + r * bd;
+        if (q < Sf) U[w.act[q]] = sy[r];
+    }
+    __syncthreads();
+    T* vout = vptr<T>(J, out_vec, it.frame) + w.node_off;
+#pragma unroll
+    for (int r = 0; r < QM; ++r) {
+        const int e = tid + r * bd;
+        if (e < nn * nn) {
+            const int a = e / nn, b = e % nn;
+            Acc v = vacc[r];
+            if (a < ns && b >= 1) v += U[a * ns + b - 1];
+            if (a < ns && b < ns) v -= U[a * ns + b];
+            if (a >= 1 && b >= 1) v += U[(a - 1) * ns + b - 1];
+            if (a >= 1 && b < ns) v -= U[(a - 1) * ns + b];
+            vout[e] = static_cast<T>(0.5 * v);
+        }
+    }
+}
+
+// ------------------------------------------------------------- PCG steps ----
+// r0 = b (cold: x = 0) or b - A x0 (warm, A x0 in V_Q); p0 = z0 = J^-1 r0;
+// partials of <r0, z0> and <r0, r0> into the parity-0 segments.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
+    __shared__ double red[17];
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    T* x = vptr<T>(J, V_X, it.frame);
+    const T* b = vptr<T>(J, V_B, it.frame);
+    const T* q = vptr<T>(J, V_Q, it.frame);
+    T* r = vptr<T>(J, V_R, it.frame);
+    T* p = vptr<T>(J, V_P, it.frame);
+    const T* jac = reinterpret_cast<const T*>(P.jac);
+    Acc rz = 0.0, rr = 0.0;
+    const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
+    for (int k = threadIdx.x; k < VEC_CHUNK; k += blockDim.x) {
+        const int64_t i = i0 + k;
+        if (i < P.n) {
+            Acc rv;
+            if (warm) {
+                rv = static_cast<Acc>(b[i]) - static_cast<Acc>(q[i]);
+            } else {
+                rv = b[i];
+                x[i] = 0;
+            }
+            const T rs = static_cast<T>(rv);
+            const Acc z = P.precond ? static_cast<Acc>(rs) / static_cast<Acc>(jac[i]) : static_cast<Acc>(rs);
+            r[i] = rs;
+            p[i] = static_cast<T>(z);
+            rz += static_cast<Acc>(rs) * z;
+            rr += static_cast<Acc>(rs) * static_cast<Acc>(rs);
+        }
+    }
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        part_ptr(J, it.frame, PT_RZ0)[it.slot] = rz;
+        part_ptr(J, it.frame, PT_RR0)[it.slot] = rr;
+        if (it.b == 0) J.status[it.frame] = WMCAO_FRAME_OK;
+    }
+}
+
+// a = rho_i / <p, q>; r -= a q; partials of <r, J^-1 r>, <r, r> (next parity).
+template <class T>
+__global__ void __launch_bounds__(256)
+k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
+    __shared__ double red[17];
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    const double pq = sum_slots(part_ptr(J, it.frame, PT_PQ), P.n_fdwt_slots, red);
+    const double rho = sum_slots(part_ptr(J, it.frame, PT_RZ0 + (iter & 1)), P.n_vec_slots, red);
+    int st = J.status[it.frame];
+    double a = 0.0;
+    if (st == WMCAO_FRAME_OK) {
+        if (rho == 0.0)
+            st = WMCAO_FRAME_CONVERGED;
+        else if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho))
+            st = WMCAO_FRAME_BREAKDOWN;
+        else
+            a = rho / pq;
+    }
+    if (iter == 0) {
+        const double rr0 = sum_slots(part_ptr(J, it.frame, PT_RR0), P.n_vec_slots, red);
+        if (it.b == 0 && threadIdx.x == 0) {
+            J.alpha[2 * it.frame + 1] = sqrt(rr0);
+            if (J.resid) J.resid[static_cast<int64_t>(it.frame) * J.resid_ld] = sqrt(rr0);
+        }
+    }
+    if (it.b == 0 && threadIdx.x == 0) {
+        J.alpha[2 * it.frame] = a;
+        J.status[it.frame] = st;
+    }
+    if (st != WMCAO_FRAME_OK) return;
+    T* r = vptr<T>(J, V_R, it.frame);
+    const T* q = vptr<T>(J, V_Q, it.frame);
+    const T* jac = reinterpret_cast<const T*>(P.jac);
+    Acc rz = 0.0, rr = 0.0;
+    const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
+    for (int k = threadIdx.x; k < VEC_CHUNK; k += blockDim.x) {
+        const int64_t i = i0 + k;
+        if (i < P.n) {
+            const T rs = static_cast<T>(static_cast<Acc>(r[i]) - a * static_cast<Acc>(q[i]));
+            r[i] = rs;
+            const Acc rv = rs;
+            const Acc z = P.precond ? rv / static_cast<Acc>(jac[i]) : rv;
+            rz += rv * z;
+            rr += rv * rv;
+        }
+    }
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        part_ptr(J, it.frame, PT_RZ0 + ((iter + 1) & 1))[it.slot] = rz;
+        part_ptr(J, it.frame, PT_RR0 + ((iter + 1) & 1))[it.slot] = rr;
+    }
+}
+
+// beta = rho_{i+1} / rho_i; x += a p; p = J^-1 r + beta p.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
+    __shared__ double red[17];
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    const int st = J.status[it.frame];
+    if (st != WMCAO_FRAME_OK) {
+        if (it.b == 0 && threadIdx.x == 0 && J.resid)
+            J.resid[static_cast<int64_t>(it.frame) * J.resid_ld + iter + 1] = J.alpha[2 * it.frame + 1];
+        return;
+    }
+    const double a = J.alpha[2 * it.frame];
+    const double rho0 = sum_slots(part_ptr(J, it.frame, PT_RZ0 + (iter & 1)), P.n_vec_slots, red);
+    const double rho1 =
+        sum_slots(part_ptr(J, it.frame, PT_RZ0 + ((iter + 1) & 1)), P.n_vec_slots, red);
+    const double beta = rho1 / rho0;
+    if (it.b == 0) {
+        const double rr =
+            sum_slots(part_ptr(J, it.frame, PT_RR0 + ((iter + 1) & 1)), P.n_vec_slots, red);
+        if (threadIdx.x == 0) {
+            J.alpha[2 * it.frame + 1] = sqrt(rr);
+            if (J.resid) J.resid[static_cast<int64_t>(it.frame) * J.resid_ld + iter + 1] = sqrt(rr);
+        }
+    }
+    T* x = vptr<T>(J, V_X, it.frame);
+    T* p = vptr<T>(J, V_P, it.frame);
+    const T* r = vptr<T>(J, V_R, it.frame);
+    const T* jac = reinterpret_cast<const T*>(P.jac);
+    const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
+    for (int k = threadIdx.x; k < VEC_CHUNK; k += blockDim.x) {
+        const int64_t i = i0 + k;
+        if (i < P.n) {
+            const Acc pv = p[i];
+            x[i] = static_cast<T>(static_cast<Acc>(x[i]) + a * pv);
+            const Acc rv = r[i];
+            const Acc z = P.precond ? rv / static_cast<Acc>(jac[i]) : rv;
+            p[i] = static_cast<T>(z + beta * pv);
+        }
+    }
+}
+
+// Residual replacement: r = b - A x (A x in V_Q), fresh partials for rho_i.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_replace_r(const JobArgs args, const Item* __restrict__ items, int iter) {
+    __shared__ double red[17];
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    if (J.status[it.frame] != WMCAO_FRAME_OK) return;
+    const T* b = vptr<T>(J, V_B, it.frame);
+    const T* q = vptr<T>(J, V_Q, it.frame);
+    T* r = vptr<T>(J, V_R, it.frame);
+    const T* jac = reinterpret_cast<const T*>(P.jac);
+    Acc rz = 0.0, rr = 0.0;
+    const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
+    for (int k = threadIdx.x; k < VEC_CHUNK; k += blockDim.x) {
+        const int64_t i = i0 + k;
+        if (i < P.n) {
+            const T rs = static_cast<T>(static_cast<Acc>(b[i]) - static_cast<Acc>(q[i]));
+            r[i] = rs;
+            const Acc rv = rs;
+            const Acc z = P.precond ? rv / static_cast<Acc>(jac[i]) : rv;
+            rz += rv * z;
+            rr += rv * rv;
+        }
+    }
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        part_ptr(J, it.frame, PT_RZ0 + (iter & 1))[it.slot] = rz;
+        part_ptr(J, it.frame, PT_RR0 + (iter & 1))[it.slot] = rr;
+    }
+}
+
+// ------------------------------------------------------------ plan time ----
+struct JacArgs {
+    const double* protos;
+    const int* proto_off;     // [l][k-1][type]
+    const double* txd;
+    const double* tyd;
+    const double* blocksd;
+};
+
+// Jacobi diagonal in closed form, one thread per coefficient.  A level-k
+// coefficient (x, y) has the basis function f_x (outer) f_y, f = a shift by
+// 2^k * position of the level-k scaling or wavelet prototype; its slopes in
+// sensor m are s^x_ij = dF_i sG_j and s^y_ij = sF_i dG_j with F = B_x f_x.
+__global__ void __launch_bounds__(128)
+k_jacobi(const PlanDev* __restrict__ Pp, JacArgs ja, int64_t n, double* __restrict__ out) {
+    const int64_t lam = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (lam >= n) return;
+    const PlanDev& P = *Pp;
+    int l = 0;
+    while (l + 1 < P.L && lam >= P.layer[l + 1].coff) ++l;
+    const LayerInfo& Ly = P.layer[l];
+    const int N = Ly.N;
+    const int64_t loc = lam - Ly.coff;
+    const int x = static_cast<int>(loc / N), y = static_cast<int>(loc % N);
+    const int k = level_of(x, y, N, P.levels);
+    const int Hk = N >> k;
+    const int txy = x >= Hk, tyy = y >= Hk;
+    const int ax = txy ? x - Hk : x, ay = tyy ? y - Hk : y;
+    const double* fx = ja.protos + ja.proto_off[(l * WM_MAXLEV + (k - 1)) * 2 + txy];
+    const double* fy = ja.protos + ja.proto_off[(l * WM_MAXLEV + (k - 1)) * 2 + tyy];
+    const int shx = ax << k, shy = ay << k;
+    double acc = P.alpha * Ly.D[k - 1];
+    for (int m = 0; m < P.W; ++m) {
+        const WfsInfo& w = P.wfs[m];
+        if (!w.in_precond) continue;
+        const int ns = w.n_sub;
+        const int no = P.node_tab_off[m][l];
+        auto Fv = [&](int i) {
+            const int i0 = P.ix0[no + i];
+            const double t = ja.txd[no + i];
+            int p0 = (i0 - shx) % N;
+            if (p0 < 0) p0 += N;
+            int p1 = p0 + 1;
+            if (p1 == N) p1 = 0;
+            return (1.0 - t) * fx[p0] + t * fx[p1];
+        };
+        auto Gv = [&](int j) {
+            const int j0 = P.jy0[no + j];
+            const double t = ja.tyd[no + j];
+            int p0 = (j0 - shy) % N;
+            if (p0 < 0) p0 += N;
+            int p1 = p0 + 1;
+            if (p1 == N) p1 = 0;
+            return (1.0 - t) * fy[p0] + t * fy[p1];
+        };
+        int ilo = ns, ihi = -1, jlo = ns, jhi = -1;
+        double prev = Fv(0);
+        for (int i = 0; i < ns; ++i) {
+            const double nx = Fv(i + 1);
+            if (prev != 0.0 || nx != 0.0) { if (i < ilo) ilo = i; ihi = i; }
+            prev = nx;
+        }
+        if (ihi < 0) continue;
+        prev = Gv(0);
+        for (int j = 0; j < ns; ++j) {
+            const double nx = Gv(j + 1);
+            if (prev != 0.0 || nx != 0.0) { if (j < jlo) jlo = j; jhi = j; }
+            prev = nx;
+        }
+        if (jhi < 0) continue;
+        // blocks are packed per sensor in slope order: 3 values per measurement
+        const double* B = ja.blocksd + (w.soff / 2) * 3;
+        if (!w.agg) {
+            for (int i = ilo; i <= ihi; ++i) {
+                const double F0 = Fv(i), F1 = Fv(i + 1);
+                const double dF = F1 - F0, sF = 0.5 * (F0 + F1);
+                for (int j = jlo; j <= jhi; ++j) {
+                    const int q = w.maskmap[i * ns + j];
+                    if (q < 0) continue;
+                    const double G0 = Gv(j), G1 = Gv(j + 1);
+                    const double dG = G1 - G0, sG = 0.5 * (G0 + G1);
+                    const double sxv = dF * sG, syv = sF * dG;
+                    acc += B[3 * q] * sxv * sxv + 2.0 * B[3 * q + 1] * sxv * syv +
+                           B[3 * q + 2] * syv * syv;
+                }
+            }
+        } else {
+            double cx[WM_MAXCELL], cy[WM_MAXCELL];
+            for (int c = 0; c < WM_MAXCELL; ++c) cx[c] = cy[c] = 0.0;
+            for (int i = ilo; i <= ihi; ++i) {
+                const double F0 = Fv(i), F1 = Fv(i + 1);
+                const double dF = F1 - F0, sF = 0.5 * (F0 + F1);
+                for (int j = jlo; j <= jhi; ++j) {
+                    const int c = w.maskmap[i * ns + j];
+                    if (c < 0) continue;
+                    const double G0 = Gv(j), G1 = Gv(j + 1);
+                    const double dG = G1 - G0, sG = 0.5 * (G0 + G1);
+                    cx[c] += dF * sG;
+                    cy[c] += sF * dG;
+                }
+            }
+            for (int c = 0; c < w.S; ++c) {
+                const double vx = cx[c] / w.cell_count[c], vy = cy[c] / w.cell_count[c];
+                acc += B[3 * c] * vx * vx + 2.0 * B[3 * c + 1] * vx * vy + B[3 * c + 2] * vy * vy;
+            }
+        }
+    }
+    out[lam] = acc;
+}
+
+template <class T>
+__global__ void k_cast_from_double(const double* in, T* out, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = static_cast<T>(in[i]);
+}
+
+// -------------------------------------------------------------- launchers ----
+template <class T>
+void launch_idwt_coarse(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
+                        int lds_bytes, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_idwt_coarse<T>, dim3(n), dim3(1024), lds_bytes, s, a, items, in_vec,
+                       out_vec);
+}
+
+template <class T>
+void launch_idwt_tile(const JobArgs& a, const Item* items, int n, int level, int in_vec,
+                      int out_vec, int tile, hipStream_t s) {
+    if (n <= 0) return;
+    if (tile == 16)
+        hipLaunchKernelGGL((k_idwt_tile<T, 16>), dim3(n), dim3(256), 0, s, a, items, level, in_vec, out_vec);
+    else if (tile == 64)
+        hipLaunchKernelGGL((k_idwt_tile<T, 64>), dim3(n), dim3(256), 0, s, a, items, level, in_vec, out_vec);
+    else
+        hipLaunchKernelGGL((k_idwt_tile<T, 32>), dim3(n), dim3(256), 0, s, a, items, level, in_vec, out_vec);
+}
+
+template <class T>
+void launch_fdwt_tile(const JobArgs& a, const Item* items, int n, int level, int src, int in_vec,
+                      int out_vec, int epi, int aux_vec, int tile, hipStream_t s) {
+    if (n <= 0) return;
+    if (tile == 16)
+        hipLaunchKernelGGL((k_fdwt_tile<T, 16>), dim3(n), dim3(256), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
+    else if (tile == 64)
+        hipLaunchKernelGGL((k_fdwt_tile<T, 64>), dim3(n), dim3(256), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
+    else
+        hipLaunchKernelGGL((k_fdwt_tile<T, 32>), dim3(n), dim3(256), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
+}
+
+template <class T>
+void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int in_vec,
+                        int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fdwt_coarse<T>, dim3(n), dim3(1024), lds_bytes, s, a, items, src, in_vec,
+                       out_vec, epi, aux_vec);
+}
+
+template <class T>
+void launch_sensor(const JobArgs& a, const Item* items, int n, int mode, int in_vec, int out_vec,
+                   int lds_bytes, hipStream_t s) {
+    if (n <= 0) return;
+    // lds_bytes carries the node-field size; elements per thread follow from it
+    const int elems = lds_bytes / static_cast<int>(sizeof(Acc));
+    if (elems <= 8 * 1024)
+        hipLaunchKernelGGL((k_sensor<T, 8>), dim3(n), dim3(1024), lds_bytes, s, a, items, mode, in_vec, out_vec);
+    else
+        hipLaunchKernelGGL((k_sensor<T, 16>), dim3(n), dim3(1024), lds_bytes, s, a, items, mode, in_vec, out_vec);
+}
+
+template <class T>
+void launch_init(const JobArgs& a, const Item* items, int n, int warm, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_init<T>, dim3(n), dim3(256), 0, s, a, items, warm);
+}
+
+template <class T>
+void launch_update_r(const JobArgs& a, const Item* items, int n, int iter, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_update_r<T>, dim3(n), dim3(256), 0, s, a, items, iter);
+}
+
+template <class T>
+void launch_update_p(const JobArgs& a, const Item* items, int n, int iter, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_update_p<T>, dim3(n), dim3(256), 0, s, a, items, iter);
+}
+
+template <class T>
+void launch_replace_r(const JobArgs& a, const Item* items, int n, int iter, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_replace_r<T>, dim3(n), dim3(256), 0, s, a, items, iter);
+}
+
+void launch_jacobi(const PlanDev* P, const double* protos, const int* proto_off,
+                   const double* txd, const double* tyd, const double* blocksd, int64_t n,
+                   double* out, hipStream_t s) {
+    JacArgs ja{protos, proto_off, txd, tyd, blocksd};
+    const int nb = static_cast<int>((n + 127) / 128);
+    hipLaunchKernelGGL(k_jacobi, dim3(nb), dim3(128), 0, s, P, ja, n, out);
+}
+
+template <class T>
+void launch_cast_from_double(const double* in, T* out, int64_t n, hipStream_t s) {
+    const int nb = static_cast<int>((n + 255) / 256);
+    hipLaunchKernelGGL(k_cast_from_double<T>, dim3(nb), dim3(256), 0, s, in, out, n);
+}
+
+// Let the whole-band kernels use up to the 160 KB of LDS of a CDNA4 compute
+// unit (static shared memory included); clear any error this leaves behind.
+template <class K>
+static void allow_full_lds(K* k) {
+    hipFuncAttributes at{};
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(k)) == hipSuccess) {
+        const int dyn = 160 * 1024 - static_cast<int>(at.sharedSizeBytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    }
+    (void)hipGetLastError();
+}
+
+void configure_kernels() {
+    allow_full_lds(&k_idwt_coarse<float>);
+    allow_full_lds(&k_idwt_coarse<double>);
+    allow_full_lds(&k_fdwt_coarse<float>);
+    allow_full_lds(&k_fdwt_coarse<double>);
+    allow_full_lds(&k_sensor<float, 8>);
+    allow_full_lds(&k_sensor<float, 16>);
+    allow_full_lds(&k_sensor<double, 8>);
+    allow_full_lds(&k_sensor<double, 16>);
+}
+
+#define WM_INSTANTIATE(T)                                                                       \
+    template void launch_idwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, hipStream_t); \
+    template void launch_idwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
+    template void launch_fdwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, int, hipStream_t); \
+    template void launch_fdwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, hipStream_t); \
+    template void launch_sensor<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
+    template void launch_init<T>(const JobArgs&, const Item*, int, int, hipStream_t);          \
+    template void launch_update_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \
+    template void launch_update_p<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \
+    template void launch_replace_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);     \
+    template void launch_cast_from_double<T>(const double*, T*, int64_t, hipStream_t);
+
+WM_INSTANTIATE(float)
+WM_INSTANTIATE(double)
+
+}  // namespace wm

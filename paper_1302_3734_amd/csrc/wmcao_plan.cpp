@@ -1,0 +1,1051 @@
+// Host side of the C ABI: plan construction (geometry, tables, prior, Jacobi
+// diagonal, scratch), per-batch work schedules, and the PCG driver that
+// enqueues the HIP kernels.  No arithmetic of the solve runs here: every step
+// of an apply or a solve is a kernel launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "wmcao.h"
+#include "wmcao_internal.hpp"
+
+using namespace wm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define WM_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(WMCAO_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device allocation owned by a plan or a schedule.
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+struct Sched {
+    // Item lists per stage, on the device.
+    std::unique_ptr<DevBuf> buf;
+    const Item* coarse = nullptr;
+    int n_coarse = 0;
+    const Item* tiled[WM_MAXLEV + 1] = {};
+    int n_tiled[WM_MAXLEV + 1] = {};
+    const Item* sensor = nullptr;
+    int n_sensor = 0;
+    const Item* vec = nullptr;
+    int n_vec = 0;
+    int maxk0 = 0;
+    int lds_coarse = 0;
+    int lds_sensor = 0;
+    int tile = 32;
+};
+
+// Per-plan kernel timing with HIP events on the launch stream.
+struct Profiler {
+    bool on = false;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> rec;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    void clear() {
+        for (auto& r : rec) {
+            pool.push_back(std::get<1>(r));
+            pool.push_back(std::get<2>(r));
+        }
+        rec.clear();
+    }
+    ~Profiler() {
+        clear();
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+thread_local Profiler* g_prof = nullptr;
+
+// Launch through f, bracketed by events when a profiler is active.
+template <class F>
+void timed(int kind, hipStream_t s, F&& f) {
+    if (!g_prof || !g_prof->on) {
+        f();
+        return;
+    }
+    hipEvent_t a = g_prof->get(), b = g_prof->get();
+    (void)hipEventRecord(a, s);
+    f();
+    (void)hipEventRecord(b, s);
+    g_prof->rec.emplace_back(kind, a, b);
+}
+
+struct ProfScope {
+    Profiler* prev;
+    explicit ProfScope(Profiler* p) : prev(g_prof) { g_prof = p; }
+    ~ProfScope() { g_prof = prev; }
+};
+
+}  // namespace
+
+struct wmcao_plan_s {
+    int device = 0;
+    wmcao_dtype dtype = WMCAO_F64;
+    size_t esz = 8;
+    int L = 0, W = 0, levels = 0;
+    int max_batch = 1;
+    int tile = 32;
+    int lds_budget = 64 * 1024;
+    int resid_replace = 0;
+    PlanDev host{};
+    PlanDev* dev = nullptr;
+    std::vector<std::unique_ptr<DevBuf>> allocs;
+    void* vb = nullptr;
+    void* vr = nullptr;
+    void* vp = nullptr;
+    void* vq = nullptr;
+    void* vphi = nullptr;
+    void* vll = nullptr;
+    void* vnode = nullptr;
+    double* part = nullptr;
+    double* scal = nullptr;
+    int* status = nullptr;
+    double* jac_d = nullptr;
+    int64_t n = 0, n_slopes = 0, n_nodes = 0, ll_size = 0;
+    std::vector<int64_t> layer_off, slope_off;
+    std::map<int, std::unique_ptr<Sched>> sched;
+    // captured graph of one wmcao_solve_graph argument set
+    hipGraphExec_t gexec = nullptr;
+    std::tuple<const void*, void*, int, int, int, double*, int*, void*> gkey{};
+    std::mutex mu;
+    Profiler prof;
+
+    void* alloc(size_t bytes, int* rc) {
+        auto b = std::make_unique<DevBuf>();
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(&b->p, bytes);
+        if (e != hipSuccess) {
+            *rc = fail(WMCAO_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        void* p = b->p;
+        allocs.push_back(std::move(b));
+        return p;
+    }
+};
+
+namespace {
+
+// ------------------------------------------------------------ db3 filter ----
+// Daubechies' 6-tap orthonormal scaling filter (closed form of Daubechies
+// 1988 for three vanishing moments) and its quadrature mirror.
+void db3_filters(double* h, double* g) {
+    const double s10 = std::sqrt(10.0);
+    const double q = std::sqrt(5.0 + 2.0 * s10);
+    const double c = 1.0 / (16.0 * std::sqrt(2.0));
+    h[0] = (1.0 + s10 + q) * c;
+    h[1] = (5.0 + s10 + 3.0 * q) * c;
+    h[2] = (10.0 - 2.0 * s10 + 2.0 * q) * c;
+    h[3] = (10.0 - 2.0 * s10 - 2.0 * q) * c;
+    h[4] = (5.0 + s10 - 3.0 * q) * c;
+    h[5] = (1.0 + s10 - q) * c;
+    for (int n = 0; n < 6; ++n) g[n] = ((n & 1) ? -1.0 : 1.0) * h[5 - n];
+}
+
+// 1-D periodic synthesis of a length-M vector from its low half a and high
+// half d: x[(2k+n) mod M] += h_n a_k + g_n d_k.
+void synth1(const double* h, const double* g, const std::vector<double>& in, int M,
+            std::vector<double>& out) {
+    std::fill(out.begin(), out.begin() + M, 0.0);
+    const int H = M / 2;
+    for (int k = 0; k < H; ++k)
+        for (int n = 0; n < 6; ++n) out[(2 * k + n) % M] += h[n] * in[k] + g[n] * in[H + k];
+}
+
+// Prototype basis vector of an N-periodic k-level 1-D transform: the
+// synthesis of a unit coefficient at position 0 of the level-k low band
+// (type 0) or detail band (type 1).
+std::vector<double> prototype(const double* h, const double* g, int N, int k, int type) {
+    std::vector<double> x(N, 0.0), tmp(N, 0.0);
+    x[type ? (N >> k) : 0] = 1.0;
+    for (int lev = k; lev >= 1; --lev) {
+        const int M = N >> (lev - 1);
+        synth1(h, g, x, M, tmp);
+        std::copy(tmp.begin(), tmp.begin() + M, x.begin());
+    }
+    return x;
+}
+
+int upload(wmcao_plan_s* p, const void* host, size_t bytes, void** out) {
+    int rc = WMCAO_OK;
+    void* d = p->alloc(bytes, &rc);
+    if (!d) return rc;
+    if (bytes) WM_HIP(hipMemcpy(d, host, bytes, hipMemcpyHostToDevice));
+    *out = d;
+    return WMCAO_OK;
+}
+
+template <class V>
+int upload_vec(wmcao_plan_s* p, const std::vector<V>& v, const V** out) {
+    void* d = nullptr;
+    int rc = upload(p, v.data(), v.size() * sizeof(V), &d);
+    *out = static_cast<const V*>(d);
+    return rc;
+}
+
+// ------------------------------------------------------------- schedules ----
+struct JobSpec {
+    wmcao_plan_s* plan;
+    int count;
+};
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Items for every stage of a job of several plans: frame-major order inside
+// each plan, plans in order.  The FDWT pass of one frame writes its <p, Ap>
+// partials into slots 0.. in the order level-1 tiles, level-2 tiles, ...,
+// coarse blocks; the vector passes use one slot per chunk.
+int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
+    std::vector<Item> coarse, sensor, vec;
+    std::vector<Item> tiled[WM_MAXLEV + 1];
+    int maxk0 = 0, lds_c = 0, lds_s = 0;
+    for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
+        const wmcao_plan_s* P = jobs[jp].plan;
+        for (int f = 0; f < jobs[jp].count; ++f) {
+            int slot = 0;
+            for (int k = 1; k <= WM_MAXLEV; ++k) {
+                for (int l = 0; l < P->L; ++l) {
+                    const LayerInfo& Ly = P->host.layer[l];
+                    if (Ly.k0 < k) continue;
+                    const int M = Ly.N >> (k - 1);
+                    const int nt = ceil_div(M, tile);
+                    for (int t = 0; t < nt * nt; ++t) tiled[k].push_back(Item{jp, f, l, t, slot++, 0, 0, 0});
+                    maxk0 = std::max(maxk0, k);
+                }
+            }
+            for (int l = 0; l < P->L; ++l) {
+                coarse.push_back(Item{jp, f, l, 0, slot++, 0, 0, 0});
+                const int M0 = P->host.layer[l].N >> P->host.layer[l].k0;
+                lds_c = std::max(lds_c, static_cast<int>(M0 * M0 * P->esz));
+            }
+            for (int m = 0; m < P->W; ++m) {
+                sensor.push_back(Item{jp, f, m, 0, 0, 0, 0, 0});
+                const int nn = P->host.wfs[m].nn;
+                lds_s = std::max(lds_s, static_cast<int>(nn * nn * sizeof(double)));
+            }
+            const int nch = static_cast<int>((P->n + VEC_CHUNK - 1) / VEC_CHUNK);
+            for (int c = 0; c < nch; ++c) vec.push_back(Item{jp, f, 0, c, c, 0, 0, 0});
+        }
+    }
+    std::vector<Item> all;
+    std::vector<size_t> offs;
+    auto add = [&](const std::vector<Item>& v) {
+        offs.push_back(all.size());
+        all.insert(all.end(), v.begin(), v.end());
+    };
+    add(coarse);
+    add(sensor);
+    add(vec);
+    for (int k = 1; k <= WM_MAXLEV; ++k) add(tiled[k]);
+    S->buf = std::make_unique<DevBuf>();
+    const size_t bytes = std::max<size_t>(all.size(), 1) * sizeof(Item);
+    hipError_t e = hipMalloc(&S->buf->p, bytes);
+    if (e != hipSuccess) return fail(WMCAO_ERR_OOM, "schedule allocation failed");
+    WM_HIP(hipMemcpy(S->buf->p, all.data(), all.size() * sizeof(Item), hipMemcpyHostToDevice));
+    const Item* base = static_cast<const Item*>(S->buf->p);
+    S->coarse = base + offs[0];
+    S->n_coarse = static_cast<int>(coarse.size());
+    S->sensor = base + offs[1];
+    S->n_sensor = static_cast<int>(sensor.size());
+    S->vec = base + offs[2];
+    S->n_vec = static_cast<int>(vec.size());
+    for (int k = 1; k <= WM_MAXLEV; ++k) {
+        S->tiled[k] = base + offs[2 + k];
+        S->n_tiled[k] = static_cast<int>(tiled[k].size());
+    }
+    S->maxk0 = maxk0;
+    S->lds_coarse = lds_c;
+    S->lds_sensor = lds_s;
+    S->tile = tile;
+    return WMCAO_OK;
+}
+
+std::mutex g_multi_mu;
+std::map<std::vector<std::pair<const void*, int>>, std::unique_ptr<Sched>> g_multi_cache;
+
+int get_sched(wmcao_plan_s* p, int batch, Sched** out) {
+    auto it = p->sched.find(batch);
+    if (it != p->sched.end()) {
+        *out = it->second.get();
+        return WMCAO_OK;
+    }
+    auto S = std::make_unique<Sched>();
+    int rc = build_sched({JobSpec{p, batch}}, p->tile, S.get());
+    if (rc) return rc;
+    *out = S.get();
+    p->sched[batch] = std::move(S);
+    return WMCAO_OK;
+}
+
+JobPlan make_jobplan(wmcao_plan_s* p, int nframes) {
+    JobPlan J{};
+    J.P = p->dev;
+    J.vec[V_B] = p->vb;
+    J.vec[V_R] = p->vr;
+    J.vec[V_P] = p->vp;
+    J.vec[V_Q] = p->vq;
+    J.vec[V_PHI] = p->vphi;
+    J.vec[V_LL] = p->vll;
+    J.vec[V_NODE] = p->vnode;
+    for (int v : {V_X, V_B, V_R, V_P, V_Q, V_PHI}) J.stride[v] = p->n;
+    J.stride[V_LL] = p->ll_size;
+    J.stride[V_NODE] = p->n_nodes;
+    J.stride[V_SLOPES] = p->n_slopes;
+    J.part = p->part;
+    J.alpha = p->scal;
+    J.status = p->status;
+    J.resid = nullptr;
+    J.resid_ld = 0;
+    J.nframes = nframes;
+    return J;
+}
+
+// ------------------------------------------------------- stage drivers ----
+template <class T>
+void run_idwt(const JobArgs& a, const Sched& S, int in_vec, int out_vec, hipStream_t s) {
+    timed(WMCAO_K_IDWT_COARSE, s, [&] {
+        launch_idwt_coarse<T>(a, S.coarse, S.n_coarse, in_vec, out_vec, S.lds_coarse, s);
+    });
+    for (int k = S.maxk0; k >= 1; --k)
+        timed(WMCAO_K_IDWT_TILE, s, [&] {
+            launch_idwt_tile<T>(a, S.tiled[k], S.n_tiled[k], k, in_vec, out_vec, S.tile, s);
+        });
+}
+
+template <class T>
+void run_fdwt(const JobArgs& a, const Sched& S, int src, int in_vec, int out_vec, int epi,
+              int aux_vec, hipStream_t s) {
+    for (int k = 1; k <= S.maxk0; ++k)
+        timed(WMCAO_K_FDWT_TILE, s, [&] {
+            launch_fdwt_tile<T>(a, S.tiled[k], S.n_tiled[k], k, src, in_vec, out_vec, epi,
+                                aux_vec, S.tile, s);
+        });
+    timed(WMCAO_K_FDWT_COARSE, s, [&] {
+        launch_fdwt_coarse<T>(a, S.coarse, S.n_coarse, src, in_vec, out_vec, epi, aux_vec,
+                              S.lds_coarse, s);
+    });
+}
+
+// y = A x for every frame of the job (x_vec, y_vec are vector kinds).
+template <class T>
+void run_apply(const JobArgs& a, const Sched& S, int x_vec, int y_vec, hipStream_t s) {
+    run_idwt<T>(a, S, x_vec, V_PHI, s);
+    timed(WMCAO_K_SENSOR, s, [&] {
+        launch_sensor<T>(a, S.sensor, S.n_sensor, SM_APPLY, V_PHI, V_NODE, S.lds_sensor, s);
+    });
+    run_fdwt<T>(a, S, SRC_PT, V_NODE, y_vec, EPI_APPLY, x_vec, s);
+}
+
+template <class T>
+void run_rhs(const JobArgs& a, const Sched& S, int slopes_vec, int b_vec, hipStream_t s) {
+    timed(WMCAO_K_SENSOR, s, [&] {
+        launch_sensor<T>(a, S.sensor, S.n_sensor, SM_RHS, slopes_vec, V_NODE, S.lds_sensor, s);
+    });
+    run_fdwt<T>(a, S, SRC_PT, V_NODE, b_vec, EPI_NONE, b_vec, s);
+}
+
+template <class T>
+void run_solve(const JobArgs& a, const Sched& S, int n_iter, int warm, int resid_replace,
+               hipStream_t s) {
+    run_rhs<T>(a, S, V_SLOPES, V_B, s);
+    if (warm) run_apply<T>(a, S, V_X, V_Q, s);
+    timed(WMCAO_K_INIT, s, [&] { launch_init<T>(a, S.vec, S.n_vec, warm, s); });
+    for (int it = 0; it < n_iter; ++it) {
+        if (resid_replace > 0 && it > 0 && it % resid_replace == 0) {
+            run_apply<T>(a, S, V_X, V_Q, s);
+            timed(WMCAO_K_REPLACE_R, s, [&] { launch_replace_r<T>(a, S.vec, S.n_vec, it, s); });
+        }
+        run_apply<T>(a, S, V_P, V_Q, s);
+        timed(WMCAO_K_UPDATE_R, s, [&] { launch_update_r<T>(a, S.vec, S.n_vec, it, s); });
+        timed(WMCAO_K_UPDATE_P, s, [&] { launch_update_p<T>(a, S.vec, S.n_vec, it, s); });
+    }
+}
+
+int check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(WMCAO_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return WMCAO_OK;
+}
+
+int check_batch(wmcao_plan_s* p, int batch) {
+    if (!p) return fail(WMCAO_ERR_INVALID_ARG, "plan is NULL");
+    if (batch < 1 || batch > p->max_batch)
+        return fail(WMCAO_ERR_INVALID_ARG, "batch must be in 1..max_batch");
+    return WMCAO_OK;
+}
+
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DevGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int enqueue_solve(wmcao_plan_s* p, const void* slopes, void* coeffs, int batch, int n_iter,
+                  int warm, double* resid, int* status, hipStream_t s) {
+    Sched* S = nullptr;
+    int rc = get_sched(p, batch, &S);
+    if (rc) return rc;
+    JobArgs a{};
+    a.njp = 1;
+    a.jp[0] = make_jobplan(p, batch);
+    a.jp[0].vec[V_X] = coeffs;
+    a.jp[0].vec[V_SLOPES] = const_cast<void*>(slopes);
+    if (status) a.jp[0].status = status;
+    a.jp[0].resid = resid;
+    a.jp[0].resid_ld = n_iter + 1;
+    if (p->dtype == WMCAO_F32)
+        run_solve<float>(a, *S, n_iter, warm, p->resid_replace, s);
+    else
+        run_solve<double>(a, *S, n_iter, warm, p->resid_replace, s);
+    return check_launch();
+}
+
+}  // namespace
+
+// =================================================================== ABI ====
+extern "C" {
+
+const char* wmcao_strerror(int code) {
+    switch (code) {
+        case WMCAO_OK: return "ok";
+        case WMCAO_ERR_INVALID_ARG: return "invalid argument";
+        case WMCAO_ERR_SIZE: return "unsupported size (layer grid must be divisible by 2^levels)";
+        case WMCAO_ERR_FOOTPRINT: return "a sensor node projects outside a layer grid";
+        case WMCAO_ERR_UNSUPPORTED: return "unsupported wavelet or sensor size";
+        case WMCAO_ERR_OOM: return "out of memory";
+        case WMCAO_ERR_HIP: return "HIP runtime error";
+        case WMCAO_ERR_BREAKDOWN: return "CG breakdown (p^T A p <= 0 or non-finite)";
+        default: return "unknown error";
+    }
+}
+
+const char* wmcao_last_error(void) { return g_last_error.c_str(); }
+
+int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers,
+               const wmcao_wfs* wfs, int n_wfs, wmcao_wavelet wavelet, int levels,
+               const wmcao_options* opts, wmcao_plan_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(WMCAO_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!pupil || !layers || !wfs || !opts) return fail(WMCAO_ERR_INVALID_ARG, "NULL argument");
+    if (n_layers < 1 || n_layers > WM_MAXL) return fail(WMCAO_ERR_INVALID_ARG, "n_layers out of range");
+    if (n_wfs < 1 || n_wfs > WM_MAXW) return fail(WMCAO_ERR_INVALID_ARG, "n_wfs out of range");
+    if (wavelet.family != 0 || wavelet.order != 3)
+        return fail(WMCAO_ERR_UNSUPPORTED, "only Daubechies order 3 is built");
+    if (levels < 1 || levels > WM_MAXLEV) return fail(WMCAO_ERR_SIZE, "levels out of range");
+    if (opts->dtype != WMCAO_F32 && opts->dtype != WMCAO_F64)
+        return fail(WMCAO_ERR_INVALID_ARG, "dtype");
+    if (opts->max_batch < 1) return fail(WMCAO_ERR_INVALID_ARG, "max_batch < 1");
+    if (!(opts->alpha > 0.0) || !(opts->r0_m > 0.0) || !(opts->L0_m > 0.0))
+        return fail(WMCAO_ERR_INVALID_ARG, "alpha, r0 and L0 must be positive");
+    if (opts->tile != 0 && opts->tile != 16 && opts->tile != 32 && opts->tile != 64)
+        return fail(WMCAO_ERR_INVALID_ARG, "tile must be 0, 16, 32 or 64");
+    if (opts->precond != 0 && opts->precond != 1) return fail(WMCAO_ERR_INVALID_ARG, "precond");
+    if (opts->resid_replace_every < 0) return fail(WMCAO_ERR_INVALID_ARG, "resid_replace_every < 0");
+    if (!(pupil->diameter_m > 0.0) || pupil->obstruction_ratio < 0.0 || pupil->obstruction_ratio >= 1.0)
+        return fail(WMCAO_ERR_INVALID_ARG, "pupil");
+    bool seen_ngs = false;
+    for (int m = 0; m < n_wfs; ++m) {
+        const wmcao_wfs& w = wfs[m];
+        if (w.n_sub < 1 || w.n_sub > WM_NSUB_MAX) return fail(WMCAO_ERR_UNSUPPORTED, "n_sub out of range");
+        if (w.tt_aggregate < 0 || w.tt_aggregate > 4 || (w.tt_aggregate && w.n_sub % w.tt_aggregate))
+            return fail(WMCAO_ERR_INVALID_ARG, "tt_aggregate must be 0..4 and divide n_sub");
+        if (!w.cinv_blocks && !(w.sigma > 0.0)) return fail(WMCAO_ERR_INVALID_ARG, "sigma must be > 0");
+        if (w.is_lgs) {
+            if (seen_ngs) return fail(WMCAO_ERR_INVALID_ARG, "laser guide stars must come first");
+            if (!(w.lgs_height_m > 0.0)) return fail(WMCAO_ERR_INVALID_ARG, "lgs_height_m");
+        } else {
+            seen_ngs = true;
+        }
+    }
+    for (int l = 0; l < n_layers; ++l) {
+        const int N = layers[l].n;
+        if (N < 6 || N % (1 << levels) != 0 || (N >> (levels - 1)) < 6)
+            return fail(WMCAO_ERR_SIZE, "layer size must be divisible by 2^levels and N/2^(levels-1) >= 6");
+        if (!(layers[l].spacing_m > 0.0) || !(layers[l].cn2_weight > 0.0))
+            return fail(WMCAO_ERR_INVALID_ARG, "layer spacing and weight must be positive");
+        for (int m = 0; m < n_wfs; ++m)
+            if (wfs[m].is_lgs && layers[l].altitude_m >= wfs[m].lgs_height_m)
+                return fail(WMCAO_ERR_INVALID_ARG, "layer above a laser guide star");
+    }
+
+    auto p = std::make_unique<wmcao_plan_s>();
+    int rc = WMCAO_OK;
+    if (hipGetDevice(&p->device) != hipSuccess) return fail(WMCAO_ERR_HIP, "no HIP device");
+    static std::once_flag once;
+    std::call_once(once, [] { configure_kernels(); });
+    p->dtype = opts->dtype;
+    p->esz = opts->dtype == WMCAO_F32 ? 4 : 8;
+    p->L = n_layers;
+    p->W = n_wfs;
+    p->levels = levels;
+    p->max_batch = opts->max_batch;
+    p->tile = opts->tile ? opts->tile : 32;
+    if (p->dtype == WMCAO_F64 && p->tile == 64) p->tile = 32;   // LDS of a 64-tile in FP64
+    p->lds_budget = opts->lds_budget > 0 ? opts->lds_budget : 64 * 1024;
+    p->lds_budget = std::min(p->lds_budget, 160 * 1024);
+    p->resid_replace = opts->resid_replace_every;
+    PlanDev& H = p->host;
+    H.L = n_layers;
+    H.W = n_wfs;
+    H.levels = levels;
+    H.dtype = opts->dtype;
+    H.precond = opts->precond;
+    H.alpha = opts->alpha;
+    db3_filters(H.h, H.g);
+
+    // ---- layers ---------------------------------------------------------
+    int64_t off = 0, lloff = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        LayerInfo& Ly = H.layer[l];
+        const int N = layers[l].n;
+        Ly.N = N;
+        Ly.coff = off;
+        off += static_cast<int64_t>(N) * N;
+        int k0 = 0;
+        while (k0 < levels - 1) {
+            const int64_t M0 = N >> k0;
+            if (M0 * M0 * static_cast<int64_t>(p->esz) <= p->lds_budget && M0 * M0 <= 1024 * WM_QMAX) break;
+            ++k0;
+        }
+        const int64_t M0 = N >> k0;
+        if (M0 * M0 * static_cast<int64_t>(p->esz) > 160 * 1024 || M0 * M0 > 1024 * WM_QMAX)
+            return fail(WMCAO_ERR_UNSUPPORTED, "layer too large for the wavelet kernels");
+        Ly.k0 = k0;
+        for (int k = 1; k <= k0; ++k) {
+            Ly.ll_off[k] = lloff;
+            lloff += static_cast<int64_t>(N >> k) * (N >> k);
+        }
+        // prior (eq. (13)): D = d^2 (L0^-11/3 + nu_k^11/3) / c_rho, nu_k = 2^-k / d
+        const double d = layers[l].spacing_m;
+        const double c_rho = 0.023 * layers[l].cn2_weight * std::pow(opts->r0_m, -5.0 / 3.0);
+        for (int k = 1; k <= levels; ++k) {
+            const double nu = std::ldexp(1.0, -k) / d;
+            Ly.D[k - 1] = d * d * (std::pow(opts->L0_m, -11.0 / 3.0) + std::pow(nu, 11.0 / 3.0)) / c_rho;
+        }
+    }
+    p->n = off;
+    p->ll_size = lloff;
+    H.n = off;
+    H.ll_size = lloff;
+    p->layer_off.resize(n_layers + 1);
+    for (int l = 0; l < n_layers; ++l) p->layer_off[l] = H.layer[l].coff;
+    p->layer_off[n_layers] = off;
+
+    // ---- sensors --------------------------------------------------------
+    std::vector<int> ix0, jy0, pfx, pcx, pfy, pcy;
+    std::vector<double> txd, tyd, blocksd;
+    int64_t soff = 0, noff = 0;
+    p->slope_off.assign(1, 0);
+    struct WfsHost { std::vector<int> act, cell_of, cell_count, maskmap; };
+    std::vector<WfsHost> wh(n_wfs);
+    const double Dp = pupil->diameter_m;
+    for (int m = 0; m < n_wfs; ++m) {
+        const wmcao_wfs& w = wfs[m];
+        WfsInfo& I = H.wfs[m];
+        const int ns = w.n_sub, nn = ns + 1;
+        const double dsub = Dp / ns;
+        I.n_sub = ns;
+        I.nn = nn;
+        I.agg = w.tt_aggregate;
+        I.remove_tt = w.remove_tt < 0 ? (w.is_lgs ? 1 : 0) : (w.remove_tt ? 1 : 0);
+        I.in_precond = w.in_precond < 0 ? ((ns > 2 && w.tt_aggregate == 0) ? 1 : 0) : (w.in_precond ? 1 : 0);
+        // pupil: centre of subaperture (i, j) in the closed annulus
+        const double ro2 = 0.25 * Dp * Dp, ri2 = 0.25 * Dp * Dp * pupil->obstruction_ratio * pupil->obstruction_ratio;
+        WfsHost& X = wh[m];
+        X.maskmap.assign(ns * ns, -1);
+        for (int i = 0; i < ns; ++i)
+            for (int j = 0; j < ns; ++j) {
+                const double cx = (i + 0.5 - ns / 2.0) * dsub, cy = (j + 0.5 - ns / 2.0) * dsub;
+                const double r2 = cx * cx + cy * cy;
+                if (r2 <= ro2 && r2 >= ri2) X.act.push_back(i * ns + j);
+            }
+        I.S_fine = static_cast<int>(X.act.size());
+        if (I.S_fine == 0) return fail(WMCAO_ERR_INVALID_ARG, "sensor without active subapertures");
+        if (I.S_fine > 1024 * WM_QMAX || nn * nn > 1024 * WM_QMAX)
+            return fail(WMCAO_ERR_UNSUPPORTED, "sensor too large");
+        if (static_cast<int64_t>(nn) * nn * 8 > 150 * 1024)
+            return fail(WMCAO_ERR_UNSUPPORTED, "sensor node field exceeds LDS");
+        if (I.agg) {
+            const int k = I.agg, b = ns / k;
+            std::vector<int> cell_id(k * k, -1);
+            for (int q = 0; q < I.S_fine; ++q) {
+                const int i = X.act[q] / ns, j = X.act[q] % ns;
+                const int c = (i / b) * k + (j / b);
+                cell_id[c] = 0;
+            }
+            int nc = 0;
+            for (int c = 0; c < k * k; ++c)
+                if (cell_id[c] == 0) cell_id[c] = nc++;
+            X.cell_count.assign(nc, 0);
+            X.cell_of.resize(I.S_fine);
+            for (int q = 0; q < I.S_fine; ++q) {
+                const int i = X.act[q] / ns, j = X.act[q] % ns;
+                const int c = cell_id[(i / b) * k + (j / b)];
+                X.cell_of[q] = c;
+                X.cell_count[c]++;
+                X.maskmap[X.act[q]] = c;
+            }
+            I.S = nc;
+        } else {
+            for (int q = 0; q < I.S_fine; ++q) X.maskmap[X.act[q]] = q;
+            X.cell_of.assign(1, 0);
+            X.cell_count.assign(1, 0);
+            I.S = I.S_fine;
+        }
+        for (int q = 0; q < I.S; ++q) {
+            if (w.cinv_blocks) {
+                blocksd.push_back(w.cinv_blocks[3 * q]);
+                blocksd.push_back(w.cinv_blocks[3 * q + 1]);
+                blocksd.push_back(w.cinv_blocks[3 * q + 2]);
+            } else {
+                const double iv = 1.0 / (w.sigma * w.sigma);
+                blocksd.push_back(iv);
+                blocksd.push_back(0.0);
+                blocksd.push_back(iv);
+            }
+        }
+        I.soff = soff;
+        soff += 2 * I.S;
+        p->slope_off.push_back(soff);
+        I.node_off = noff;
+        noff += static_cast<int64_t>(nn) * nn;
+        // projection tables per layer (Sec. 2.1): sample at s * r + theta * h
+        for (int l = 0; l < n_layers; ++l) {
+            const double hl = layers[l].altitude_m;
+            const double s = w.is_lgs ? 1.0 - hl / w.lgs_height_m : 1.0;
+            const int N = layers[l].n;
+            const double d = layers[l].spacing_m;
+            H.node_tab_off[m][l] = static_cast<int>(ix0.size());
+            H.pix_tab_off[m][l] = static_cast<int>(pfx.size());
+            for (int axis = 0; axis < 2; ++axis) {
+                const double theta = axis == 0 ? w.theta_x : w.theta_y;
+                std::vector<int>& i0v = axis == 0 ? ix0 : jy0;
+                std::vector<double>& tv = axis == 0 ? txd : tyd;
+                std::vector<int>& fv = axis == 0 ? pfx : pfy;
+                std::vector<int>& cv = axis == 0 ? pcx : pcy;
+                const size_t base = i0v.size();
+                for (int i = 0; i < nn; ++i) {
+                    const double xi = (i - ns / 2.0) * dsub;
+                    const double u = (s * xi + theta * hl) / d + N / 2.0;
+                    if (!(u >= 0.0 && u <= N - 1.0))
+                        return fail(WMCAO_ERR_FOOTPRINT, "sensor " + std::to_string(m) +
+                                    " leaves layer " + std::to_string(l));
+                    int i0 = static_cast<int>(std::floor(u));
+                    i0 = std::min(std::max(i0, 0), N - 2);
+                    i0v.push_back(i0);
+                    tv.push_back(u - i0);
+                }
+                std::vector<int> first(N, -1), last(N, -2);
+                for (int i = 0; i < nn; ++i) {
+                    const int i0 = i0v[base + i];
+                    for (int px : {i0, i0 + 1}) {
+                        if (first[px] < 0) first[px] = i;
+                        last[px] = i;
+                    }
+                }
+                for (int px = 0; px < N; ++px) {
+                    fv.push_back(first[px] < 0 ? 0 : first[px]);
+                    cv.push_back(first[px] < 0 ? 0 : last[px] - first[px] + 1);
+                }
+            }
+        }
+    }
+    p->n_slopes = soff;
+    p->n_nodes = noff;
+    H.n_slopes = soff;
+    H.n_nodes = noff;
+
+    // ---- upload tables --------------------------------------------------
+#define UP(vec, dst)                                          \
+    do {                                                      \
+        rc = upload_vec(p.get(), vec, &dst);                  \
+        if (rc) return rc;                                    \
+    } while (0)
+    for (int m = 0; m < n_wfs; ++m) {
+        UP(wh[m].act, H.wfs[m].act);
+        UP(wh[m].cell_of, H.wfs[m].cell_of);
+        UP(wh[m].cell_count, H.wfs[m].cell_count);
+        UP(wh[m].maskmap, H.wfs[m].maskmap);
+    }
+    UP(ix0, H.ix0);
+    UP(jy0, H.jy0);
+    UP(pfx, H.pfx);
+    UP(pcx, H.pcx);
+    UP(pfy, H.pfy);
+    UP(pcy, H.pcy);
+    const double* txd_dev = nullptr;
+    const double* tyd_dev = nullptr;
+    const double* blk_dev_d = nullptr;
+    UP(txd, txd_dev);
+    UP(tyd, tyd_dev);
+    UP(blocksd, blk_dev_d);
+    // geometry weights and noise blocks stay FP64 for both dtypes (small tables)
+    H.tx = txd_dev;
+    H.ty = tyd_dev;
+    for (int m = 0; m < n_wfs; ++m) H.wfs[m].blocks = blk_dev_d + (H.wfs[m].soff / 2) * 3;
+
+    // ---- slots and scratch ------------------------------------------------
+    {
+        int nf = 0;
+        for (int l = 0; l < n_layers; ++l) {
+            for (int k = 1; k <= H.layer[l].k0; ++k) {
+                const int M = H.layer[l].N >> (k - 1);
+                const int nt = ceil_div(M, p->tile);
+                nf += nt * nt;
+            }
+            nf += 1;
+        }
+        H.n_fdwt_slots = nf;
+        H.n_vec_slots = static_cast<int>((p->n + VEC_CHUNK - 1) / VEC_CHUNK);
+        H.slots = std::max(H.n_fdwt_slots, H.n_vec_slots);
+    }
+    const int B = p->max_batch;
+    const size_t ve = static_cast<size_t>(p->n) * B * p->esz;
+    if (!(p->vb = p->alloc(ve, &rc))) return rc;
+    if (!(p->vr = p->alloc(ve, &rc))) return rc;
+    if (!(p->vp = p->alloc(ve, &rc))) return rc;
+    if (!(p->vq = p->alloc(ve, &rc))) return rc;
+    if (!(p->vphi = p->alloc(ve, &rc))) return rc;
+    if (!(p->vll = p->alloc(static_cast<size_t>(p->ll_size) * B * p->esz, &rc))) return rc;
+    if (!(p->vnode = p->alloc(static_cast<size_t>(p->n_nodes) * B * p->esz, &rc))) return rc;
+    if (!(p->part = static_cast<double*>(p->alloc(sizeof(double) * NPT * H.slots * B, &rc)))) return rc;
+    if (!(p->scal = static_cast<double*>(p->alloc(sizeof(double) * 2 * B, &rc)))) return rc;
+    if (!(p->status = static_cast<int*>(p->alloc(sizeof(int) * B, &rc)))) return rc;
+    WM_HIP(hipMemset(p->part, 0, sizeof(double) * NPT * H.slots * B));
+    WM_HIP(hipMemset(p->scal, 0, sizeof(double) * 2 * B));
+    WM_HIP(hipMemset(p->status, 0, sizeof(int) * B));
+
+    // ---- Jacobi diagonal (Sec. 5.1), on the device ----------------------
+    void* jac_t = nullptr;
+    if (!(p->jac_d = static_cast<double*>(p->alloc(sizeof(double) * p->n, &rc)))) return rc;
+    if (p->dtype == WMCAO_F32) {
+        if (!(jac_t = p->alloc(sizeof(float) * p->n, &rc))) return rc;
+    } else {
+        jac_t = p->jac_d;
+    }
+    H.jac = jac_t;
+    void* dev = nullptr;
+    rc = upload(p.get(), &H, sizeof(PlanDev), &dev);
+    if (rc) return rc;
+    p->dev = static_cast<PlanDev*>(dev);
+    {
+        std::vector<double> protos;
+        std::vector<int> poff(WM_MAXL * WM_MAXLEV * 2, 0);
+        for (int l = 0; l < n_layers; ++l)
+            for (int k = 1; k <= levels; ++k)
+                for (int t = 0; t < 2; ++t) {
+                    poff[(l * WM_MAXLEV + (k - 1)) * 2 + t] = static_cast<int>(protos.size());
+                    auto v = prototype(H.h, H.g, H.layer[l].N, k, t);
+                    protos.insert(protos.end(), v.begin(), v.end());
+                }
+        const double* pr = nullptr;
+        const int* po = nullptr;
+        UP(protos, pr);
+        UP(poff, po);
+        launch_jacobi(p->dev, pr, po, txd_dev, tyd_dev, blk_dev_d, p->n, p->jac_d, nullptr);
+        rc = check_launch();
+        if (rc) return rc;
+        if (p->dtype == WMCAO_F32)
+            launch_cast_from_double<float>(p->jac_d, static_cast<float*>(jac_t), p->n, nullptr);
+        rc = check_launch();
+        if (rc) return rc;
+        WM_HIP(hipDeviceSynchronize());
+    }
+#undef UP
+    *out = p.release();
+    return WMCAO_OK;
+}
+
+int wmcao_sizes(wmcao_plan_t plan, int64_t* n_coeffs, int64_t* n_slopes, int64_t* layer_offsets,
+                int64_t* slope_offsets) {
+    if (!plan) return fail(WMCAO_ERR_INVALID_ARG, "plan is NULL");
+    if (n_coeffs) *n_coeffs = plan->n;
+    if (n_slopes) *n_slopes = plan->n_slopes;
+    if (layer_offsets)
+        for (int l = 0; l <= plan->L; ++l) layer_offsets[l] = plan->layer_off[l];
+    if (slope_offsets)
+        for (int m = 0; m <= plan->W; ++m) slope_offsets[m] = plan->slope_off[m];
+    return WMCAO_OK;
+}
+
+static int simple_call(wmcao_plan_t p, const void* in, void* out, int batch, void* stream,
+                       int kind) {
+    int rc = check_batch(p, batch);
+    if (rc) return rc;
+    if (!in || !out) return fail(WMCAO_ERR_INVALID_ARG, "NULL buffer");
+    std::lock_guard<std::mutex> lk(p->mu);
+    DevGuard g(p->device);
+    Sched* S = nullptr;
+    rc = get_sched(p, batch, &S);
+    if (rc) return rc;
+    JobArgs a{};
+    a.njp = 1;
+    a.jp[0] = make_jobplan(p, batch);
+    a.jp[0].vec[V_IN] = const_cast<void*>(in);
+    a.jp[0].vec[V_OUT] = out;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool f32 = p->dtype == WMCAO_F32;
+    ProfScope ps(&p->prof);
+    switch (kind) {
+        case 0:   // W^-1
+            a.jp[0].stride[V_IN] = a.jp[0].stride[V_OUT] = p->n;
+            if (f32) run_idwt<float>(a, *S, V_IN, V_OUT, s); else run_idwt<double>(a, *S, V_IN, V_OUT, s);
+            break;
+        case 1:   // W
+            a.jp[0].stride[V_IN] = a.jp[0].stride[V_OUT] = p->n;
+            if (f32) run_fdwt<float>(a, *S, SRC_PIX, V_IN, V_OUT, EPI_NONE, V_IN, s);
+            else run_fdwt<double>(a, *S, SRC_PIX, V_IN, V_OUT, EPI_NONE, V_IN, s);
+            break;
+        case 2:   // forward slopes from layers
+            a.jp[0].stride[V_IN] = p->n;
+            a.jp[0].stride[V_OUT] = p->n_slopes;
+            if (f32) launch_sensor<float>(a, S->sensor, S->n_sensor, SM_FWD, V_IN, V_OUT, S->lds_sensor, s);
+            else launch_sensor<double>(a, S->sensor, S->n_sensor, SM_FWD, V_IN, V_OUT, S->lds_sensor, s);
+            break;
+        case 3:   // rhs
+            a.jp[0].stride[V_IN] = p->n_slopes;
+            a.jp[0].stride[V_OUT] = p->n;
+            if (f32) run_rhs<float>(a, *S, V_IN, V_OUT, s); else run_rhs<double>(a, *S, V_IN, V_OUT, s);
+            break;
+        case 4:   // apply
+            a.jp[0].stride[V_IN] = a.jp[0].stride[V_OUT] = p->n;
+            if (f32) run_apply<float>(a, *S, V_IN, V_OUT, s); else run_apply<double>(a, *S, V_IN, V_OUT, s);
+            break;
+        default:
+            return fail(WMCAO_ERR_INVALID_ARG, "kind");
+    }
+    return check_launch();
+}
+
+int wmcao_coeffs_to_layers(wmcao_plan_t plan, const void* coeffs, void* layers, int batch,
+                           void* hip_stream) {
+    return simple_call(plan, coeffs, layers, batch, hip_stream, 0);
+}
+
+int wmcao_layers_to_coeffs(wmcao_plan_t plan, const void* layers, void* coeffs, int batch,
+                           void* hip_stream) {
+    return simple_call(plan, layers, coeffs, batch, hip_stream, 1);
+}
+
+int wmcao_forward_layers(wmcao_plan_t plan, const void* layers, void* slopes, int batch,
+                         void* hip_stream) {
+    return simple_call(plan, layers, slopes, batch, hip_stream, 2);
+}
+
+int wmcao_rhs(wmcao_plan_t plan, const void* slopes, void* b, int batch, void* hip_stream) {
+    return simple_call(plan, slopes, b, batch, hip_stream, 3);
+}
+
+int wmcao_apply_A(wmcao_plan_t plan, const void* x, void* y, int batch, void* hip_stream) {
+    if (x == y) return fail(WMCAO_ERR_INVALID_ARG, "x and y must not alias");
+    return simple_call(plan, x, y, batch, hip_stream, 4);
+}
+
+int wmcao_precond_diag(wmcao_plan_t plan, double* j_dev, void* hip_stream) {
+    if (!plan || !j_dev) return fail(WMCAO_ERR_INVALID_ARG, "NULL argument");
+    DevGuard g(plan->device);
+    WM_HIP(hipMemcpyAsync(j_dev, plan->jac_d, sizeof(double) * plan->n, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(hip_stream)));
+    return WMCAO_OK;
+}
+
+int wmcao_solve(wmcao_plan_t plan, const void* slopes, void* coeffs, int batch, int n_iter,
+                int warm_start, double* resid_dev, int* status_dev, void* hip_stream) {
+    int rc = check_batch(plan, batch);
+    if (rc) return rc;
+    if (!slopes || !coeffs) return fail(WMCAO_ERR_INVALID_ARG, "NULL buffer");
+    if (n_iter < 0) return fail(WMCAO_ERR_INVALID_ARG, "n_iter < 0");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    DevGuard g(plan->device);
+    ProfScope ps(&plan->prof);
+    return enqueue_solve(plan, slopes, coeffs, batch, n_iter, warm_start, resid_dev, status_dev,
+                         static_cast<hipStream_t>(hip_stream));
+}
+
+int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int batch, int n_iter,
+                      int warm_start, double* resid_dev, int* status_dev, void* hip_stream) {
+    int rc = check_batch(plan, batch);
+    if (rc) return rc;
+    if (!slopes || !coeffs) return fail(WMCAO_ERR_INVALID_ARG, "NULL buffer");
+    if (!hip_stream) return fail(WMCAO_ERR_INVALID_ARG, "graph capture needs a non-default stream");
+    if (n_iter < 0) return fail(WMCAO_ERR_INVALID_ARG, "n_iter < 0");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    DevGuard g(plan->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    auto key = std::make_tuple(slopes, coeffs, batch, n_iter, warm_start, resid_dev, status_dev,
+                               hip_stream);
+    if (!plan->gexec || plan->gkey != key) {
+        Sched* S = nullptr;
+        rc = get_sched(plan, batch, &S);   // build outside the capture (it allocates)
+        if (rc) return rc;
+        if (plan->gexec) {
+            (void)hipGraphExecDestroy(plan->gexec);
+            plan->gexec = nullptr;
+        }
+        WM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_solve(plan, slopes, coeffs, batch, n_iter, warm_start, resid_dev, status_dev, s);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(WMCAO_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&plan->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            plan->gexec = nullptr;
+            return fail(WMCAO_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+        }
+        plan->gkey = key;
+    }
+    WM_HIP(hipGraphLaunch(plan->gexec, s));
+    return WMCAO_OK;
+}
+
+int wmcao_solve_multi(const wmcao_plan_t* plans, const void* const* slopes, void* const* coeffs,
+                      const int* counts, int n_plans, int n_iter, int warm_start,
+                      void* hip_stream) {
+    if (!plans || !slopes || !coeffs || !counts) return fail(WMCAO_ERR_INVALID_ARG, "NULL argument");
+    if (n_plans < 1 || n_plans > WM_MAXJP) return fail(WMCAO_ERR_INVALID_ARG, "n_plans out of range");
+    if (n_iter < 0) return fail(WMCAO_ERR_INVALID_ARG, "n_iter < 0");
+    const wmcao_dtype dt = plans[0] ? plans[0]->dtype : WMCAO_F32;
+    std::vector<JobSpec> jobs;
+    for (int i = 0; i < n_plans; ++i) {
+        int rc = check_batch(plans[i], counts[i]);
+        if (rc) return rc;
+        if (plans[i]->dtype != dt) return fail(WMCAO_ERR_INVALID_ARG, "plans must share the dtype");
+        if (!slopes[i] || !coeffs[i]) return fail(WMCAO_ERR_INVALID_ARG, "NULL buffer");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(WMCAO_ERR_INVALID_ARG, "a plan appears twice");
+        jobs.push_back(JobSpec{plans[i], counts[i]});
+    }
+    // one schedule per distinct job shape, dropped when one of its plans is destroyed
+    std::vector<std::pair<const void*, int>> key;
+    for (auto& j : jobs) key.emplace_back(j.plan, j.count);
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    auto& cache = g_multi_cache;
+    std::vector<std::unique_lock<std::mutex>> locks;
+    for (auto& j : jobs) locks.emplace_back(j.plan->mu);
+    DevGuard g(plans[0]->device);
+    const int tile = plans[0]->tile;
+    for (auto& j : jobs)
+        if (j.plan->tile != tile) return fail(WMCAO_ERR_INVALID_ARG, "plans must share the tile size");
+    auto it = cache.find(key);
+    Sched* S = nullptr;
+    if (it == cache.end()) {
+        auto sp = std::make_unique<Sched>();
+        int rc = build_sched(jobs, tile, sp.get());
+        if (rc) return rc;
+        S = sp.get();
+        cache[key] = std::move(sp);
+    } else {
+        S = it->second.get();
+    }
+    JobArgs a{};
+    a.njp = n_plans;
+    int rr = 0;
+    for (int i = 0; i < n_plans; ++i) {
+        a.jp[i] = make_jobplan(plans[i], counts[i]);
+        a.jp[i].vec[V_X] = coeffs[i];
+        a.jp[i].vec[V_SLOPES] = const_cast<void*>(slopes[i]);
+        rr = std::max(rr, plans[i]->resid_replace);
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (dt == WMCAO_F32)
+        run_solve<float>(a, *S, n_iter, warm_start, rr, s);
+    else
+        run_solve<double>(a, *S, n_iter, warm_start, rr, s);
+    return check_launch();
+}
+
+int wmcao_profile_enable(wmcao_plan_t plan, int enable) {
+    if (!plan) return fail(WMCAO_ERR_INVALID_ARG, "plan is NULL");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    DevGuard g(plan->device);
+    if (enable) {
+        WM_HIP(hipDeviceSynchronize());
+        plan->prof.clear();
+    }
+    plan->prof.on = enable != 0;
+    return WMCAO_OK;
+}
+
+int wmcao_profile_read(wmcao_plan_t plan, int kind, double* total_ms, int* launches) {
+    if (!plan || !total_ms || !launches || kind < 0 || kind >= WMCAO_K_COUNT)
+        return fail(WMCAO_ERR_INVALID_ARG, "bad argument");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    DevGuard g(plan->device);
+    double tot = 0.0;
+    int cnt = 0;
+    for (auto& r : plan->prof.rec) {
+        if (std::get<0>(r) != kind) continue;
+        WM_HIP(hipEventSynchronize(std::get<2>(r)));
+        float ms = 0.0f;
+        WM_HIP(hipEventElapsedTime(&ms, std::get<1>(r), std::get<2>(r)));
+        tot += ms;
+        ++cnt;
+    }
+    *total_ms = tot;
+    *launches = cnt;
+    return WMCAO_OK;
+}
+
+void wmcao_plan_destroy(wmcao_plan_t plan) {
+    if (!plan) return;
+    DevGuard g(plan->device);
+    (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lk(g_multi_mu);
+        for (auto it = g_multi_cache.begin(); it != g_multi_cache.end();) {
+            bool uses = false;
+            for (auto& kv : it->first) uses = uses || kv.first == plan;
+            if (uses) it = g_multi_cache.erase(it); else ++it;
+        }
+    }
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    delete plan;
+}
+
+}  // extern "C"
