@@ -36,6 +36,8 @@ N_FRAMES_ROT = 4            # distinct frozen-flow frames per stream in rotation
 def _cpu_worker(args):
     """Oracle on frames of one stream: rhs + 10 warm PCG iterations timed."""
     stream, frames, n_iter = args
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)                     # one core per worker process
     import oracle as O
     cfg = WL.config_c2()
     S0 = O.System(cfg, [1.0] * len(cfg["wfs"]))
@@ -62,8 +64,6 @@ def _cpu_worker(args):
 
 def cpu_baseline(workers, frames_per_worker, n_iter):
     import multiprocessing as mp
-    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        os.environ[v] = "1"
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
@@ -79,28 +79,87 @@ def cpu_baseline(workers, frames_per_worker, n_iter):
 
 
 # ----------------------------------------------------------------- GPU leg ----
-def algorithmic_bytes(plan_info, kernel, esz, frames, epi_apply=True):
-    """Bytes one launch of ``kernel`` must move for ``frames`` frames (see the
-    per-kernel table in the design notes): n unknowns, Q node values."""
-    n, Q = plan_info["n"], plan_info["n_nodes"]
-    lay = plan_info["layers"]                      # list of (N, k0)
-    if kernel == "update_p":                       # read x, p, r, J; write x, p
-        per = 6 * n
-    elif kernel == "update_r":                     # read r, q, J; write r
-        per = 4 * n
-    elif kernel == "idwt_tile":                    # level-1 launch: read LL1 + details, write pixels
-        per = 2 * sum(N * N for N, k0 in lay if k0 >= 1)
-    elif kernel == "fdwt_tile":                    # nodes in; p details in; LL1 + details out
-        per = Q + (1.75 if epi_apply else 1.0) * sum(N * N for N, k0 in lay if k0 >= 1)
-    elif kernel == "idwt_coarse":
-        per = 2 * sum((N >> k0) ** 2 for N, k0 in lay)
-    elif kernel == "fdwt_coarse":
-        per = 3 * sum((N >> k0) ** 2 for N, k0 in lay)
-    elif kernel == "sensor":                       # pixels of every layer in, node fields out
-        per = n + Q
-    else:
-        per = 4 * n
-    return per * esz * frames
+def pctl(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
+
+
+def served_stream(duration_s, rate_hz, n_iter):
+    """Poisson arrivals over four telescope configurations (8 m and 16 m
+    NGS-only, 39 m and 42 m LGS-only), one stream each at rate_hz/4, served
+    with continuous batching in FP32; frozen-flow frames from a pool of 8 per
+    stream.  Returns latency percentiles and throughput."""
+    import torch
+    from paper_1302_3734_amd import Plan
+    from paper_1302_3734_amd.serve import Server
+    names = ["C4-8m-ngs", "C4-16m-ngs", "C4-39m-lgs", "C4-42m-lgs"]
+    cfgs, pools = {}, {}
+    for nm in names:
+        cfg = WL.config_by_name(nm)
+        fwd = Plan(cfg, [1.0] * len(cfg["wfs"]), dtype="f64", max_batch=1)
+        so = fwd.slope_offsets
+        lay = []
+        for t in range(8):
+            v = np.concatenate([a.ravel() for a in WL.layer_screens(cfg, t, seed_frame=0)])
+            lay.append(fwd.forward_layers(torch.tensor(v, device="cuda")[None])[0])
+        sig = WL.sigmas_from_clean(cfg, lay[0].cpu().numpy(), so)
+        sv = torch.tensor(np.concatenate([np.full(so[m + 1] - so[m], sig[m])
+                                          for m in range(len(sig))]), device="cuda")
+        pools[nm] = [(lay[t] + sv * torch.tensor(WL.noise_draw(cfg["cfg_id"], t, fwd.n_slopes),
+                                                 device="cuda")).float() for t in range(8)]
+        cfgs[nm] = (cfg, sig)
+        fwd.close()
+    srv = Server(cfgs, {nm: nm for nm in names}, dtype="f32", n_iter=n_iter, hip_streams=2)
+    arrivals = sorted((t, nm) for k, nm in enumerate(names)
+                      for t in WL.poisson_arrivals(500 + k, rate_hz / len(names), duration_s))
+    torch.cuda.synchronize()
+    futs = []
+    cnt = {nm: 0 for nm in names}
+    t0 = time.perf_counter()
+    for t, nm in arrivals:
+        while time.perf_counter() - t0 < t:
+            pass
+        futs.append(srv.submit(nm, pools[nm][cnt[nm] % 8]))
+        cnt[nm] += 1
+    for f in futs:
+        f.result(timeout=120)
+    elapsed = time.perf_counter() - t0
+    srv.close()
+    lat = srv.latencies_ms()
+    return {"configs": names, "rate_hz": rate_hz, "duration_s": duration_s, "frames": len(lat),
+            "frames_per_s": round(len(lat) / elapsed, 1),
+            "p50_frame_latency_ms": round(pctl(lat, 0.5), 4),
+            "p99_frame_latency_ms": round(pctl(lat, 0.99), 4),
+            "launches": srv.launches,
+            "mean_frames_per_launch": round(float(np.mean(srv.frames_in_launch)), 3)}
+
+
+def onaxis_residual(cfg, layers_vec, truth_vec):
+    """On-axis wavefront residual (rad RMS at 500 nm, piston removed) over the
+    pupil nodes of the 84x84 grid, and its Marechal Strehl in K band (2.2 um).
+    At zero field angle the 0.5 m nodes coincide with 0.5 m layer pixels, so
+    the on-axis wavefront is a plain sum of layer samples."""
+    n_sub, D, eps = 84, cfg["diameter"], cfg["obstruction"]
+    d = D / n_sub
+    c = (np.arange(n_sub) + 0.5 - n_sub / 2.0) * d
+    r2 = c[:, None] ** 2 + c[None, :] ** 2
+    act = (r2 <= (D / 2) ** 2) & (r2 >= (eps * D / 2) ** 2)
+    nodes = np.zeros((n_sub + 1, n_sub + 1), bool)
+    for di in (0, 1):
+        for dj in (0, 1):
+            nodes[di:di + n_sub, dj:dj + n_sub] |= act
+    diff = np.asarray(layers_vec, dtype=np.float64) - np.asarray(truth_vec, dtype=np.float64)
+    w = np.zeros((n_sub + 1, n_sub + 1))
+    off = 0
+    for L in cfg["layers"]:
+        N = L["n"]
+        lay = diff[off:off + N * N].reshape(N, N)
+        o = N // 2 - n_sub // 2
+        w += lay[o:o + n_sub + 1, o:o + n_sub + 1]
+        off += N * N
+    v = w[nodes] - w[nodes].mean()
+    rms = float(np.sqrt(np.mean(v ** 2)))
+    return rms, float(np.exp(-(rms * 0.5 / 2.2) ** 2))
 
 
 def main():
@@ -115,6 +174,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the per-frame FP64 comparison")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -189,7 +250,7 @@ def main():
     wall = time.perf_counter() - wall0
     lat = sorted(a.elapsed_time(b) for a, b in ev)
     p50 = statistics.median(lat)
-    p99 = lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]
+    p99 = pctl(lat, 0.99)
     fps = B * K / wall
     ms_step = 1e3 * wall / K
     print(f"[bench] fp32 batch {B}: {fps:.1f} frames/s, {ms_step:.3f} ms/step, p99 {p99:.3f} ms",
@@ -203,17 +264,20 @@ def main():
     prof = p32.profile_read()
     p32.profile(False)
     dom = max(prof, key=lambda k: prof[k][0])
-    dms, dcnt = prof[dom]
-    plan_info = {"n": n, "n_nodes": 9 * 85 * 85,
-                 "layers": [(L["n"], 0 if (L["n"] ** 2) * 4 <= 65536 else 1) for L in cfg["layers"]]}
-    abytes = algorithmic_bytes(plan_info, dom, 4, B)
+    dms, dcnt, dbytes = prof[dom]
     avg_s = dms / max(dcnt, 1) / 1e3
+    abytes = dbytes / max(dcnt, 1)
     achieved = abytes / avg_s / 1e9
+    tot_ms = sum(v[0] for v in prof.values())
     kernels = {k: {"avg_us": round(1e3 * v[0] / v[1], 3), "launches": v[1],
-                   "share": round(v[0] / sum(x[0] for x in prof.values()), 4)}
+                   "share": round(v[0] / tot_ms, 4),
+                   "gbs": round(v[2] / (v[0] / 1e3) / 1e9, 1)}
                for k, v in prof.items() if v[1]}
     print(f"[bench] dominant kernel {dom}: {1e6 * avg_s:.1f} us/launch, {achieved:.0f} GB/s",
           flush=True)
+    for k, v in kernels.items():
+        print(f"[bench]   {k:12s} {v['avg_us']:9.1f} us  x{v['launches']:4d}  "
+              f"{100 * v['share']:5.1f}%  {v['gbs']:7.1f} GB/s", flush=True)
 
     # ---- reconstruction check and the per-frame FP64 comparison -------------
     result = {}
@@ -240,30 +304,38 @@ def main():
         stream.synchronize()
         l64 = sorted(a.elapsed_time(b) for a, b in lat64[2:])
         fps64 = 1e3 / statistics.mean(l64)
-        p99_64 = l64[min(len(l64) - 1, int(math.ceil(0.99 * len(l64))) - 1)]
-        # equal reconstruction: FP32 and FP64 solves of stream 0 frame 1 from
-        # the same frame-0 reconstructions
+        p99_64 = pctl(l64, 0.99)
+        # equal reconstruction: FP32 and FP64 solves of stream 0 frame 1, both
+        # warm-started from the same FP64 frame-0 reconstruction
         xa = torch.zeros(1, n, dtype=torch.float64, device="cuda")
         p64.solve(slopes64[0, :1].contiguous(), xa, n_iter=30)
+        xb = xa.float()
         p64.solve(slopes64[1, :1].contiguous(), xa, n_iter=IT, warm_start=True)
-        xb = torch.zeros(1, n, dtype=torch.float32, device="cuda")
-        p32.solve(slopes32[0, :1].contiguous(), xb, n_iter=30)
         p32.solve(slopes32[1, :1].contiguous(), xb, n_iter=IT, warm_start=True)
         la = p64.coeffs_to_layers(xa).cpu().numpy().ravel()
         lb = p32.coeffs_to_layers(xb).double().cpu().numpy().ravel()
         tr = truths[1]
-        err_a = float(np.linalg.norm(la - tr) / np.linalg.norm(tr))
-        err_b = float(np.linalg.norm(lb - tr) / np.linalg.norm(tr))
+        rms_a, strehl_a = onaxis_residual(cfg, la, tr)
+        rms_b, strehl_b = onaxis_residual(cfg, lb, tr)
+        rms_0, _ = onaxis_residual(cfg, np.zeros_like(tr), tr)
         result["fp64_per_frame"] = {"frames_per_s": round(fps64, 2),
                                     "p99_frame_latency_ms": round(p99_64, 4),
                                     "mode": "batch 1, hipGraph replay"}
         result["reconstruction"] = {
+            "frame": "stream 0, frame 1, both warm-started from the FP64 30-iteration frame 0",
             "fp32_vs_fp64_coeff_rel_diff": float(
                 np.linalg.norm(xb.double().cpu().numpy() - xa.cpu().numpy())
                 / np.linalg.norm(xa.cpu().numpy())),
-            "truth_rel_err_fp64": err_a, "truth_rel_err_fp32": err_b,
-            "truth_err_rel_diff": abs(err_a - err_b) / err_a}
+            "onaxis_uncorrected_rms_rad": round(rms_0, 4),
+            "onaxis_residual_rms_rad_fp64": round(rms_a, 5),
+            "onaxis_residual_rms_rad_fp32": round(rms_b, 5),
+            "strehl_K_fp64": round(strehl_a, 5), "strehl_K_fp32": round(strehl_b, 5),
+            "strehl_rel_diff": abs(strehl_a - strehl_b) / strehl_a}
         p64.close()
+
+    if args.serve_seconds > 0:
+        result["served"] = served_stream(args.serve_seconds, args.serve_rate, IT)
+        print(f"[bench] served {result['served']}", flush=True)
 
     out = {
         "metric": "PCG frames/s and p99 frame latency at E-ELT scale; operator HBM GB/s vs peak",

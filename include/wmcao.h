@@ -204,14 +204,15 @@ int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int b
 /* Kernel kinds for per-kernel timing. */
 #define WMCAO_K_IDWT_COARSE 0   /* W^-1, low-pass block in LDS            */
 #define WMCAO_K_IDWT_TILE 1     /* W^-1, one tiled level                  */
-#define WMCAO_K_SENSOR 2        /* P, Gamma, C^-1, (I-T), Gamma^T         */
+#define WMCAO_K_SENSOR 2        /* Gamma, C^-1, (I-T), Gamma^T            */
 #define WMCAO_K_FDWT_TILE 3     /* P^T + W one tiled level + alpha D, dot */
 #define WMCAO_K_FDWT_COARSE 4   /* W coarse levels + alpha D, dot         */
 #define WMCAO_K_INIT 5          /* r0, p0                                 */
 #define WMCAO_K_UPDATE_R 6      /* r -= a q, <r, J^-1 r>                  */
 #define WMCAO_K_UPDATE_P 7      /* x += a p, p = J^-1 r + beta p          */
 #define WMCAO_K_REPLACE_R 8     /* r = b - A x                            */
-#define WMCAO_K_COUNT 9
+#define WMCAO_K_PROJECT 9       /* P: layers -> sensor node fields        */
+#define WMCAO_K_COUNT 10
 
 /* Per-kernel timing of later wmcao_solve / wmcao_apply_A calls on this plan:
  * with enable != 0 every launch is bracketed by HIP events on the launch
@@ -219,9 +220,12 @@ int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int b
  * stops recording; the accumulated times are kept until the next enable. */
 int wmcao_profile_enable(wmcao_plan_t plan, int enable);
 
-/* Accumulated device time (ms) and launch count of one kernel kind since the
- * last enable.  Synchronises with the recorded events. */
-int wmcao_profile_read(wmcao_plan_t plan, int kind, double* total_ms, int* launches);
+/* Accumulated device time (ms), launch count and algorithmic bytes (what the
+ * launches must read and write, counted per frame from the plan's sizes; may be
+ * NULL) of one kernel kind since the last enable.  Synchronises with the
+ * recorded events. */
+int wmcao_profile_read(wmcao_plan_t plan, int kind, double* total_ms, int* launches,
+                       double* bytes);
 
 /* Free the plan and everything it owns (waits for the device). */
 void wmcao_plan_destroy(wmcao_plan_t plan);

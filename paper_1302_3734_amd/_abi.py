@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(HERE, "libwmcao.so")
 WMCAO_F32, WMCAO_F64 = 0, 1
 WMCAO_FRAME_OK, WMCAO_FRAME_CONVERGED, WMCAO_FRAME_BREAKDOWN = 0, 1, -7
 KERNELS = ["idwt_coarse", "idwt_tile", "sensor", "fdwt_tile", "fdwt_coarse", "init", "update_r",
-           "update_p", "replace_r"]
+           "update_p", "replace_r", "project"]
 ERRORS = {-1: "INVALID_ARG", -2: "SIZE", -3: "FOOTPRINT", -4: "UNSUPPORTED", -5: "OOM",
           -6: "HIP", -7: "BREAKDOWN"}
 
@@ -69,7 +69,8 @@ def lib():
         L.wmcao_solve_multi.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                         C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int, vp]
         L.wmcao_profile_enable.argtypes = [vp, C.c_int]
-        L.wmcao_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.wmcao_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int),
+                                         C.POINTER(C.c_double)]
         L.wmcao_plan_destroy.argtypes = [vp]
         L.wmcao_plan_destroy.restype = None
         L.wmcao_strerror.restype = C.c_char_p

@@ -14,6 +14,7 @@
 #define WM_MAXJP 8        // plans packed into one launch
 #define WM_QMAX 16        // elements per thread of the 1024-thread kernels
 #define WM_NSUB_MAX 127   // nodes per sensor <= 128^2
+#define WM_PTK 4          // sensor nodes touching one layer pixel row (bilinear adjoint)
 
 namespace wm {
 
@@ -30,6 +31,7 @@ enum Vec : int {
     V_SLOPES,     // caller's slopes (in)
     V_IN,         // caller's generic input
     V_OUT,        // caller's generic output
+    V_U,          // sensor node fields of the projection, FP64 (scratch)
     NV
 };
 
@@ -61,6 +63,17 @@ struct WfsInfo {
     const int* maskmap;     // [n_sub * n_sub] measurement index of a fine subaperture or -1
 };
 
+// Adjoint-projection weights of one layer pixel row (or column) for one
+// sensor: the nodes f..f+c-1 touch it with weights w[0..c-1].
+struct PixTab {
+    int f, c, pad0, pad1;
+    double w[WM_PTK];
+};
+
+// Per (layer, tile) record of the adjoint projection: bit m of mask is set if
+// sensor m touches the tile's pixel window; its node rows are alo[m]..ahi[m].
+constexpr int TMETA = 1 + 2 * WM_MAXW;
+
 struct PlanDev {
     int L, W, levels, dtype;
     int precond;
@@ -78,10 +91,10 @@ struct PlanDev {
     const int* jy0;
     const double* tx;       // bilinear weight of the right/upper pixel per node
     const double* ty;
-    const int* pfx;         // first node touching pixel row p
-    const int* pcx;         // number of nodes touching pixel row p
-    const int* pfy;
-    const int* pcy;
+    const PixTab* pixx;     // per (sensor, layer) pixel rows: nodes touching them
+    const PixTab* pixy;     // per (sensor, layer) pixel columns
+    const int* tmeta;       // TMETA ints per (layer, level-1 tile) (one per layer if k0 = 0)
+    int tmeta_off[WM_MAXL];
     int node_tab_off[WM_MAXW][WM_MAXL];
     int pix_tab_off[WM_MAXW][WM_MAXL];
     const void* jac;        // [n] Jacobi diagonal, plan dtype
@@ -126,7 +139,9 @@ void launch_fdwt_tile(const JobArgs& a, const Item* items, int n, int level, int
                       int out_vec, int epi, int aux_vec, int tile, hipStream_t s);
 template <class T>
 void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int in_vec,
-                        int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s);
+                        int out_vec, int epi, int aux_vec, int lds_bytes, int tcap, hipStream_t s);
+template <class T>
+void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, hipStream_t s);
 template <class T>
 void launch_sensor(const JobArgs& a, const Item* items, int n, int mode, int in_vec, int out_vec,
                    int lds_bytes, hipStream_t s);
@@ -146,5 +161,6 @@ template <class T>
 void launch_cast_from_double(const double* in, T* out, int64_t n, hipStream_t s);
 
 constexpr int VEC_CHUNK = 2048;   // elements per block of the vector kernels
+constexpr int PROJ_ROWS = 8;      // sensor node rows per block of the projection
 
 }  // namespace wm

@@ -80,10 +80,9 @@ __device__ __forceinline__ void load_filters(const PlanDev& P, Acc* hf, Acc* gf)
 // stride ld), along y (columns within a row) or along x, staged through
 // registers: x_i = sum over the 3 coarse k with 0 <= i - 2k < 6 of
 // h[i-2k] lo_k + g[i-2k] hi_k.
-template <class T>
-__device__ void syn_pass(T* A, int ld, int M, int along_y, const Acc* hf, const Acc* gf) {
+__device__ void syn_pass(Acc* A, int ld, int M, int along_y, const Acc* hf, const Acc* gf) {
     const int H = M >> 1, cnt = M * M;
-    T reg[WM_QMAX];
+    Acc reg[WM_QMAX];
 #pragma unroll
     for (int r = 0; r < WM_QMAX; ++r) {
         const int e = threadIdx.x + r * blockDim.x;
@@ -101,7 +100,7 @@ __device__ void syn_pass(T* A, int ld, int M, int along_y, const Acc* hf, const 
                 const Acc hi = along_y ? A[row * ld + H + k] : A[(H + k) * ld + col];
                 acc += hf[n] * lo + gf[n] * hi;
             }
-            reg[r] = static_cast<T>(acc);
+            reg[r] = acc;
         }
     }
     __syncthreads();
@@ -118,10 +117,9 @@ __device__ void syn_pass(T* A, int ld, int M, int along_y, const Acc* hf, const 
 
 // One in-place periodic analysis step: a_c = sum_n h_n x[(2c+n) mod M] into
 // the low half, d_c with g into the high half.
-template <class T>
-__device__ void ana_pass(T* A, int ld, int M, int along_y, const Acc* hf, const Acc* gf) {
+__device__ void ana_pass(Acc* A, int ld, int M, int along_y, const Acc* hf, const Acc* gf) {
     const int H = M >> 1, cnt = M * M;
-    T reg[WM_QMAX];
+    Acc reg[WM_QMAX];
 #pragma unroll
     for (int r = 0; r < WM_QMAX; ++r) {
         const int e = threadIdx.x + r * blockDim.x;
@@ -138,7 +136,7 @@ __device__ void ana_pass(T* A, int ld, int M, int along_y, const Acc* hf, const 
                 const Acc v = along_y ? A[row * ld + idx] : A[idx * ld + col];
                 acc += (hi ? gf[n] : hf[n]) * v;
             }
-            reg[r] = static_cast<T>(acc);
+            reg[r] = acc;
         }
     }
     __syncthreads();
@@ -153,43 +151,72 @@ __device__ void ana_pass(T* A, int ld, int M, int along_y, const Acc* hf, const 
     __syncthreads();
 }
 
-// Adjoint projection of all sensors onto pixel (px, py) of layer l:
-// g = sum_m sum_{a,b} wx_m(a,px) wy_m(b,py) v_m[a][b], where node a of sensor m
-// touches pixel px with weight 1-t if its left pixel is px and t if it is
-// px-1 (the transpose of the bilinear samples, gathered without atomics).
+// Adjoint projection P^T of the sensors that touch a window of PR x PC pixels
+// of layer l starting at (px0, py0) (periodic indices), accumulated into G
+// (row stride ldg, FP64).  Because P_ml = B_x (kron) B_y, P^T v = B_x^T V B_y is
+// done separably per sensor: T[a][c] = sum_b wy(b, c) V[a][b] over the node rows
+// a = alo..ahi the window needs (LDS), then G[r][c] += sum_a wx(a, r) T[a][c].
+// The weights are the transpose of the bilinear samples (precomputed per
+// pixel row and column).  rec is the tile's record (sensor mask, node-row
+// ranges).  No atomics; each G entry belongs to one thread.  A window whose
+// node rows do not fit in T (tcap values) takes the direct per-pixel sum.
 template <class T>
-__device__ Acc pt_gather(const PlanDev& P, const T* nodes, int l, int px, int py) {
-    const double* txp = P.tx;
-    const double* typ = P.ty;
-    Acc acc = 0;
+__device__ void pt_gather_window(const PlanDev& P, const T* nodes, int l, int N, int px0, int py0,
+                                 int PR, int PC, Acc* G, int ldg, Acc* Tb, int tcap,
+                                 const int* rec) {
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const unsigned mask = static_cast<unsigned>(rec[0]);
     for (int m = 0; m < P.W; ++m) {
+        if (!((mask >> m) & 1u)) continue;
+        const int alo = rec[1 + m], ahi = rec[1 + WM_MAXW + m];
         const int po = P.pix_tab_off[m][l];
-        const int cx = P.pcx[po + px];
-        if (cx == 0) continue;
-        const int cy = P.pcy[po + py];
-        if (cy == 0) continue;
-        const int fx = P.pfx[po + px], fy = P.pfy[po + py];
-        const int no = P.node_tab_off[m][l];
+        const PixTab* tx = P.pixx + po;
+        const PixTab* ty = P.pixy + po;
         const int nn = P.wfs[m].nn;
-        const T* vm = nodes + P.wfs[m].node_off;
-        for (int a = fx; a < fx + cx; ++a) {
-            const Acc t = txp[no + a];
-            const Acc wa = (P.ix0[no + a] == px) ? (1.0 - t) : t;
-            Acc row = 0;
-            for (int b = fy; b < fy + cy; ++b) {
-                const Acc s = typ[no + b];
-                const Acc wb = (P.jy0[no + b] == py) ? (1.0 - s) : s;
-                row += wb * static_cast<Acc>(vm[a * nn + b]);
+        const T* V = nodes + P.wfs[m].node_off;
+        const int NR = ahi - alo + 1;
+        if (NR * PC <= tcap) {
+            for (int e = tid; e < NR * PC; e += bd) {
+                const int la = e / PC, c = e - (e / PC) * PC;
+                const PixTab& cy = ty[(py0 + c) % N];
+                const T* vr = V + (alo + la) * nn + cy.f;
+                Acc acc = 0;
+                for (int q = 0; q < cy.c; ++q) acc += cy.w[q] * static_cast<Acc>(vr[q]);
+                Tb[e] = acc;
             }
-            acc += wa * row;
+            __syncthreads();
+            for (int e = tid; e < PR * PC; e += bd) {
+                const int r = e / PC, c = e - (e / PC) * PC;
+                const PixTab& rx = tx[(px0 + r) % N];
+                if (rx.c == 0) continue;
+                const Acc* tr = Tb + (rx.f - alo) * PC + c;
+                Acc acc = 0;
+                for (int q = 0; q < rx.c; ++q) acc += rx.w[q] * tr[q * PC];
+                G[r * ldg + c] += acc;
+            }
+            __syncthreads();
+        } else {
+            for (int e = tid; e < PR * PC; e += bd) {
+                const int r = e / PC, c = e - (e / PC) * PC;
+                const PixTab& rx = tx[(px0 + r) % N];
+                const PixTab& cy = ty[(py0 + c) % N];
+                if (rx.c == 0 || cy.c == 0) continue;
+                Acc acc = 0;
+                for (int qa = 0; qa < rx.c; ++qa) {
+                    const T* vr = V + (rx.f + qa) * nn + cy.f;
+                    Acc row = 0;
+                    for (int qb = 0; qb < cy.c; ++qb) row += cy.w[qb] * static_cast<Acc>(vr[qb]);
+                    acc += rx.w[qa] * row;
+                }
+                G[r * ldg + c] += acc;
+            }
         }
     }
-    return acc;
 }
 
 // ------------------------------------------------------------------ W^-1 ----
 // Levels J..k0+1 of the synthesis of one layer, with the whole M0 x M0
-// (M0 = N / 2^k0) low-pass block resident in LDS.
+// (M0 = N / 2^k0) low-pass block resident in LDS (FP64).
 template <class T>
 __global__ void __launch_bounds__(1024)
 k_idwt_coarse(const JobArgs args, const Item* __restrict__ items, int in_vec, int out_vec) {
@@ -199,7 +226,7 @@ k_idwt_coarse(const JobArgs args, const Item* __restrict__ items, int in_vec, in
     const LayerInfo& Ly = P.layer[it.a];
     const int N = Ly.N, k0 = Ly.k0, M0 = N >> k0;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* A = reinterpret_cast<T*>(smem_raw);
+    Acc* A = reinterpret_cast<Acc*>(smem_raw);
     Acc hf[6], gf[6];
     load_filters(P, hf, gf);
     const T* src = vptr<T>(J, in_vec, it.frame) + Ly.coff;
@@ -208,8 +235,8 @@ k_idwt_coarse(const JobArgs args, const Item* __restrict__ items, int in_vec, in
     __syncthreads();
     for (int lev = P.levels; lev > k0; --lev) {
         const int M = N >> (lev - 1);
-        syn_pass<T>(A, M0, M, 0, hf, gf);   // undo the x step
-        syn_pass<T>(A, M0, M, 1, hf, gf);   // undo the y step
+        syn_pass(A, M0, M, 0, hf, gf);   // undo the x step
+        syn_pass(A, M0, M, 1, hf, gf);   // undo the y step
     }
     T* dst;
     int ld;
@@ -221,7 +248,7 @@ k_idwt_coarse(const JobArgs args, const Item* __restrict__ items, int in_vec, in
         ld = N;
     }
     for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x)
-        dst[static_cast<int64_t>(e / M0) * ld + (e % M0)] = A[e];
+        dst[static_cast<int64_t>(e / M0) * ld + (e % M0)] = static_cast<T>(A[e]);
 }
 
 // One synthesis level k <= k0 over a TS x TS output tile: reads the low-pass
@@ -233,8 +260,8 @@ __global__ void __launch_bounds__(256)
 k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int in_vec,
             int out_vec) {
     constexpr int CW = TS / 2 + 2;
-    __shared__ T sLL[CW][CW + 1], sLH[CW][CW + 1], sHL[CW][CW + 1], sHH[CW][CW + 1];
-    __shared__ T sAL[TS][CW + 1], sAH[TS][CW + 1];
+    __shared__ Acc sLL[CW][CW + 1], sLH[CW][CW + 1], sHL[CW][CW + 1], sHH[CW][CW + 1];
+    __shared__ Acc sAL[TS][CW + 1], sAH[TS][CW + 1];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -267,11 +294,11 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             const int k = base - t, n = par + 2 * t;
-            al += hf[n] * static_cast<Acc>(sLL[k][b]) + gf[n] * static_cast<Acc>(sHL[k][b]);
-            ah += hf[n] * static_cast<Acc>(sLH[k][b]) + gf[n] * static_cast<Acc>(sHH[k][b]);
+            al += hf[n] * sLL[k][b] + gf[n] * sHL[k][b];
+            ah += hf[n] * sLH[k][b] + gf[n] * sHH[k][b];
         }
-        sAL[li][b] = static_cast<T>(al);
-        sAH[li][b] = static_cast<T>(ah);
+        sAL[li][b] = al;
+        sAH[li][b] = ah;
     }
     __syncthreads();
     T* dst;
@@ -292,7 +319,7 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             const int k = base - t, n = par + 2 * t;
-            v += hf[n] * static_cast<Acc>(sAL[li][k]) + gf[n] * static_cast<Acc>(sAH[li][k]);
+            v += hf[n] * sAL[li][k] + gf[n] * sAH[li][k];
         }
         dst[static_cast<int64_t>(i) * ld + j] = static_cast<T>(v);
     }
@@ -309,8 +336,10 @@ __global__ void __launch_bounds__(256)
 k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int src, int in_vec,
             int out_vec, int epi, int aux_vec) {
     constexpr int HT = TS / 2, PW = TS + 4;
-    __shared__ T sA[PW][PW + 1];
-    __shared__ T sL[PW][HT + 1], sH[PW][HT + 1];
+    constexpr int TCAP = (PW + PW / 2 + 4) * PW;   // node rows of a window at scale >= 2/3
+    __shared__ Acc sA[PW][PW + 1];
+    __shared__ Acc sL[PW][HT + 1], sH[PW][HT + 1];
+    __shared__ Acc sT[TCAP];
     __shared__ double red[17];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
@@ -322,23 +351,27 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     const int px0 = 2 * cx0, py0 = 2 * cy0;
     Acc hf[6], gf[6];
     load_filters(P, hf, gf);
-    const T* in = nullptr;
-    int ld = N;
-    if (level > 1) {
-        in = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[level - 1];
-        ld = M;
-    } else if (src == SRC_PIX) {
-        in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
+    if (level == 1 && src == SRC_PT) {
+        for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) sA[e / PW][e % PW] = 0;
+        __syncthreads();
+        pt_gather_window<T>(P, vptr<T>(J, in_vec, it.frame), it.a, N, px0, py0, PW, PW,
+                            &sA[0][0], PW + 1, sT, TCAP,
+                            P.tmeta + (P.tmeta_off[it.a] + it.b) * TMETA);
     } else {
-        in = vptr<T>(J, in_vec, it.frame);   // node fields of this frame
-    }
-    for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) {
-        const int a = e / PW, b = e % PW;
-        const int gx = (px0 + a) % M, gy = (py0 + b) % M;
-        if (level == 1 && src == SRC_PT)
-            sA[a][b] = static_cast<T>(pt_gather<T>(P, in, it.a, gx, gy));
-        else
+        const T* in;
+        int ld;
+        if (level > 1) {
+            in = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[level - 1];
+            ld = M;
+        } else {
+            in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
+            ld = N;
+        }
+        for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) {
+            const int a = e / PW, b = e % PW;
+            const int gx = (px0 + a) % M, gy = (py0 + b) % M;
             sA[a][b] = in[static_cast<int64_t>(gx) * ld + gy];
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < PW * HT; e += blockDim.x) {
@@ -350,8 +383,8 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
             lo += hf[n] * v;
             hi += gf[n] * v;
         }
-        sL[a][c] = static_cast<T>(lo);
-        sH[a][c] = static_cast<T>(hi);
+        sL[a][c] = lo;
+        sH[a][c] = hi;
     }
     __syncthreads();
     T* out = vptr<T>(J, out_vec, it.frame) + Ly.coff;
@@ -399,13 +432,14 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     }
 }
 
-// Levels k0+1..J of the analysis with the M0 x M0 block in LDS, then the
-// epilogue over every coefficient of that block.  At k0 = 0 the block is the
-// whole layer, read (SRC_PIX) or gathered through P^T (SRC_PT).
+// Levels k0+1..J of the analysis with the M0 x M0 block in LDS (FP64), then
+// the epilogue over every coefficient of that block.  At k0 = 0 the block is
+// the whole layer, read (SRC_PIX) or gathered through P^T (SRC_PT).  Dynamic
+// LDS: the block, then (SRC_PT at k0 = 0) tcap values of gather scratch.
 template <class T>
 __global__ void __launch_bounds__(1024)
 k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int in_vec,
-              int out_vec, int epi, int aux_vec) {
+              int out_vec, int epi, int aux_vec, int tcap) {
     __shared__ double red[17];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
@@ -413,7 +447,7 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
     const LayerInfo& Ly = P.layer[it.a];
     const int N = Ly.N, k0 = Ly.k0, M0 = N >> k0;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* A = reinterpret_cast<T*>(smem_raw);
+    Acc* A = reinterpret_cast<Acc*>(smem_raw);
     Acc hf[6], gf[6];
     load_filters(P, hf, gf);
     if (k0 > 0) {
@@ -423,15 +457,16 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
         const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
         for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = in[e];
     } else {
-        const T* nodes = vptr<T>(J, in_vec, it.frame);
-        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x)
-            A[e] = static_cast<T>(pt_gather<T>(P, nodes, it.a, e / M0, e % M0));
+        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = 0;
+        __syncthreads();
+        pt_gather_window<T>(P, vptr<T>(J, in_vec, it.frame), it.a, N, 0, 0, N, N, A, N,
+                            A + M0 * M0, tcap, P.tmeta + P.tmeta_off[it.a] * TMETA);
     }
     __syncthreads();
     for (int lev = k0 + 1; lev <= P.levels; ++lev) {
         const int M = N >> (lev - 1);
-        ana_pass<T>(A, M0, M, 1, hf, gf);   // along y first
-        ana_pass<T>(A, M0, M, 0, hf, gf);   // then along x
+        ana_pass(A, M0, M, 1, hf, gf);   // along y first
+        ana_pass(A, M0, M, 0, hf, gf);   // then along x
     }
     T* out = vptr<T>(J, out_vec, it.frame) + Ly.coff;
     const T* pv = (epi == EPI_APPLY) ? vptr<T>(J, aux_vec, it.frame) + Ly.coff : nullptr;
@@ -439,14 +474,16 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
     for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) {
         const int x = e / M0, y = e % M0;
         const int64_t gi = static_cast<int64_t>(x) * N + y;
-        T v = A[e];
+        Acc v = A[e];
         if (epi == EPI_APPLY) {
             const int k = level_of(x, y, N, P.levels);
             const Acc p = pv[gi];
-            v = static_cast<T>(static_cast<Acc>(v) + P.alpha * Ly.D[k - 1] * p);
-            acc += p * static_cast<Acc>(v);
+            const T o = static_cast<T>(v + P.alpha * Ly.D[k - 1] * p);
+            acc += p * static_cast<Acc>(o);
+            out[gi] = o;
+        } else {
+            out[gi] = static_cast<T>(v);
         }
-        out[gi] = v;
     }
     if (epi == EPI_APPLY) {
         const double s = block_sum(acc, red);
@@ -454,12 +491,45 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
     }
 }
 
+// --------------------------------------------------------- projection ----
+// u_m = sum over layers of bilinear samples of the layer pixels at the sensor
+// nodes (Sec. 2.1, eq. (2) and the cone-effect projection), PROJ_ROWS node
+// rows per block, written in FP64 so that the Fried differences of the next
+// stage do not cancel single-precision digits.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_project(const JobArgs args, const Item* __restrict__ items, int in_vec) {
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    const int m = it.a;
+    const int nn = P.wfs[m].nn;
+    const int r0 = it.b * PROJ_ROWS;
+    const int rows = min(PROJ_ROWS, nn - r0);
+    const T* phi = vptr<T>(J, in_vec, it.frame);
+    double* u = vptr<double>(J, V_U, it.frame) + P.wfs[m].node_off;
+    for (int e = threadIdx.x; e < rows * nn; e += blockDim.x) {
+        const int i = r0 + e / nn, j = e % nn;
+        Acc acc = 0;
+        for (int l = 0; l < P.L; ++l) {
+            const int no = P.node_tab_off[m][l];
+            const int i0 = P.ix0[no + i], j0 = P.jy0[no + j];
+            const Acc t = P.tx[no + i], s = P.ty[no + j];
+            const int N = P.layer[l].N;
+            const T* f = phi + P.layer[l].coff + static_cast<int64_t>(i0) * N + j0;
+            acc += (1.0 - t) * ((1.0 - s) * static_cast<Acc>(f[0]) + s * static_cast<Acc>(f[1])) +
+                   t * ((1.0 - s) * static_cast<Acc>(f[N]) + s * static_cast<Acc>(f[N + 1]));
+        }
+        u[i * nn + j] = acc;
+    }
+}
+
 // ----------------------------------------------------------- one sensor ----
-// SM_APPLY: layer pixels -> node field u (bilinear, summed over layers) ->
-//           Fried slopes (aggregated for a low-order sensor) -> C^-1 with
-//           (I - T) for tip/tilt-removed sensors -> Gamma^T -> node field v.
+// SM_APPLY: node field u (from k_project) -> Fried slopes (aggregated for a
+//           low-order sensor) -> C^-1 with (I - T) for tip/tilt-removed
+//           sensors -> Gamma^T -> node field v.
 // SM_RHS:   input slopes -> C^-1 (and (I - T)) -> Gamma^T -> v.
-// SM_FWD:   layer pixels -> raw slopes to the output.
+// SM_FWD:   node field u -> raw slopes to the output.
 // One block of 1024 threads per (frame, sensor); the node field and the
 // weighted-slope grids live in LDS in FP64; QM elements per thread.
 template <class T, int QM>
@@ -481,21 +551,8 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
     for (int r = 0; r < QM; ++r) sx[r] = sy[r] = 0;
 
     if (mode != SM_RHS) {
-        const T* phi = vptr<T>(J, in_vec, it.frame);
-        for (int e = tid; e < nn * nn; e += bd) {
-            const int i = e / nn, j = e % nn;
-            Acc acc = 0;
-            for (int l = 0; l < P.L; ++l) {
-                const int no = P.node_tab_off[m][l];
-                const int i0 = P.ix0[no + i], j0 = P.jy0[no + j];
-                const Acc t = P.tx[no + i], s = P.ty[no + j];
-                const int N = P.layer[l].N;
-                const T* f = phi + P.layer[l].coff + static_cast<int64_t>(i0) * N + j0;
-                acc += (1.0 - t) * ((1.0 - s) * static_cast<Acc>(f[0]) + s * static_cast<Acc>(f[1])) +
-                       t * ((1.0 - s) * static_cast<Acc>(f[N]) + s * static_cast<Acc>(f[N + 1]));
-            }
-            U[e] = acc;
-        }
+        const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
+        for (int e = tid; e < nn * nn; e += bd) U[e] = ug[e];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < QM; ++r) {
@@ -1007,10 +1064,16 @@ void launch_fdwt_tile(const JobArgs& a, const Item* items, int n, int level, int
 
 template <class T>
 void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int in_vec,
-                        int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s) {
+                        int out_vec, int epi, int aux_vec, int lds_bytes, int tcap, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fdwt_coarse<T>, dim3(n), dim3(1024), lds_bytes, s, a, items, src, in_vec,
-                       out_vec, epi, aux_vec);
+                       out_vec, epi, aux_vec, tcap);
+}
+
+template <class T>
+void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(256), 0, s, a, items, in_vec);
 }
 
 template <class T>
@@ -1091,8 +1154,9 @@ void configure_kernels() {
     template void launch_idwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, hipStream_t); \
     template void launch_idwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
     template void launch_fdwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, int, hipStream_t); \
-    template void launch_fdwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, hipStream_t); \
+    template void launch_fdwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, int, hipStream_t); \
     template void launch_sensor<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
+    template void launch_project<T>(const JobArgs&, const Item*, int, int, hipStream_t);       \
     template void launch_init<T>(const JobArgs&, const Item*, int, int, hipStream_t);          \
     template void launch_update_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \
     template void launch_update_p<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \

@@ -53,18 +53,28 @@ struct Sched {
     int n_tiled[WM_MAXLEV + 1] = {};
     const Item* sensor = nullptr;
     int n_sensor = 0;
+    const Item* proj = nullptr;
+    int n_proj = 0;
     const Item* vec = nullptr;
     int n_vec = 0;
     int maxk0 = 0;
-    int lds_coarse = 0;
+    int lds_idwt = 0;      // dynamic LDS of the whole-band synthesis
+    int lds_fdwt = 0;      // dynamic LDS of the whole-band analysis (+ gather tables)
+    int tcap = 0;          // gather scratch values of the whole-band analysis
     int lds_sensor = 0;
     int tile = 32;
+    // algorithmic bytes one launch of each stage moves (all frames of the job)
+    double b_idwt_coarse = 0, b_idwt_tile[WM_MAXLEV + 1] = {};
+    double b_fdwt_tile[2][WM_MAXLEV + 1] = {}, b_fdwt_coarse[2] = {};   // [plain, apply]
+    double b_sensor[3] = {};                                              // [apply, rhs, fwd]
+    double b_project = 0;
+    double b_init = 0, b_update_r = 0, b_update_p = 0, b_replace = 0;
 };
 
 // Per-plan kernel timing with HIP events on the launch stream.
 struct Profiler {
     bool on = false;
-    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> rec;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t, double>> rec;
     std::vector<hipEvent_t> pool;
     hipEvent_t get() {
         if (!pool.empty()) {
@@ -93,7 +103,7 @@ thread_local Profiler* g_prof = nullptr;
 
 // Launch through f, bracketed by events when a profiler is active.
 template <class F>
-void timed(int kind, hipStream_t s, F&& f) {
+void timed(int kind, double bytes, hipStream_t s, F&& f) {
     if (!g_prof || !g_prof->on) {
         f();
         return;
@@ -102,7 +112,7 @@ void timed(int kind, hipStream_t s, F&& f) {
     (void)hipEventRecord(a, s);
     f();
     (void)hipEventRecord(b, s);
-    g_prof->rec.emplace_back(kind, a, b);
+    g_prof->rec.emplace_back(kind, a, b, bytes);
 }
 
 struct ProfScope {
@@ -132,11 +142,13 @@ struct wmcao_plan_s {
     void* vphi = nullptr;
     void* vll = nullptr;
     void* vnode = nullptr;
+    double* vu = nullptr;
     double* part = nullptr;
     double* scal = nullptr;
     int* status = nullptr;
     double* jac_d = nullptr;
     int64_t n = 0, n_slopes = 0, n_nodes = 0, ll_size = 0;
+    int64_t n_fp = 0;   // layer pixels some sensor node's bilinear stencil touches
     std::vector<int64_t> layer_off, slope_off;
     std::map<int, std::unique_ptr<Sched>> sched;
     // captured graph of one wmcao_solve_graph argument set
@@ -231,9 +243,20 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // partials into slots 0.. in the order level-1 tiles, level-2 tiles, ...,
 // coarse blocks; the vector passes use one slot per chunk.
 int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
-    std::vector<Item> coarse, sensor, vec;
+    std::vector<Item> coarse, sensor, vec, proj;
     std::vector<Item> tiled[WM_MAXLEV + 1];
-    int maxk0 = 0, lds_c = 0, lds_s = 0;
+    int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0, tcap = 1 << 30;
+    // gather scratch of whole layers analysed in one block (k0 = 0)
+    for (const auto& j : jobs)
+        for (int l = 0; l < j.plan->L; ++l) {
+            const LayerInfo& Ly = j.plan->host.layer[l];
+            if (Ly.k0 != 0) continue;
+            const int N = Ly.N;
+            const int base = N * N * 8;
+            const int want = (N + N / 2 + 4) * N;
+            tcap = std::min(tcap, std::min(want, std::max(0, (159 * 1024 - base) / 8)));
+        }
+    if (tcap == (1 << 30)) tcap = 0;
     for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
         const wmcao_plan_s* P = jobs[jp].plan;
         for (int f = 0; f < jobs[jp].count; ++f) {
@@ -250,17 +273,55 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
             }
             for (int l = 0; l < P->L; ++l) {
                 coarse.push_back(Item{jp, f, l, 0, slot++, 0, 0, 0});
-                const int M0 = P->host.layer[l].N >> P->host.layer[l].k0;
-                lds_c = std::max(lds_c, static_cast<int>(M0 * M0 * P->esz));
+                const LayerInfo& Ly = P->host.layer[l];
+                const int N = Ly.N, M0 = N >> Ly.k0;
+                lds_i = std::max(lds_i, M0 * M0 * 8);
+                int need = M0 * M0 * 8;
+                if (Ly.k0 == 0) need += tcap * 8;
+                lds_f = std::max(lds_f, need);
             }
             for (int m = 0; m < P->W; ++m) {
                 sensor.push_back(Item{jp, f, m, 0, 0, 0, 0, 0});
+                const int nb = ceil_div(P->host.wfs[m].nn, PROJ_ROWS);
+                for (int b = 0; b < nb; ++b) proj.push_back(Item{jp, f, m, b, 0, 0, 0, 0});
                 const int nn = P->host.wfs[m].nn;
                 lds_s = std::max(lds_s, static_cast<int>(nn * nn * sizeof(double)));
             }
             const int nch = static_cast<int>((P->n + VEC_CHUNK - 1) / VEC_CHUNK);
             for (int c = 0; c < nch; ++c) vec.push_back(Item{jp, f, 0, c, c, 0, 0, 0});
         }
+        // algorithmic bytes (see the kernel table in the design notes)
+        const double e = static_cast<double>(P->esz) * jobs[jp].count;
+        const double Q = static_cast<double>(P->n_nodes), n = static_cast<double>(P->n);
+        bool gathers_tile = false, gathers_coarse = false;
+        for (int l = 0; l < P->L; ++l) {
+            const LayerInfo& Ly = P->host.layer[l];
+            const double M0 = Ly.N >> Ly.k0;
+            S->b_idwt_coarse += 2 * M0 * M0 * e;
+            S->b_fdwt_coarse[0] += (Ly.k0 ? 2 : 1) * M0 * M0 * e;
+            S->b_fdwt_coarse[1] += (Ly.k0 ? 3 : 2) * M0 * M0 * e;
+            gathers_coarse = gathers_coarse || Ly.k0 == 0;
+            for (int k = 1; k <= Ly.k0; ++k) {
+                const double M = Ly.N >> (k - 1);
+                S->b_idwt_tile[k] += 2 * M * M * e;
+                S->b_fdwt_tile[0][k] += (k == 1 ? 1 : 2) * M * M * e;
+                S->b_fdwt_tile[1][k] += (k == 1 ? 1.75 : 2.75) * M * M * e;
+                gathers_tile = gathers_tile || k == 1;
+            }
+        }
+        for (int a = 0; a < 2; ++a) {
+            if (gathers_tile) S->b_fdwt_tile[a][1] += Q * e;
+            if (gathers_coarse) S->b_fdwt_coarse[a] += Q * e;
+        }
+        const double u8 = 8.0 * jobs[jp].count;     // node fields of the projection are FP64
+        S->b_project += P->n_fp * e + Q * u8;
+        S->b_sensor[0] += Q * u8 + Q * e;
+        S->b_sensor[1] += P->n_slopes * e + Q * e;
+        S->b_sensor[2] += Q * u8 + P->n_slopes * e;
+        S->b_init += 5 * n * e;
+        S->b_update_r += 4 * n * e;
+        S->b_update_p += 6 * n * e;
+        S->b_replace += 4 * n * e;
     }
     std::vector<Item> all;
     std::vector<size_t> offs;
@@ -271,6 +332,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     add(coarse);
     add(sensor);
     add(vec);
+    add(proj);
     for (int k = 1; k <= WM_MAXLEV; ++k) add(tiled[k]);
     S->buf = std::make_unique<DevBuf>();
     const size_t bytes = std::max<size_t>(all.size(), 1) * sizeof(Item);
@@ -284,12 +346,16 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     S->n_sensor = static_cast<int>(sensor.size());
     S->vec = base + offs[2];
     S->n_vec = static_cast<int>(vec.size());
+    S->proj = base + offs[3];
+    S->n_proj = static_cast<int>(proj.size());
     for (int k = 1; k <= WM_MAXLEV; ++k) {
-        S->tiled[k] = base + offs[2 + k];
+        S->tiled[k] = base + offs[3 + k];
         S->n_tiled[k] = static_cast<int>(tiled[k].size());
     }
     S->maxk0 = maxk0;
-    S->lds_coarse = lds_c;
+    S->lds_idwt = lds_i;
+    S->lds_fdwt = lds_f;
+    S->tcap = tcap;
     S->lds_sensor = lds_s;
     S->tile = tile;
     return WMCAO_OK;
@@ -322,6 +388,8 @@ JobPlan make_jobplan(wmcao_plan_s* p, int nframes) {
     J.vec[V_PHI] = p->vphi;
     J.vec[V_LL] = p->vll;
     J.vec[V_NODE] = p->vnode;
+    J.vec[V_U] = p->vu;
+    J.stride[V_U] = p->n_nodes;
     for (int v : {V_X, V_B, V_R, V_P, V_Q, V_PHI}) J.stride[v] = p->n;
     J.stride[V_LL] = p->ll_size;
     J.stride[V_NODE] = p->n_nodes;
@@ -338,11 +406,11 @@ JobPlan make_jobplan(wmcao_plan_s* p, int nframes) {
 // ------------------------------------------------------- stage drivers ----
 template <class T>
 void run_idwt(const JobArgs& a, const Sched& S, int in_vec, int out_vec, hipStream_t s) {
-    timed(WMCAO_K_IDWT_COARSE, s, [&] {
-        launch_idwt_coarse<T>(a, S.coarse, S.n_coarse, in_vec, out_vec, S.lds_coarse, s);
+    timed(WMCAO_K_IDWT_COARSE, S.b_idwt_coarse, s, [&] {
+        launch_idwt_coarse<T>(a, S.coarse, S.n_coarse, in_vec, out_vec, S.lds_idwt, s);
     });
     for (int k = S.maxk0; k >= 1; --k)
-        timed(WMCAO_K_IDWT_TILE, s, [&] {
+        timed(WMCAO_K_IDWT_TILE, S.b_idwt_tile[k], s, [&] {
             launch_idwt_tile<T>(a, S.tiled[k], S.n_tiled[k], k, in_vec, out_vec, S.tile, s);
         });
 }
@@ -351,13 +419,13 @@ template <class T>
 void run_fdwt(const JobArgs& a, const Sched& S, int src, int in_vec, int out_vec, int epi,
               int aux_vec, hipStream_t s) {
     for (int k = 1; k <= S.maxk0; ++k)
-        timed(WMCAO_K_FDWT_TILE, s, [&] {
+        timed(WMCAO_K_FDWT_TILE, S.b_fdwt_tile[epi == EPI_APPLY][k], s, [&] {
             launch_fdwt_tile<T>(a, S.tiled[k], S.n_tiled[k], k, src, in_vec, out_vec, epi,
                                 aux_vec, S.tile, s);
         });
-    timed(WMCAO_K_FDWT_COARSE, s, [&] {
+    timed(WMCAO_K_FDWT_COARSE, S.b_fdwt_coarse[epi == EPI_APPLY], s, [&] {
         launch_fdwt_coarse<T>(a, S.coarse, S.n_coarse, src, in_vec, out_vec, epi, aux_vec,
-                              S.lds_coarse, s);
+                              S.lds_fdwt, S.tcap, s);
     });
 }
 
@@ -365,15 +433,16 @@ void run_fdwt(const JobArgs& a, const Sched& S, int src, int in_vec, int out_vec
 template <class T>
 void run_apply(const JobArgs& a, const Sched& S, int x_vec, int y_vec, hipStream_t s) {
     run_idwt<T>(a, S, x_vec, V_PHI, s);
-    timed(WMCAO_K_SENSOR, s, [&] {
-        launch_sensor<T>(a, S.sensor, S.n_sensor, SM_APPLY, V_PHI, V_NODE, S.lds_sensor, s);
+    timed(WMCAO_K_PROJECT, S.b_project, s, [&] { launch_project<T>(a, S.proj, S.n_proj, V_PHI, s); });
+    timed(WMCAO_K_SENSOR, S.b_sensor[0], s, [&] {
+        launch_sensor<T>(a, S.sensor, S.n_sensor, SM_APPLY, V_U, V_NODE, S.lds_sensor, s);
     });
     run_fdwt<T>(a, S, SRC_PT, V_NODE, y_vec, EPI_APPLY, x_vec, s);
 }
 
 template <class T>
 void run_rhs(const JobArgs& a, const Sched& S, int slopes_vec, int b_vec, hipStream_t s) {
-    timed(WMCAO_K_SENSOR, s, [&] {
+    timed(WMCAO_K_SENSOR, S.b_sensor[1], s, [&] {
         launch_sensor<T>(a, S.sensor, S.n_sensor, SM_RHS, slopes_vec, V_NODE, S.lds_sensor, s);
     });
     run_fdwt<T>(a, S, SRC_PT, V_NODE, b_vec, EPI_NONE, b_vec, s);
@@ -384,15 +453,15 @@ void run_solve(const JobArgs& a, const Sched& S, int n_iter, int warm, int resid
                hipStream_t s) {
     run_rhs<T>(a, S, V_SLOPES, V_B, s);
     if (warm) run_apply<T>(a, S, V_X, V_Q, s);
-    timed(WMCAO_K_INIT, s, [&] { launch_init<T>(a, S.vec, S.n_vec, warm, s); });
+    timed(WMCAO_K_INIT, S.b_init, s, [&] { launch_init<T>(a, S.vec, S.n_vec, warm, s); });
     for (int it = 0; it < n_iter; ++it) {
         if (resid_replace > 0 && it > 0 && it % resid_replace == 0) {
             run_apply<T>(a, S, V_X, V_Q, s);
-            timed(WMCAO_K_REPLACE_R, s, [&] { launch_replace_r<T>(a, S.vec, S.n_vec, it, s); });
+            timed(WMCAO_K_REPLACE_R, S.b_replace, s, [&] { launch_replace_r<T>(a, S.vec, S.n_vec, it, s); });
         }
         run_apply<T>(a, S, V_P, V_Q, s);
-        timed(WMCAO_K_UPDATE_R, s, [&] { launch_update_r<T>(a, S.vec, S.n_vec, it, s); });
-        timed(WMCAO_K_UPDATE_P, s, [&] { launch_update_p<T>(a, S.vec, S.n_vec, it, s); });
+        timed(WMCAO_K_UPDATE_R, S.b_update_r, s, [&] { launch_update_r<T>(a, S.vec, S.n_vec, it, s); });
+        timed(WMCAO_K_UPDATE_P, S.b_update_p, s, [&] { launch_update_p<T>(a, S.vec, S.n_vec, it, s); });
     }
 }
 
@@ -521,9 +590,9 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     p->levels = levels;
     p->max_batch = opts->max_batch;
     p->tile = opts->tile ? opts->tile : 32;
-    if (p->dtype == WMCAO_F64 && p->tile == 64) p->tile = 32;   // LDS of a 64-tile in FP64
-    p->lds_budget = opts->lds_budget > 0 ? opts->lds_budget : 64 * 1024;
-    p->lds_budget = std::min(p->lds_budget, 160 * 1024);
+    // LDS of the whole-band wavelet block (FP64): 32 KB keeps it at <= 64 x 64
+    p->lds_budget = opts->lds_budget > 0 ? opts->lds_budget : 32 * 1024;
+    p->lds_budget = std::min(p->lds_budget, 128 * 1024);
     p->resid_replace = opts->resid_replace_every;
     PlanDev& H = p->host;
     H.L = n_layers;
@@ -545,11 +614,11 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         int k0 = 0;
         while (k0 < levels - 1) {
             const int64_t M0 = N >> k0;
-            if (M0 * M0 * static_cast<int64_t>(p->esz) <= p->lds_budget && M0 * M0 <= 1024 * WM_QMAX) break;
+            if (M0 * M0 * 8 <= p->lds_budget && M0 * M0 <= 1024 * WM_QMAX) break;
             ++k0;
         }
         const int64_t M0 = N >> k0;
-        if (M0 * M0 * static_cast<int64_t>(p->esz) > 160 * 1024 || M0 * M0 > 1024 * WM_QMAX)
+        if (M0 * M0 * 8 > 128 * 1024 || M0 * M0 > 1024 * WM_QMAX)
             return fail(WMCAO_ERR_UNSUPPORTED, "layer too large for the wavelet kernels");
         Ly.k0 = k0;
         for (int k = 1; k <= k0; ++k) {
@@ -573,7 +642,8 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     p->layer_off[n_layers] = off;
 
     // ---- sensors --------------------------------------------------------
-    std::vector<int> ix0, jy0, pfx, pcx, pfy, pcy;
+    std::vector<int> ix0, jy0;
+    std::vector<PixTab> pixx, pixy;
     std::vector<double> txd, tyd, blocksd;
     int64_t soff = 0, noff = 0;
     p->slope_off.assign(1, 0);
@@ -657,13 +727,12 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             const int N = layers[l].n;
             const double d = layers[l].spacing_m;
             H.node_tab_off[m][l] = static_cast<int>(ix0.size());
-            H.pix_tab_off[m][l] = static_cast<int>(pfx.size());
+            H.pix_tab_off[m][l] = static_cast<int>(pixx.size());
             for (int axis = 0; axis < 2; ++axis) {
                 const double theta = axis == 0 ? w.theta_x : w.theta_y;
                 std::vector<int>& i0v = axis == 0 ? ix0 : jy0;
                 std::vector<double>& tv = axis == 0 ? txd : tyd;
-                std::vector<int>& fv = axis == 0 ? pfx : pfy;
-                std::vector<int>& cv = axis == 0 ? pcx : pcy;
+                std::vector<PixTab>& pv = axis == 0 ? pixx : pixy;
                 const size_t base = i0v.size();
                 for (int i = 0; i < nn; ++i) {
                     const double xi = (i - ns / 2.0) * dsub;
@@ -685,14 +754,37 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
                     }
                 }
                 for (int px = 0; px < N; ++px) {
-                    fv.push_back(first[px] < 0 ? 0 : first[px]);
-                    cv.push_back(first[px] < 0 ? 0 : last[px] - first[px] + 1);
+                    const int cnt = first[px] < 0 ? 0 : last[px] - first[px] + 1;
+                    if (cnt > WM_PTK)
+                        return fail(WMCAO_ERR_UNSUPPORTED, "sensor nodes denser than 3 per layer pixel");
+                    PixTab t{};
+                    t.f = first[px] < 0 ? 0 : first[px];
+                    t.c = cnt;
+                    for (int q = 0; q < cnt; ++q) {   // transpose of the bilinear weights
+                        const int a = t.f + q;
+                        const double tt = tv[base + a];
+                        t.w[q] = (i0v[base + a] == px) ? 1.0 - tt : tt;
+                    }
+                    pv.push_back(t);
                 }
             }
         }
     }
     p->n_slopes = soff;
     p->n_nodes = noff;
+    for (int l = 0; l < n_layers; ++l) {   // pixels the projection reads
+        const int N = layers[l].n;
+        std::vector<char> hit(static_cast<size_t>(N) * N, 0);
+        for (int m = 0; m < n_wfs; ++m) {
+            const int nn = H.wfs[m].nn, no = H.node_tab_off[m][l];
+            for (int i = 0; i < nn; ++i)
+                for (int j = 0; j < nn; ++j)
+                    for (int di = 0; di < 2; ++di)
+                        for (int dj = 0; dj < 2; ++dj)
+                            hit[static_cast<size_t>(ix0[no + i] + di) * N + jy0[no + j] + dj] = 1;
+        }
+        for (char c : hit) p->n_fp += c;
+    }
     H.n_slopes = soff;
     H.n_nodes = noff;
 
@@ -710,10 +802,47 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     }
     UP(ix0, H.ix0);
     UP(jy0, H.jy0);
-    UP(pfx, H.pfx);
-    UP(pcx, H.pcx);
-    UP(pfy, H.pfy);
-    UP(pcy, H.pcy);
+    UP(pixx, H.pixx);
+    UP(pixy, H.pixy);
+    {
+        // adjoint-projection records per (layer, level-1 tile), or per layer at k0 = 0
+        std::vector<int> meta;
+        const int HT = p->tile / 2, PW = p->tile + 4;
+        for (int l = 0; l < n_layers; ++l) {
+            const int N = H.layer[l].N;
+            H.tmeta_off[l] = static_cast<int>(meta.size() / TMETA);
+            const int nt = H.layer[l].k0 >= 1 ? ceil_div(N / 2, HT) : 1;
+            for (int t = 0; t < nt * nt; ++t) {
+                int x0 = 0, y0 = 0, W0 = N;
+                if (H.layer[l].k0 >= 1) {
+                    x0 = 2 * (t % nt) * HT;
+                    y0 = 2 * (t / nt) * HT;
+                    W0 = PW;
+                }
+                std::vector<int> rec(TMETA, 0);
+                for (int m = 0; m < n_wfs; ++m) {
+                    const int po = H.pix_tab_off[m][l];
+                    int alo = 1 << 30, ahi = -1;
+                    bool anyc = false;
+                    for (int k = 0; k < W0; ++k) {
+                        const PixTab& rx = pixx[po + (x0 + k) % N];
+                        if (rx.c > 0) {
+                            alo = std::min(alo, rx.f);
+                            ahi = std::max(ahi, rx.f + rx.c - 1);
+                        }
+                        anyc = anyc || pixy[po + (y0 + k) % N].c > 0;
+                    }
+                    if (ahi >= alo && anyc) {
+                        rec[0] |= 1 << m;
+                        rec[1 + m] = alo;
+                        rec[1 + WM_MAXW + m] = ahi;
+                    }
+                }
+                meta.insert(meta.end(), rec.begin(), rec.end());
+            }
+        }
+        UP(meta, H.tmeta);
+    }
     const double* txd_dev = nullptr;
     const double* tyd_dev = nullptr;
     const double* blk_dev_d = nullptr;
@@ -749,6 +878,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     if (!(p->vphi = p->alloc(ve, &rc))) return rc;
     if (!(p->vll = p->alloc(static_cast<size_t>(p->ll_size) * B * p->esz, &rc))) return rc;
     if (!(p->vnode = p->alloc(static_cast<size_t>(p->n_nodes) * B * p->esz, &rc))) return rc;
+    if (!(p->vu = static_cast<double*>(p->alloc(static_cast<size_t>(p->n_nodes) * B * 8, &rc)))) return rc;
     if (!(p->part = static_cast<double*>(p->alloc(sizeof(double) * NPT * H.slots * B, &rc)))) return rc;
     if (!(p->scal = static_cast<double*>(p->alloc(sizeof(double) * 2 * B, &rc)))) return rc;
     if (!(p->status = static_cast<int*>(p->alloc(sizeof(int) * B, &rc)))) return rc;
@@ -840,8 +970,13 @@ static int simple_call(wmcao_plan_t p, const void* in, void* out, int batch, voi
         case 2:   // forward slopes from layers
             a.jp[0].stride[V_IN] = p->n;
             a.jp[0].stride[V_OUT] = p->n_slopes;
-            if (f32) launch_sensor<float>(a, S->sensor, S->n_sensor, SM_FWD, V_IN, V_OUT, S->lds_sensor, s);
-            else launch_sensor<double>(a, S->sensor, S->n_sensor, SM_FWD, V_IN, V_OUT, S->lds_sensor, s);
+            if (f32) {
+                launch_project<float>(a, S->proj, S->n_proj, V_IN, s);
+                launch_sensor<float>(a, S->sensor, S->n_sensor, SM_FWD, V_U, V_OUT, S->lds_sensor, s);
+            } else {
+                launch_project<double>(a, S->proj, S->n_proj, V_IN, s);
+                launch_sensor<double>(a, S->sensor, S->n_sensor, SM_FWD, V_U, V_OUT, S->lds_sensor, s);
+            }
             break;
         case 3:   // rhs
             a.jp[0].stride[V_IN] = p->n_slopes;
@@ -1012,12 +1147,13 @@ int wmcao_profile_enable(wmcao_plan_t plan, int enable) {
     return WMCAO_OK;
 }
 
-int wmcao_profile_read(wmcao_plan_t plan, int kind, double* total_ms, int* launches) {
+int wmcao_profile_read(wmcao_plan_t plan, int kind, double* total_ms, int* launches,
+                       double* bytes) {
     if (!plan || !total_ms || !launches || kind < 0 || kind >= WMCAO_K_COUNT)
         return fail(WMCAO_ERR_INVALID_ARG, "bad argument");
     std::lock_guard<std::mutex> lk(plan->mu);
     DevGuard g(plan->device);
-    double tot = 0.0;
+    double tot = 0.0, by = 0.0;
     int cnt = 0;
     for (auto& r : plan->prof.rec) {
         if (std::get<0>(r) != kind) continue;
@@ -1025,10 +1161,12 @@ int wmcao_profile_read(wmcao_plan_t plan, int kind, double* total_ms, int* launc
         float ms = 0.0f;
         WM_HIP(hipEventElapsedTime(&ms, std::get<1>(r), std::get<2>(r)));
         tot += ms;
+        by += std::get<3>(r);
         ++cnt;
     }
     *total_ms = tot;
     *launches = cnt;
+    if (bytes) *bytes = by;
     return WMCAO_OK;
 }
 

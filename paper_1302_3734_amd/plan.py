@@ -142,14 +142,16 @@ class Plan:
         _abi.check(_abi.lib().wmcao_profile_enable(self._h, int(bool(enable))), "wmcao_profile_enable")
 
     def profile_read(self):
-        """{kernel name: (total ms, launches)} since the last profile(True)."""
+        """{kernel name: (total ms, launches, algorithmic bytes)} since the last
+        profile(True)."""
         out = {}
         for k, name in enumerate(_abi.KERNELS):
             ms = C.c_double()
             n = C.c_int()
-            _abi.check(_abi.lib().wmcao_profile_read(self._h, k, C.byref(ms), C.byref(n)),
-                       "wmcao_profile_read")
-            out[name] = (ms.value, n.value)
+            by = C.c_double()
+            _abi.check(_abi.lib().wmcao_profile_read(self._h, k, C.byref(ms), C.byref(n),
+                                                     C.byref(by)), "wmcao_profile_read")
+            out[name] = (ms.value, n.value, by.value)
         return out
 
     def solve(self, slopes, coeffs=None, n_iter=10, warm_start=False, resid=None, status=None,

