@@ -94,7 +94,13 @@ typedef struct {
  *   cinv_blocks       ... unless non-NULL: host array of 3 doubles (a, b, c) per
  *                     measurement (active subaperture or cell) giving the
  *                     symmetric 2x2 block [[a, b], [b, c]] of C~^-1 (eq. (16)).
- *                     Copied at plan time. */
+ *                     Copied at plan time.
+ *   kind              0: Fried Shack-Hartmann slopes.  1: the phase itself at
+ *                     the pupil nodes that are corners of active subapertures
+ *                     (one value per node, weight a of its block): the target
+ *                     of the fitting step in one direction (Sec. 4.1, eq. (15)).
+ *                     Natural-star geometry, no aggregation, no tip/tilt
+ *                     removal. */
 typedef struct {
     int is_lgs;
     double theta_x, theta_y;
@@ -105,6 +111,7 @@ typedef struct {
     int in_precond;
     double sigma;
     const double* cinv_blocks;
+    int kind;
 } wmcao_wfs;
 
 /* Wavelet family: only Daubechies (family 0) of order 3 is built (Sec. 5.1). */
@@ -141,6 +148,9 @@ typedef struct {
 /* Build a plan on the current HIP device: validates the geometry, builds the
  * projection and slope tables, the prior D and the Jacobi diagonal J (on the
  * device, synchronously), and allocates scratch for max_batch frames.
+ * levels = 0 means no wavelet transform: the unknowns are the grid values
+ * themselves and the regulariser is alpha times the identity (used for the
+ * deformable-mirror grids of the fitting step, Sec. 4.1).
  * Errors: INVALID_ARG, SIZE (n % 2^levels != 0 or n/2^(levels-1) < 6),
  * FOOTPRINT, UNSUPPORTED (wavelet other than db3, n_sub too large), OOM, HIP.
  * On error *out is NULL. */
@@ -226,6 +236,11 @@ int wmcao_profile_enable(wmcao_plan_t plan, int enable);
  * recorded events. */
 int wmcao_profile_read(wmcao_plan_t plan, int kind, double* total_ms, int* launches,
                        double* bytes);
+
+/* out = a x + b y over n elements of the given dtype (out may alias x or y):
+ * the vector step of the pseudo-open-loop control (Sec. 4.2, Alg. 4.1). */
+int wmcao_axpby(wmcao_dtype dtype, int64_t n, double a, const void* x, double b, const void* y,
+                void* out, void* hip_stream);
 
 /* Free the plan and everything it owns (waits for the device). */
 void wmcao_plan_destroy(wmcao_plan_t plan);

@@ -11,3 +11,4 @@ from .wavelet import (db3_lowpass, haar_lowpass, highpass, analysis_1d, synthesi
 from .geometry import FootprintError
 from .system import System
 from .pcg import pcg, STATUS_OK, STATUS_CONVERGED, STATUS_BREAKDOWN
+from .control import fit, Polc

@@ -25,6 +25,14 @@ projection.
 Coefficient vectors: per layer an N x N row-major Mallat array, layers
 concatenated.  Slope vectors: per sensor, x-slopes of the active
 subapertures (or active low-order cells) in row-major order, then y-slopes.
+
+The fitting step (Sec. 4.1, eq. (15)) reuses this system: its unknowns are the
+actuator grids of the deformable mirrors (piecewise bilinear surfaces, treated
+as "layers" at the mirror altitudes, with no wavelet transform: levels = 0),
+its sensors measure the phase itself at the pupil nodes in each fitting
+direction ("kind": "phase", one value per node that is a corner of an active
+subaperture, weight 1), and its regulariser is alpha times the identity, a
+small Tikhonov term that selects the minimum-norm least-squares solution.
 """
 import math
 
@@ -57,9 +65,18 @@ class System:
                 ix0, tx = geo.bilinear_axis(xn, s, w["theta"][0] * hl, L["n"], L["spacing"])
                 jy0, ty = geo.bilinear_axis(xn, s, w["theta"][1] * hl, L["n"], L["spacing"])
                 axes.append((s, ix0, tx, jy0, ty))
+            phase = w.get("kind", "sh") == "phase"
             k = int(w["tt_aggregate"])
             cells = geo.aggregation_cells(mask, k) if k else None
-            S = len(cells) if cells is not None else int(mask.sum())
+            node_mask = None
+            if phase:
+                node_mask = np.zeros((n_sub + 1, n_sub + 1), dtype=bool)
+                for di in (0, 1):
+                    for dj in (0, 1):
+                        node_mask[di:di + n_sub, dj:dj + n_sub] |= mask
+                S = int(node_mask.sum())
+            else:
+                S = len(cells) if cells is not None else int(mask.sum())
             if cinv_blocks is not None and cinv_blocks[m] is not None:
                 blk = np.asarray(cinv_blocks[m], dtype=np.float64).reshape(S, 3)
             else:
@@ -67,12 +84,14 @@ class System:
                 blk = np.tile([sg ** -2, 0.0, sg ** -2], (S, 1))
             self.sensors.append({
                 "lgs": bool(w["lgs"]), "n_sub": n_sub, "mask": mask, "nodes": xn, "axes": axes,
-                "cells": cells, "S": S, "blocks": blk,
-                "remove_tt": bool(w["remove_tt"]), "in_precond": bool(w["in_precond"]),
+                "cells": cells, "S": S, "blocks": blk, "phase": phase, "node_mask": node_mask,
+                "nmeas": S if phase else 2 * S,
+                "remove_tt": bool(w["remove_tt"]) and not phase,
+                "in_precond": bool(w["in_precond"]),
                 "theta": w["theta"], "H": float(w["H"]),
             })
         self.slope_off = np.concatenate(
-            [[0], np.cumsum([2 * s["S"] for s in self.sensors])]).astype(int)
+            [[0], np.cumsum([s["nmeas"] for s in self.sensors])]).astype(int)
         self.n_slopes = int(self.slope_off[-1])
         self.D = self.prior_diag()
 
@@ -105,7 +124,10 @@ class System:
                 for (s, ix0, tx, jy0, ty), N in zip(sen["axes"], self.N)]
 
     def _measure(self, sen, u):
-        """Gamma_m: Fried slopes, aggregated into low-order cells if asked."""
+        """Gamma_m: Fried slopes, aggregated into low-order cells if asked; a
+        phase sensor returns the phase at its pupil nodes."""
+        if sen["phase"]:
+            return u[sen["node_mask"]]
         fine = geo.fried_slopes(u, sen["mask"])
         if sen["cells"] is None:
             return fine
@@ -120,6 +142,10 @@ class System:
         return np.array(ax + ay)
 
     def _measure_adjoint(self, sen, w):
+        if sen["phase"]:
+            v = np.zeros(sen["node_mask"].shape)
+            v[sen["node_mask"]] = w
+            return v
         mask = sen["mask"]
         if sen["cells"] is not None:
             S = sen["S"]
@@ -141,7 +167,10 @@ class System:
         return out
 
     def _cinv(self, sen, s):
-        """C~_m^-1 with one symmetric 2x2 block (a, b, c) per subaperture."""
+        """C~_m^-1 with one symmetric 2x2 block (a, b, c) per subaperture; a
+        phase sensor weights each node by a."""
+        if sen["phase"]:
+            return sen["blocks"][:, 0] * s
         S = sen["S"]
         a, b, c = sen["blocks"][:, 0], sen["blocks"][:, 1], sen["blocks"][:, 2]
         return np.concatenate([a * s[:S] + b * s[S:], b * s[:S] + c * s[S:]])
@@ -192,7 +221,10 @@ class System:
 
     # ---- prior and preconditioner --------------------------------------------
     def prior_level_values(self, l):
-        """D of layer l for scale index k = 1..J (entry k-1)."""
+        """D of layer l for scale index k = 1..J (entry k-1); without a
+        wavelet transform (levels = 0) the regulariser is the identity."""
+        if self.levels == 0:
+            return np.array([1.0])
         L = self.layers[l]
         d = float(L["spacing"])
         c_rho = 0.023 * float(L["weight"]) * float(self.cfg["r0"]) ** (-5.0 / 3.0)
@@ -207,6 +239,9 @@ class System:
         parts = []
         for l, N in enumerate(self.N):
             vals = self.prior_level_values(l)
+            if self.levels == 0:
+                parts.append(np.ones(N * N))
+                continue
             lev = wav.coefficient_level(N, self.levels)
             parts.append(vals[lev - 1].ravel())
         return np.concatenate(parts)
@@ -243,14 +278,14 @@ class System:
         J = self.alpha * self.D.copy()
         for l, N in enumerate(self.N):
             Jl = np.zeros((N, N))
-            lev = wav.coefficient_level(N, self.levels)
-            for k in range(1, self.levels + 1):
-                M = N >> (k - 1)
+            lev = wav.coefficient_level(N, max(self.levels, 1))
+            for k in range(1, max(self.levels, 1) + 1):
+                M = N >> (k - 1) if self.levels else N
                 Phi = np.zeros((N, M))
                 for x in range(M):
                     e = np.zeros(N)
                     e[x] = 1.0
-                    Phi[:, x] = wav.idwt1_multilevel(e, k, self.h)
+                    Phi[:, x] = wav.idwt1_multilevel(e, k, self.h) if self.levels else e
                 Jk = np.zeros((M, M))
                 for sen in self.sensors:
                     if not sen["in_precond"]:
@@ -264,10 +299,15 @@ class System:
                     By[np.arange(len(jy0)), jy0 + 1] += ty
                     F = Bx @ Phi
                     G = By @ Phi
+                    blk = sen["blocks"]
+                    if sen["phase"]:
+                        Am = np.zeros(sen["node_mask"].shape)
+                        Am[sen["node_mask"]] = blk[:, 0]
+                        Jk += (F ** 2).T @ Am @ (G ** 2)
+                        continue
                     dF, sF = F[1:] - F[:-1], 0.5 * (F[1:] + F[:-1])
                     dG, sG = G[1:] - G[:-1], 0.5 * (G[1:] + G[:-1])
                     mask = sen["mask"]
-                    blk = sen["blocks"]
                     if sen["cells"] is None:
                         A = np.zeros(mask.shape)
                         B = np.zeros(mask.shape)
@@ -283,6 +323,9 @@ class System:
                             syq = sF.T @ w @ dG
                             Jk += blk[q, 0] * sxq ** 2 + 2 * blk[q, 1] * sxq * syq \
                                 + blk[q, 2] * syq ** 2
+                if self.levels == 0:
+                    Jl = Jk
+                    continue
                 sel = lev[:M, :M] == k
                 Jl[:M, :M][sel] = Jk[sel]
             J[self.layer_off[l]:self.layer_off[l + 1]] += Jl.ravel()

@@ -26,7 +26,7 @@ class Wfs(C.Structure):
     _fields_ = [("is_lgs", C.c_int), ("theta_x", C.c_double), ("theta_y", C.c_double),
                 ("lgs_height_m", C.c_double), ("n_sub", C.c_int), ("tt_aggregate", C.c_int),
                 ("remove_tt", C.c_int), ("in_precond", C.c_int), ("sigma", C.c_double),
-                ("cinv_blocks", C.POINTER(C.c_double))]
+                ("cinv_blocks", C.POINTER(C.c_double)), ("kind", C.c_int)]
 
 
 class Wavelet(C.Structure):
@@ -71,6 +71,8 @@ def lib():
         L.wmcao_profile_enable.argtypes = [vp, C.c_int]
         L.wmcao_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int),
                                          C.POINTER(C.c_double)]
+        L.wmcao_axpby.argtypes = [C.c_int, C.c_int64, C.c_double, vp, C.c_double, vp, vp, vp]
+        L.wmcao_axpby.restype = C.c_int
         L.wmcao_plan_destroy.argtypes = [vp]
         L.wmcao_plan_destroy.restype = None
         L.wmcao_strerror.restype = C.c_char_p
@@ -94,5 +96,5 @@ def check(rc, where):
 EXPORTED = ("wmcao_plan", "wmcao_sizes", "wmcao_coeffs_to_layers", "wmcao_layers_to_coeffs",
             "wmcao_forward_layers", "wmcao_rhs", "wmcao_apply_A", "wmcao_precond_diag",
             "wmcao_solve", "wmcao_solve_multi", "wmcao_solve_graph", "wmcao_profile_enable",
-            "wmcao_profile_read", "wmcao_plan_destroy",
+            "wmcao_profile_read", "wmcao_axpby", "wmcao_plan_destroy",
             "wmcao_strerror", "wmcao_last_error")

@@ -8,13 +8,12 @@
 #include "wmcao.h"
 
 #define WM_MAXL 16        // layers per plan
-#define WM_MAXW 16        // sensors per plan
+#define WM_MAXW 32        // sensors per plan
 #define WM_MAXLEV 8       // wavelet levels
 #define WM_MAXCELL 16     // cells of a low-order sensor (k <= 4)
 #define WM_MAXJP 8        // plans packed into one launch
 #define WM_QMAX 16        // elements per thread of the 1024-thread kernels
 #define WM_NSUB_MAX 127   // nodes per sensor <= 128^2
-#define WM_PTK 4          // sensor nodes touching one layer pixel row (bilinear adjoint)
 
 namespace wm {
 
@@ -53,26 +52,23 @@ struct WfsInfo {
     int agg;                // 0 or k of a k x k low-order sensor
     int remove_tt;
     int in_precond;
-    int pad_;
+    int kind;               // 0: Fried Shack-Hartmann; 1: phase at the pupil nodes
     int64_t soff;           // slope offset in a frame
     int64_t node_off;       // node-field offset in a frame's node scratch
-    const int* act;         // [S_fine] packed i * n_sub + j (row-major)
+    int64_t boff;           // index of the sensor's first noise block
+    const int* act;         // [S_fine] packed i * n_sub + j (row-major); phase: node i * nn + j
     const int* cell_of;     // [S_fine] measurement (cell) index of each fine subaperture
     const int* cell_count;  // [S] fine subapertures per cell
     const double* blocks;   // [S][3] (a, b, c) of the symmetric 2x2 block of C~^-1
-    const int* maskmap;     // [n_sub * n_sub] measurement index of a fine subaperture or -1
+    const int* maskmap;     // [n_sub^2] measurement of a fine subaperture or -1 (phase: [nn^2] per node)
 };
 
 // Adjoint-projection weights of one layer pixel row (or column) for one
-// sensor: the nodes f..f+c-1 touch it with weights w[0..c-1].
+// sensor: the nodes f..f+c-1 touch it with weights pixw[woff..woff+c-1].
 struct PixTab {
-    int f, c, pad0, pad1;
-    double w[WM_PTK];
+    int f, c, woff, pad;
 };
 
-// Per (layer, tile) record of the adjoint projection: bit m of mask is set if
-// sensor m touches the tile's pixel window; its node rows are alo[m]..ahi[m].
-constexpr int TMETA = 1 + 2 * WM_MAXW;
 
 struct PlanDev {
     int L, W, levels, dtype;
@@ -93,7 +89,9 @@ struct PlanDev {
     const double* ty;
     const PixTab* pixx;     // per (sensor, layer) pixel rows: nodes touching them
     const PixTab* pixy;     // per (sensor, layer) pixel columns
-    const int* tmeta;       // TMETA ints per (layer, level-1 tile) (one per layer if k0 = 0)
+    const double* pixw;     // weights referenced by pixx and pixy
+    const int* tmeta;       // per (layer, level-1 tile), one per layer if k0 = 0: bit m set
+                            // if sensor m reaches the tile's pixel window
     int tmeta_off[WM_MAXL];
     int node_tab_off[WM_MAXW][WM_MAXL];
     int pix_tab_off[WM_MAXW][WM_MAXL];
@@ -139,7 +137,7 @@ void launch_fdwt_tile(const JobArgs& a, const Item* items, int n, int level, int
                       int out_vec, int epi, int aux_vec, int tile, hipStream_t s);
 template <class T>
 void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int in_vec,
-                        int out_vec, int epi, int aux_vec, int lds_bytes, int tcap, hipStream_t s);
+                        int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s);
 template <class T>
 void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, hipStream_t s);
 template <class T>
@@ -158,9 +156,11 @@ void launch_jacobi(const PlanDev* P, const double* protos, const int* proto_off,
                    int64_t n, double* out, hipStream_t s);
 void configure_kernels();
 template <class T>
+void launch_axpby(int64_t n, double a, const T* x, double b, const T* y, T* out, hipStream_t s);
+template <class T>
 void launch_cast_from_double(const double* in, T* out, int64_t n, hipStream_t s);
 
-constexpr int VEC_CHUNK = 2048;   // elements per block of the vector kernels
+constexpr int VEC_CHUNK = 4096;   // elements per block of the vector kernels
 constexpr int PROJ_ROWS = 8;      // sensor node rows per block of the projection
 
 }  // namespace wm

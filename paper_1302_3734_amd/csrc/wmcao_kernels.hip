@@ -17,6 +17,8 @@
 // inner products are accumulated in FP64 and reduced in a fixed order (one
 // partial per block, summed by the consumer), so a frame's result does not
 // depend on what else is in the batch.
+#include <initializer_list>
+
 #include "wmcao_internal.hpp"
 
 namespace wm {
@@ -153,62 +155,71 @@ __device__ void ana_pass(Acc* A, int ld, int M, int along_y, const Acc* hf, cons
 
 // Adjoint projection P^T of the sensors that touch a window of PR x PC pixels
 // of layer l starting at (px0, py0) (periodic indices), accumulated into G
-// (row stride ldg, FP64).  Because P_ml = B_x (kron) B_y, P^T v = B_x^T V B_y is
-// done separably per sensor: T[a][c] = sum_b wy(b, c) V[a][b] over the node rows
-// a = alo..ahi the window needs (LDS), then G[r][c] += sum_a wx(a, r) T[a][c].
-// The weights are the transpose of the bilinear samples (precomputed per
-// pixel row and column).  rec is the tile's record (sensor mask, node-row
-// ranges).  No atomics; each G entry belongs to one thread.  A window whose
-// node rows do not fit in T (tcap values) takes the direct per-pixel sum.
+// (row stride ldg, FP64).  P_ml = B_x (kron) B_y, so every pixel (r, c) takes
+// sum_a sum_b wx(a, r) wy(b, c) V[a][b] over the few nodes whose bilinear
+// stencil reaches it; the weights are the transposed bilinear samples,
+// tabulated per pixel row and column (nodes f..f+c-1, weights at woff).  A
+// thread owns one column and every rstep-th row of it, so each G entry has
+// one writer: no atomics and no barrier.  mask: bit m set if sensor m touches
+// the window.
 template <class T>
 __device__ void pt_gather_window(const PlanDev& P, const T* nodes, int l, int N, int px0, int py0,
-                                 int PR, int PC, Acc* G, int ldg, Acc* Tb, int tcap,
-                                 const int* rec) {
+                                 int PR, int PC, Acc* G, int ldg, unsigned mask) {
     const int tid = threadIdx.x, bd = blockDim.x;
-    const unsigned mask = static_cast<unsigned>(rec[0]);
-    for (int m = 0; m < P.W; ++m) {
-        if (!((mask >> m) & 1u)) continue;
-        const int alo = rec[1 + m], ahi = rec[1 + WM_MAXW + m];
-        const int po = P.pix_tab_off[m][l];
-        const PixTab* tx = P.pixx + po;
-        const PixTab* ty = P.pixy + po;
-        const int nn = P.wfs[m].nn;
-        const T* V = nodes + P.wfs[m].node_off;
-        const int NR = ahi - alo + 1;
-        if (NR * PC <= tcap) {
-            for (int e = tid; e < NR * PC; e += bd) {
-                const int la = e / PC, c = e - (e / PC) * PC;
-                const PixTab& cy = ty[(py0 + c) % N];
-                const T* vr = V + (alo + la) * nn + cy.f;
-                Acc acc = 0;
-                for (int q = 0; q < cy.c; ++q) acc += cy.w[q] * static_cast<Acc>(vr[q]);
-                Tb[e] = acc;
-            }
-            __syncthreads();
-            for (int e = tid; e < PR * PC; e += bd) {
-                const int r = e / PC, c = e - (e / PC) * PC;
-                const PixTab& rx = tx[(px0 + r) % N];
-                if (rx.c == 0) continue;
-                const Acc* tr = Tb + (rx.f - alo) * PC + c;
-                Acc acc = 0;
-                for (int q = 0; q < rx.c; ++q) acc += rx.w[q] * tr[q * PC];
-                G[r * ldg + c] += acc;
-            }
-            __syncthreads();
-        } else {
-            for (int e = tid; e < PR * PC; e += bd) {
-                const int r = e / PC, c = e - (e / PC) * PC;
-                const PixTab& rx = tx[(px0 + r) % N];
-                const PixTab& cy = ty[(py0 + c) % N];
-                if (rx.c == 0 || cy.c == 0) continue;
-                Acc acc = 0;
-                for (int qa = 0; qa < rx.c; ++qa) {
-                    const T* vr = V + (rx.f + qa) * nn + cy.f;
-                    Acc row = 0;
-                    for (int qb = 0; qb < cy.c; ++qb) row += cy.w[qb] * static_cast<Acc>(vr[qb]);
-                    acc += rx.w[qa] * row;
+    const double* pw = P.pixw;
+    int c0, r0, rstep, cstep;
+    if (PC <= bd) {
+        c0 = tid % PC;
+        r0 = tid / PC;
+        rstep = bd / PC;
+        cstep = PC;
+        if (r0 >= rstep) return;
+    } else {
+        c0 = tid;
+        r0 = 0;
+        rstep = 1;
+        cstep = bd;
+    }
+    for (int c = c0; c < PC; c += cstep) {
+        const int gy = (py0 + c) % N;
+        for (int m = 0; m < P.W; ++m) {
+            if (!((mask >> m) & 1u)) continue;
+            const int po = P.pix_tab_off[m][l];
+            const PixTab cy = P.pixy[po + gy];
+            if (cy.c == 0) continue;
+            const PixTab* tx = P.pixx + po;
+            const int nn = P.wfs[m].nn;
+            const T* Vc = nodes + P.wfs[m].node_off + cy.f;
+            const int cyc = cy.c;
+            if (cyc <= 4) {
+                Acc wy[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) wy[q] = q < cyc ? pw[cy.woff + q] : 0.0;
+                for (int r = r0; r < PR; r += rstep) {
+                    const PixTab rx = tx[(px0 + r) % N];
+                    Acc acc = 0;
+                    for (int qa = 0; qa < rx.c; ++qa) {
+                        const T* vr = Vc + static_cast<int64_t>(rx.f + qa) * nn;
+                        Acc row = 0;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (q < cyc) row += wy[q] * static_cast<Acc>(vr[q]);
+                        acc += pw[rx.woff + qa] * row;
+                    }
+                    G[r * ldg + c] += acc;
                 }
-                G[r * ldg + c] += acc;
+            } else {
+                for (int r = r0; r < PR; r += rstep) {
+                    const PixTab rx = tx[(px0 + r) % N];
+                    Acc acc = 0;
+                    for (int qa = 0; qa < rx.c; ++qa) {
+                        const T* vr = Vc + static_cast<int64_t>(rx.f + qa) * nn;
+                        Acc row = 0;
+                        for (int q = 0; q < cyc; ++q) row += pw[cy.woff + q] * static_cast<Acc>(vr[q]);
+                        acc += pw[rx.woff + qa] * row;
+                    }
+                    G[r * ldg + c] += acc;
+                }
             }
         }
     }
@@ -336,10 +347,8 @@ __global__ void __launch_bounds__(256)
 k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int src, int in_vec,
             int out_vec, int epi, int aux_vec) {
     constexpr int HT = TS / 2, PW = TS + 4;
-    constexpr int TCAP = (PW + PW / 2 + 4) * PW;   // node rows of a window at scale >= 2/3
     __shared__ Acc sA[PW][PW + 1];
     __shared__ Acc sL[PW][HT + 1], sH[PW][HT + 1];
-    __shared__ Acc sT[TCAP];
     __shared__ double red[17];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
@@ -355,8 +364,8 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
         for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) sA[e / PW][e % PW] = 0;
         __syncthreads();
         pt_gather_window<T>(P, vptr<T>(J, in_vec, it.frame), it.a, N, px0, py0, PW, PW,
-                            &sA[0][0], PW + 1, sT, TCAP,
-                            P.tmeta + (P.tmeta_off[it.a] + it.b) * TMETA);
+                            &sA[0][0], PW + 1,
+                            static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a] + it.b]));
     } else {
         const T* in;
         int ld;
@@ -435,11 +444,11 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
 // Levels k0+1..J of the analysis with the M0 x M0 block in LDS (FP64), then
 // the epilogue over every coefficient of that block.  At k0 = 0 the block is
 // the whole layer, read (SRC_PIX) or gathered through P^T (SRC_PT).  Dynamic
-// LDS: the block, then (SRC_PT at k0 = 0) tcap values of gather scratch.
+// LDS: the M0 x M0 block (FP64).
 template <class T>
 __global__ void __launch_bounds__(1024)
 k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int in_vec,
-              int out_vec, int epi, int aux_vec, int tcap) {
+              int out_vec, int epi, int aux_vec) {
     __shared__ double red[17];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
@@ -460,7 +469,7 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
         for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = 0;
         __syncthreads();
         pt_gather_window<T>(P, vptr<T>(J, in_vec, it.frame), it.a, N, 0, 0, N, N, A, N,
-                            A + M0 * M0, tcap, P.tmeta + P.tmeta_off[it.a] * TMETA);
+                            static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a]]));
     }
     __syncthreads();
     for (int lev = k0 + 1; lev <= P.levels; ++lev) {
@@ -476,7 +485,7 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
         const int64_t gi = static_cast<int64_t>(x) * N + y;
         Acc v = A[e];
         if (epi == EPI_APPLY) {
-            const int k = level_of(x, y, N, P.levels);
+            const int k = max(level_of(x, y, N, P.levels), 1);
             const Acc p = pv[gi];
             const T o = static_cast<T>(v + P.alpha * Ly.D[k - 1] * p);
             acc += p * static_cast<Acc>(o);
@@ -549,6 +558,42 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
     Acc sx[QM], sy[QM];
 #pragma unroll
     for (int r = 0; r < QM; ++r) sx[r] = sy[r] = 0;
+
+    if (w.kind == 1) {
+        // phase at the pupil nodes: measurement q is node act[q], weight a_q
+        if (mode != SM_RHS) {
+            const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
+            for (int e = tid; e < nn * nn; e += bd) U[e] = ug[e];
+            __syncthreads();
+        }
+        const T* in = vptr<T>(J, in_vec, it.frame) + w.soff;
+#pragma unroll
+        for (int r = 0; r < QM; ++r) {
+            const int q = tid + r * bd;
+            if (q < S) sx[r] = (mode != SM_RHS) ? U[w.act[q]] : static_cast<Acc>(in[q]);
+        }
+        if (mode == SM_FWD) {
+            T* out = vptr<T>(J, out_vec, it.frame) + w.soff;
+#pragma unroll
+            for (int r = 0; r < QM; ++r) {
+                const int q = tid + r * bd;
+                if (q < S) out[q] = static_cast<T>(sx[r]);
+            }
+            return;
+        }
+        __syncthreads();
+        for (int e = tid; e < nn * nn; e += bd) U[e] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < QM; ++r) {
+            const int q = tid + r * bd;
+            if (q < S) U[w.act[q]] = w.blocks[3 * q] * sx[r];
+        }
+        __syncthreads();
+        T* vout = vptr<T>(J, out_vec, it.frame) + w.node_off;
+        for (int e = tid; e < nn * nn; e += bd) vout[e] = static_cast<T>(U[e]);
+        return;
+    }
 
     if (mode != SM_RHS) {
         const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
@@ -735,6 +780,50 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
 }
 
 // ------------------------------------------------------------- PCG steps ----
+// The vector kernels move 4 consecutive elements per access (16 B for FP32,
+// 2 x 16 B for FP64) when the frame length is a multiple of 4; otherwise
+// element by element.  One block covers VEC_CHUNK elements of one frame.
+// True when the frame length is a multiple of 4 and every pointer allows
+// 16-byte accesses (a caller's vector may be any element-aligned address).
+__device__ __forceinline__ bool can_vec4(int64_t n, std::initializer_list<const void*> ptrs) {
+    uintptr_t bits = static_cast<uintptr_t>(n & 3);
+    for (const void* q : ptrs) bits |= reinterpret_cast<uintptr_t>(q) & 15;
+    return bits == 0;
+}
+
+template <class T>
+__device__ __forceinline__ void ld4(const T* p, int64_t i, int64_t n, bool vec, Acc* v) {
+    if (vec) {
+        if constexpr (sizeof(T) == 4) {
+            const float4 q = *reinterpret_cast<const float4*>(p + i);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+            const double2 q0 = *reinterpret_cast<const double2*>(p + i);
+            const double2 q1 = *reinterpret_cast<const double2*>(p + i + 2);
+            v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (i + j < n) ? static_cast<Acc>(p[i + j]) : 0.0;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void st4(T* p, int64_t i, int64_t n, bool vec, const T* v) {
+    if (vec) {
+        if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4*>(p + i) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+            *reinterpret_cast<double2*>(p + i) = make_double2(v[0], v[1]);
+            *reinterpret_cast<double2*>(p + i + 2) = make_double2(v[2], v[3]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (i + j < n) p[i + j] = v[j];
+    }
+}
+
 // r0 = b (cold: x = 0) or b - A x0 (warm, A x0 in V_Q); p0 = z0 = J^-1 r0;
 // partials of <r0, z0> and <r0, r0> into the parity-0 segments.
 template <class T>
@@ -750,25 +839,29 @@ k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
     T* r = vptr<T>(J, V_R, it.frame);
     T* p = vptr<T>(J, V_P, it.frame);
     const T* jac = reinterpret_cast<const T*>(P.jac);
+    const bool vec = can_vec4(P.n, {x, b, q, r, p, jac});
     Acc rz = 0.0, rr = 0.0;
     const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
-    for (int k = threadIdx.x; k < VEC_CHUNK; k += blockDim.x) {
+    for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
         const int64_t i = i0 + k;
-        if (i < P.n) {
-            Acc rv;
-            if (warm) {
-                rv = static_cast<Acc>(b[i]) - static_cast<Acc>(q[i]);
-            } else {
-                rv = b[i];
-                x[i] = 0;
-            }
-            const T rs = static_cast<T>(rv);
-            const Acc z = P.precond ? static_cast<Acc>(rs) / static_cast<Acc>(jac[i]) : static_cast<Acc>(rs);
-            r[i] = rs;
-            p[i] = static_cast<T>(z);
-            rz += static_cast<Acc>(rs) * z;
-            rr += static_cast<Acc>(rs) * static_cast<Acc>(rs);
+        if (i >= P.n) break;
+        Acc bv[4], qv[4], jv[4];
+        T rs[4], ps[4], zero[4] = {0, 0, 0, 0};
+        ld4(b, i, P.n, vec, bv);
+        ld4(jac, i, P.n, vec, jv);
+        if (warm) ld4(q, i, P.n, vec, qv);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            rs[j] = static_cast<T>(warm ? bv[j] - qv[j] : bv[j]);
+            const Acc rv = rs[j];
+            const Acc z = (P.precond && i + j < P.n) ? rv / jv[j] : rv;
+            ps[j] = static_cast<T>(z);
+            rz += rv * z;
+            rr += rv * rv;
         }
+        st4(r, i, P.n, vec, rs);
+        st4(p, i, P.n, vec, ps);
+        if (!warm) st4(x, i, P.n, vec, zero);
     }
     rz = block_sum(rz, red);
     rr = block_sum(rr, red);
@@ -814,18 +907,26 @@ k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
     T* r = vptr<T>(J, V_R, it.frame);
     const T* q = vptr<T>(J, V_Q, it.frame);
     const T* jac = reinterpret_cast<const T*>(P.jac);
+    const bool vec = can_vec4(P.n, {r, q, jac});
     Acc rz = 0.0, rr = 0.0;
     const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
-    for (int k = threadIdx.x; k < VEC_CHUNK; k += blockDim.x) {
+    for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
         const int64_t i = i0 + k;
-        if (i < P.n) {
-            const T rs = static_cast<T>(static_cast<Acc>(r[i]) - a * static_cast<Acc>(q[i]));
-            r[i] = rs;
-            const Acc rv = rs;
-            const Acc z = P.precond ? rv / static_cast<Acc>(jac[i]) : rv;
-            rz += rv * z;
-            rr += rv * rv;
+        if (i >= P.n) break;
+        Acc rv[4], qv[4], jv[4];
+        T rs[4];
+        ld4(r, i, P.n, vec, rv);
+        ld4(q, i, P.n, vec, qv);
+        ld4(jac, i, P.n, vec, jv);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            rs[j] = static_cast<T>(rv[j] - a * qv[j]);
+            const Acc v = rs[j];
+            const Acc z = (P.precond && i + j < P.n) ? v / jv[j] : v;
+            rz += v * z;
+            rr += v * v;
         }
+        st4(r, i, P.n, vec, rs);
     }
     rz = block_sum(rz, red);
     rr = block_sum(rr, red);
@@ -866,16 +967,25 @@ k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
     T* p = vptr<T>(J, V_P, it.frame);
     const T* r = vptr<T>(J, V_R, it.frame);
     const T* jac = reinterpret_cast<const T*>(P.jac);
+    const bool vec = can_vec4(P.n, {x, p, r, jac});
     const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
-    for (int k = threadIdx.x; k < VEC_CHUNK; k += blockDim.x) {
+    for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
         const int64_t i = i0 + k;
-        if (i < P.n) {
-            const Acc pv = p[i];
-            x[i] = static_cast<T>(static_cast<Acc>(x[i]) + a * pv);
-            const Acc rv = r[i];
-            const Acc z = P.precond ? rv / static_cast<Acc>(jac[i]) : rv;
-            p[i] = static_cast<T>(z + beta * pv);
+        if (i >= P.n) break;
+        Acc pv[4], xv[4], rv[4], jv[4];
+        T xs[4], ps[4];
+        ld4(p, i, P.n, vec, pv);
+        ld4(x, i, P.n, vec, xv);
+        ld4(r, i, P.n, vec, rv);
+        ld4(jac, i, P.n, vec, jv);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            xs[j] = static_cast<T>(xv[j] + a * pv[j]);
+            const Acc z = (P.precond && i + j < P.n) ? rv[j] / jv[j] : rv[j];
+            ps[j] = static_cast<T>(z + beta * pv[j]);
         }
+        st4(x, i, P.n, vec, xs);
+        st4(p, i, P.n, vec, ps);
     }
 }
 
@@ -892,18 +1002,26 @@ k_replace_r(const JobArgs args, const Item* __restrict__ items, int iter) {
     const T* q = vptr<T>(J, V_Q, it.frame);
     T* r = vptr<T>(J, V_R, it.frame);
     const T* jac = reinterpret_cast<const T*>(P.jac);
+    const bool vec = can_vec4(P.n, {b, q, r, jac});
     Acc rz = 0.0, rr = 0.0;
     const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
-    for (int k = threadIdx.x; k < VEC_CHUNK; k += blockDim.x) {
+    for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
         const int64_t i = i0 + k;
-        if (i < P.n) {
-            const T rs = static_cast<T>(static_cast<Acc>(b[i]) - static_cast<Acc>(q[i]));
-            r[i] = rs;
-            const Acc rv = rs;
-            const Acc z = P.precond ? rv / static_cast<Acc>(jac[i]) : rv;
-            rz += rv * z;
-            rr += rv * rv;
+        if (i >= P.n) break;
+        Acc bv[4], qv[4], jv[4];
+        T rs[4];
+        ld4(b, i, P.n, vec, bv);
+        ld4(q, i, P.n, vec, qv);
+        ld4(jac, i, P.n, vec, jv);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            rs[j] = static_cast<T>(bv[j] - qv[j]);
+            const Acc v = rs[j];
+            const Acc z = (P.precond && i + j < P.n) ? v / jv[j] : v;
+            rz += v * z;
+            rr += v * v;
         }
+        st4(r, i, P.n, vec, rs);
     }
     rz = block_sum(rz, red);
     rr = block_sum(rr, red);
@@ -937,14 +1055,16 @@ k_jacobi(const PlanDev* __restrict__ Pp, JacArgs ja, int64_t n, double* __restri
     const int N = Ly.N;
     const int64_t loc = lam - Ly.coff;
     const int x = static_cast<int>(loc / N), y = static_cast<int>(loc % N);
+    // level k (0 without a wavelet transform: the basis is the unit pixel)
     const int k = level_of(x, y, N, P.levels);
+    const int kk = k > 0 ? k : 1;
     const int Hk = N >> k;
     const int txy = x >= Hk, tyy = y >= Hk;
     const int ax = txy ? x - Hk : x, ay = tyy ? y - Hk : y;
-    const double* fx = ja.protos + ja.proto_off[(l * WM_MAXLEV + (k - 1)) * 2 + txy];
-    const double* fy = ja.protos + ja.proto_off[(l * WM_MAXLEV + (k - 1)) * 2 + tyy];
+    const double* fx = ja.protos + ja.proto_off[(l * WM_MAXLEV + (kk - 1)) * 2 + txy];
+    const double* fy = ja.protos + ja.proto_off[(l * WM_MAXLEV + (kk - 1)) * 2 + tyy];
     const int shx = ax << k, shy = ay << k;
-    double acc = P.alpha * Ly.D[k - 1];
+    double acc = P.alpha * Ly.D[kk - 1];
     for (int m = 0; m < P.W; ++m) {
         const WfsInfo& w = P.wfs[m];
         if (!w.in_precond) continue;
@@ -968,6 +1088,25 @@ k_jacobi(const PlanDev* __restrict__ Pp, JacArgs ja, int64_t n, double* __restri
             if (p1 == N) p1 = 0;
             return (1.0 - t) * fy[p0] + t * fy[p1];
         };
+        if (w.kind == 1) {   // phase sensor: sum over active nodes of a (F_i G_j)^2
+            const int nn = ns + 1;
+            int ilo = nn, ihi = -1, jlo = nn, jhi = -1;
+            for (int i = 0; i < nn; ++i)
+                if (Fv(i) != 0.0) { if (i < ilo) ilo = i; ihi = i; }
+            for (int j = 0; j < nn; ++j)
+                if (Gv(j) != 0.0) { if (j < jlo) jlo = j; jhi = j; }
+            const double* B = ja.blocksd + w.boff * 3;
+            for (int i = ilo; i <= ihi; ++i) {
+                const double F = Fv(i);
+                for (int j = jlo; j <= jhi; ++j) {
+                    const int q = w.maskmap[i * nn + j];
+                    if (q < 0) continue;
+                    const double v = F * Gv(j);
+                    acc += B[3 * q] * v * v;
+                }
+            }
+            continue;
+        }
         int ilo = ns, ihi = -1, jlo = ns, jhi = -1;
         double prev = Fv(0);
         for (int i = 0; i < ns; ++i) {
@@ -984,7 +1123,7 @@ k_jacobi(const PlanDev* __restrict__ Pp, JacArgs ja, int64_t n, double* __restri
         }
         if (jhi < 0) continue;
         // blocks are packed per sensor in slope order: 3 values per measurement
-        const double* B = ja.blocksd + (w.soff / 2) * 3;
+        const double* B = ja.blocksd + w.boff * 3;
         if (!w.agg) {
             for (int i = ilo; i <= ihi; ++i) {
                 const double F0 = Fv(i), F1 = Fv(i + 1);
@@ -1021,6 +1160,21 @@ k_jacobi(const PlanDev* __restrict__ Pp, JacArgs ja, int64_t n, double* __restri
         }
     }
     out[lam] = acc;
+}
+
+// out = a x + b y, elementwise (out may alias x or y).
+template <class T>
+__global__ void __launch_bounds__(256)
+k_axpby(int64_t n, double a, const T* x, double b, const T* y, T* out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = static_cast<T>(a * static_cast<Acc>(x[i]) + b * static_cast<Acc>(y[i]));
+}
+
+template <class T>
+void launch_axpby(int64_t n, double a, const T* x, double b, const T* y, T* out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_axpby<T>, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
+                       n, a, x, b, y, out);
 }
 
 template <class T>
@@ -1064,10 +1218,10 @@ void launch_fdwt_tile(const JobArgs& a, const Item* items, int n, int level, int
 
 template <class T>
 void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int in_vec,
-                        int out_vec, int epi, int aux_vec, int lds_bytes, int tcap, hipStream_t s) {
+                        int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fdwt_coarse<T>, dim3(n), dim3(1024), lds_bytes, s, a, items, src, in_vec,
-                       out_vec, epi, aux_vec, tcap);
+                       out_vec, epi, aux_vec);
 }
 
 template <class T>
@@ -1154,14 +1308,15 @@ void configure_kernels() {
     template void launch_idwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, hipStream_t); \
     template void launch_idwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
     template void launch_fdwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, int, hipStream_t); \
-    template void launch_fdwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, int, hipStream_t); \
+    template void launch_fdwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, hipStream_t); \
     template void launch_sensor<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
     template void launch_project<T>(const JobArgs&, const Item*, int, int, hipStream_t);       \
     template void launch_init<T>(const JobArgs&, const Item*, int, int, hipStream_t);          \
     template void launch_update_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \
     template void launch_update_p<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \
     template void launch_replace_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);     \
-    template void launch_cast_from_double<T>(const double*, T*, int64_t, hipStream_t);
+    template void launch_cast_from_double<T>(const double*, T*, int64_t, hipStream_t);         \
+    template void launch_axpby<T>(int64_t, double, const T*, double, const T*, T*, hipStream_t);
 
 WM_INSTANTIATE(float)
 WM_INSTANTIATE(double)

@@ -60,7 +60,6 @@ struct Sched {
     int maxk0 = 0;
     int lds_idwt = 0;      // dynamic LDS of the whole-band synthesis
     int lds_fdwt = 0;      // dynamic LDS of the whole-band analysis (+ gather tables)
-    int tcap = 0;          // gather scratch values of the whole-band analysis
     int lds_sensor = 0;
     int tile = 32;
     // algorithmic bytes one launch of each stage moves (all frames of the job)
@@ -245,18 +244,7 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     std::vector<Item> coarse, sensor, vec, proj;
     std::vector<Item> tiled[WM_MAXLEV + 1];
-    int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0, tcap = 1 << 30;
-    // gather scratch of whole layers analysed in one block (k0 = 0)
-    for (const auto& j : jobs)
-        for (int l = 0; l < j.plan->L; ++l) {
-            const LayerInfo& Ly = j.plan->host.layer[l];
-            if (Ly.k0 != 0) continue;
-            const int N = Ly.N;
-            const int base = N * N * 8;
-            const int want = (N + N / 2 + 4) * N;
-            tcap = std::min(tcap, std::min(want, std::max(0, (159 * 1024 - base) / 8)));
-        }
-    if (tcap == (1 << 30)) tcap = 0;
+    int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0;
     for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
         const wmcao_plan_s* P = jobs[jp].plan;
         for (int f = 0; f < jobs[jp].count; ++f) {
@@ -276,9 +264,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                 const LayerInfo& Ly = P->host.layer[l];
                 const int N = Ly.N, M0 = N >> Ly.k0;
                 lds_i = std::max(lds_i, M0 * M0 * 8);
-                int need = M0 * M0 * 8;
-                if (Ly.k0 == 0) need += tcap * 8;
-                lds_f = std::max(lds_f, need);
+                lds_f = std::max(lds_f, M0 * M0 * 8);
             }
             for (int m = 0; m < P->W; ++m) {
                 sensor.push_back(Item{jp, f, m, 0, 0, 0, 0, 0});
@@ -355,7 +341,6 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     S->maxk0 = maxk0;
     S->lds_idwt = lds_i;
     S->lds_fdwt = lds_f;
-    S->tcap = tcap;
     S->lds_sensor = lds_s;
     S->tile = tile;
     return WMCAO_OK;
@@ -425,7 +410,7 @@ void run_fdwt(const JobArgs& a, const Sched& S, int src, int in_vec, int out_vec
         });
     timed(WMCAO_K_FDWT_COARSE, S.b_fdwt_coarse[epi == EPI_APPLY], s, [&] {
         launch_fdwt_coarse<T>(a, S.coarse, S.n_coarse, src, in_vec, out_vec, epi, aux_vec,
-                              S.lds_fdwt, S.tcap, s);
+                              S.lds_fdwt, s);
     });
 }
 
@@ -541,7 +526,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     if (n_wfs < 1 || n_wfs > WM_MAXW) return fail(WMCAO_ERR_INVALID_ARG, "n_wfs out of range");
     if (wavelet.family != 0 || wavelet.order != 3)
         return fail(WMCAO_ERR_UNSUPPORTED, "only Daubechies order 3 is built");
-    if (levels < 1 || levels > WM_MAXLEV) return fail(WMCAO_ERR_SIZE, "levels out of range");
+    if (levels < 0 || levels > WM_MAXLEV) return fail(WMCAO_ERR_SIZE, "levels out of range");
     if (opts->dtype != WMCAO_F32 && opts->dtype != WMCAO_F64)
         return fail(WMCAO_ERR_INVALID_ARG, "dtype");
     if (opts->max_batch < 1) return fail(WMCAO_ERR_INVALID_ARG, "max_batch < 1");
@@ -559,6 +544,9 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         if (w.n_sub < 1 || w.n_sub > WM_NSUB_MAX) return fail(WMCAO_ERR_UNSUPPORTED, "n_sub out of range");
         if (w.tt_aggregate < 0 || w.tt_aggregate > 4 || (w.tt_aggregate && w.n_sub % w.tt_aggregate))
             return fail(WMCAO_ERR_INVALID_ARG, "tt_aggregate must be 0..4 and divide n_sub");
+        if (w.kind != 0 && w.kind != 1) return fail(WMCAO_ERR_INVALID_ARG, "kind must be 0 or 1");
+        if (w.kind == 1 && (w.tt_aggregate || w.is_lgs))
+            return fail(WMCAO_ERR_INVALID_ARG, "phase sensors are natural-star and not aggregated");
         if (!w.cinv_blocks && !(w.sigma > 0.0)) return fail(WMCAO_ERR_INVALID_ARG, "sigma must be > 0");
         if (w.is_lgs) {
             if (seen_ngs) return fail(WMCAO_ERR_INVALID_ARG, "laser guide stars must come first");
@@ -569,8 +557,9 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     }
     for (int l = 0; l < n_layers; ++l) {
         const int N = layers[l].n;
-        if (N < 6 || N % (1 << levels) != 0 || (N >> (levels - 1)) < 6)
+        if (levels > 0 && (N < 6 || N % (1 << levels) != 0 || (N >> (levels - 1)) < 6))
             return fail(WMCAO_ERR_SIZE, "layer size must be divisible by 2^levels and N/2^(levels-1) >= 6");
+        if (N < 2) return fail(WMCAO_ERR_SIZE, "layer size must be at least 2");
         if (!(layers[l].spacing_m > 0.0) || !(layers[l].cn2_weight > 0.0))
             return fail(WMCAO_ERR_INVALID_ARG, "layer spacing and weight must be positive");
         for (int m = 0; m < n_wfs; ++m)
@@ -625,9 +614,11 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             Ly.ll_off[k] = lloff;
             lloff += static_cast<int64_t>(N >> k) * (N >> k);
         }
-        // prior (eq. (13)): D = d^2 (L0^-11/3 + nu_k^11/3) / c_rho, nu_k = 2^-k / d
+        // prior (eq. (13)): D = d^2 (L0^-11/3 + nu_k^11/3) / c_rho, nu_k = 2^-k / d;
+        // without a wavelet transform (levels = 0) the regulariser is the identity
         const double d = layers[l].spacing_m;
         const double c_rho = 0.023 * layers[l].cn2_weight * std::pow(opts->r0_m, -5.0 / 3.0);
+        Ly.D[0] = 1.0;
         for (int k = 1; k <= levels; ++k) {
             const double nu = std::ldexp(1.0, -k) / d;
             Ly.D[k - 1] = d * d * (std::pow(opts->L0_m, -11.0 / 3.0) + std::pow(nu, 11.0 / 3.0)) / c_rho;
@@ -644,6 +635,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     // ---- sensors --------------------------------------------------------
     std::vector<int> ix0, jy0;
     std::vector<PixTab> pixx, pixy;
+    std::vector<double> pixw;
     std::vector<double> txd, tyd, blocksd;
     int64_t soff = 0, noff = 0;
     p->slope_off.assign(1, 0);
@@ -658,7 +650,8 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         I.n_sub = ns;
         I.nn = nn;
         I.agg = w.tt_aggregate;
-        I.remove_tt = w.remove_tt < 0 ? (w.is_lgs ? 1 : 0) : (w.remove_tt ? 1 : 0);
+        I.kind = w.kind;
+        I.remove_tt = w.kind == 1 ? 0 : w.remove_tt < 0 ? (w.is_lgs ? 1 : 0) : (w.remove_tt ? 1 : 0);
         I.in_precond = w.in_precond < 0 ? ((ns > 2 && w.tt_aggregate == 0) ? 1 : 0) : (w.in_precond ? 1 : 0);
         // pupil: centre of subaperture (i, j) in the closed annulus
         const double ro2 = 0.25 * Dp * Dp, ri2 = 0.25 * Dp * Dp * pupil->obstruction_ratio * pupil->obstruction_ratio;
@@ -676,7 +669,25 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             return fail(WMCAO_ERR_UNSUPPORTED, "sensor too large");
         if (static_cast<int64_t>(nn) * nn * 8 > 150 * 1024)
             return fail(WMCAO_ERR_UNSUPPORTED, "sensor node field exceeds LDS");
-        if (I.agg) {
+        if (I.kind == 1) {
+            // phase sensor: nodes that are corners of active subapertures
+            std::vector<char> on(nn * nn, 0);
+            for (int q = 0; q < I.S_fine; ++q) {
+                const int i = X.act[q] / ns, j = X.act[q] % ns;
+                on[i * nn + j] = on[(i + 1) * nn + j] = on[i * nn + j + 1] = on[(i + 1) * nn + j + 1] = 1;
+            }
+            X.act.clear();
+            X.maskmap.assign(nn * nn, -1);
+            for (int e = 0; e < nn * nn; ++e)
+                if (on[e]) {
+                    X.maskmap[e] = static_cast<int>(X.act.size());
+                    X.act.push_back(e);
+                }
+            X.cell_of.assign(1, 0);
+            X.cell_count.assign(1, 0);
+            I.S = static_cast<int>(X.act.size());
+            I.S_fine = I.S;
+        } else if (I.agg) {
             const int k = I.agg, b = ns / k;
             std::vector<int> cell_id(k * k, -1);
             for (int q = 0; q < I.S_fine; ++q) {
@@ -716,7 +727,8 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             }
         }
         I.soff = soff;
-        soff += 2 * I.S;
+        I.boff = static_cast<int64_t>(blocksd.size() / 3) - I.S;
+        soff += (I.kind == 1 ? 1 : 2) * I.S;
         p->slope_off.push_back(soff);
         I.node_off = noff;
         noff += static_cast<int64_t>(nn) * nn;
@@ -755,15 +767,14 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
                 }
                 for (int px = 0; px < N; ++px) {
                     const int cnt = first[px] < 0 ? 0 : last[px] - first[px] + 1;
-                    if (cnt > WM_PTK)
-                        return fail(WMCAO_ERR_UNSUPPORTED, "sensor nodes denser than 3 per layer pixel");
                     PixTab t{};
                     t.f = first[px] < 0 ? 0 : first[px];
                     t.c = cnt;
+                    t.woff = static_cast<int>(pixw.size());
                     for (int q = 0; q < cnt; ++q) {   // transpose of the bilinear weights
                         const int a = t.f + q;
                         const double tt = tv[base + a];
-                        t.w[q] = (i0v[base + a] == px) ? 1.0 - tt : tt;
+                        pixw.push_back((i0v[base + a] == px) ? 1.0 - tt : tt);
                     }
                     pv.push_back(t);
                 }
@@ -804,13 +815,14 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     UP(jy0, H.jy0);
     UP(pixx, H.pixx);
     UP(pixy, H.pixy);
+    UP(pixw, H.pixw);
     {
         // adjoint-projection records per (layer, level-1 tile), or per layer at k0 = 0
         std::vector<int> meta;
         const int HT = p->tile / 2, PW = p->tile + 4;
         for (int l = 0; l < n_layers; ++l) {
             const int N = H.layer[l].N;
-            H.tmeta_off[l] = static_cast<int>(meta.size() / TMETA);
+            H.tmeta_off[l] = static_cast<int>(meta.size());
             const int nt = H.layer[l].k0 >= 1 ? ceil_div(N / 2, HT) : 1;
             for (int t = 0; t < nt * nt; ++t) {
                 int x0 = 0, y0 = 0, W0 = N;
@@ -819,26 +831,17 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
                     y0 = 2 * (t / nt) * HT;
                     W0 = PW;
                 }
-                std::vector<int> rec(TMETA, 0);
+                unsigned mask = 0;
                 for (int m = 0; m < n_wfs; ++m) {
                     const int po = H.pix_tab_off[m][l];
-                    int alo = 1 << 30, ahi = -1;
-                    bool anyc = false;
+                    bool anyr = false, anyc = false;
                     for (int k = 0; k < W0; ++k) {
-                        const PixTab& rx = pixx[po + (x0 + k) % N];
-                        if (rx.c > 0) {
-                            alo = std::min(alo, rx.f);
-                            ahi = std::max(ahi, rx.f + rx.c - 1);
-                        }
+                        anyr = anyr || pixx[po + (x0 + k) % N].c > 0;
                         anyc = anyc || pixy[po + (y0 + k) % N].c > 0;
                     }
-                    if (ahi >= alo && anyc) {
-                        rec[0] |= 1 << m;
-                        rec[1 + m] = alo;
-                        rec[1 + WM_MAXW + m] = ahi;
-                    }
+                    if (anyr && anyc) mask |= 1u << m;
                 }
-                meta.insert(meta.end(), rec.begin(), rec.end());
+                meta.push_back(static_cast<int>(mask));
             }
         }
         UP(meta, H.tmeta);
@@ -852,7 +855,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     // geometry weights and noise blocks stay FP64 for both dtypes (small tables)
     H.tx = txd_dev;
     H.ty = tyd_dev;
-    for (int m = 0; m < n_wfs; ++m) H.wfs[m].blocks = blk_dev_d + (H.wfs[m].soff / 2) * 3;
+    for (int m = 0; m < n_wfs; ++m) H.wfs[m].blocks = blk_dev_d + H.wfs[m].boff * 3;
 
     // ---- slots and scratch ------------------------------------------------
     {
@@ -903,10 +906,12 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         std::vector<double> protos;
         std::vector<int> poff(WM_MAXL * WM_MAXLEV * 2, 0);
         for (int l = 0; l < n_layers; ++l)
-            for (int k = 1; k <= levels; ++k)
+            for (int k = 1; k <= std::max(levels, 1); ++k)
                 for (int t = 0; t < 2; ++t) {
                     poff[(l * WM_MAXLEV + (k - 1)) * 2 + t] = static_cast<int>(protos.size());
-                    auto v = prototype(H.h, H.g, H.layer[l].N, k, t);
+                    std::vector<double> v(H.layer[l].N, 0.0);
+                    if (levels > 0) v = prototype(H.h, H.g, H.layer[l].N, k, t);
+                    else v[0] = 1.0;   // no transform: the basis is the unit pixel
                     protos.insert(protos.end(), v.begin(), v.end());
                 }
         const double* pr = nullptr;
@@ -1168,6 +1173,21 @@ int wmcao_profile_read(wmcao_plan_t plan, int kind, double* total_ms, int* launc
     *launches = cnt;
     if (bytes) *bytes = by;
     return WMCAO_OK;
+}
+
+int wmcao_axpby(wmcao_dtype dtype, int64_t n, double a, const void* x, double b, const void* y,
+                void* out, void* hip_stream) {
+    if (n < 0 || (n > 0 && (!x || !y || !out))) return fail(WMCAO_ERR_INVALID_ARG, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (dtype == WMCAO_F32)
+        launch_axpby<float>(n, a, static_cast<const float*>(x), b, static_cast<const float*>(y),
+                            static_cast<float*>(out), s);
+    else if (dtype == WMCAO_F64)
+        launch_axpby<double>(n, a, static_cast<const double*>(x), b, static_cast<const double*>(y),
+                             static_cast<double*>(out), s);
+    else
+        return fail(WMCAO_ERR_INVALID_ARG, "dtype");
+    return check_launch();
 }
 
 void wmcao_plan_destroy(wmcao_plan_t plan) {

@@ -56,7 +56,8 @@ class Plan:
             Ws[m] = _abi.Wfs(int(w["lgs"]), w["theta"][0], w["theta"][1], w.get("H", 90e3),
                              int(w["n_sub"]), int(w.get("tt_aggregate", 0)),
                              int(w.get("remove_tt", -1)), int(w.get("in_precond", -1)),
-                             float(sigmas[m]) if sigmas is not None else 0.0, blk)
+                             float(sigmas[m]) if sigmas is not None else 0.0, blk,
+                             1 if w.get("kind", "sh") == "phase" else 0)
         pupil = _abi.Pupil(cfg["diameter"], cfg["obstruction"])
         opts = _abi.Options(cfg["alpha"], cfg["r0"], cfg["L0"], code, self.max_batch,
                             int(resid_replace_every), 1 if precond else 0, int(tile),

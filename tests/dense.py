@@ -109,16 +109,28 @@ def assemble(cfg, sigmas, cinv_blocks=None, precond_only=False):
     """Returns (A, list of per-sensor (A~_m, N_m)) with A the full matrix."""
     sysm = O.System(cfg, sigmas, cinv_blocks)
     h = O.db3_lowpass()
-    Wl = [wavelet_matrix(L["n"], cfg["levels"], h) for L in cfg["layers"]]
+    Wl = [wavelet_matrix(L["n"], cfg["levels"], h) if cfg["levels"] else np.eye(L["n"] ** 2)
+          for L in cfg["layers"]]
     W = sp.block_diag(Wl).toarray()
     parts = []
     A = np.zeros((sysm.n, sysm.n))
     for m, w in enumerate(cfg["wfs"]):
         sen = sysm.sensors[m]
         mask = sen["mask"]
-        G, act = fried_matrix(mask)
-        if w["tt_aggregate"]:
-            G = aggregation_matrix(mask, act, w["tt_aggregate"]) @ G
+        if w.get("kind", "sh") == "phase":
+            n = mask.shape[0]
+            on = np.zeros((n + 1, n + 1), bool)
+            for i in range(n):
+                for j in range(n):
+                    if mask[i, j]:
+                        on[i:i + 2, j:j + 2] = True
+            idx = np.flatnonzero(on.ravel())
+            G = np.zeros((len(idx), (n + 1) ** 2))
+            G[np.arange(len(idx)), idx] = 1.0
+        else:
+            G, act = fried_matrix(mask)
+            if w["tt_aggregate"]:
+                G = aggregation_matrix(mask, act, w["tt_aggregate"]) @ G
         cols = []
         for L in cfg["layers"]:
             s = 1.0 - L["altitude"] / w["H"] if w["lgs"] else 1.0
@@ -129,7 +141,7 @@ def assemble(cfg, sigmas, cinv_blocks=None, precond_only=False):
             cols.append(np.kron(Bx, By))
         P = np.hstack(cols)
         At = G @ P @ W.T
-        Cinv = block_matrix(sen["blocks"])
+        Cinv = block_matrix(sen["blocks"]) if not sen["phase"] else np.diag(sen["blocks"][:, 0])
         if precond_only:
             Nm = Cinv
             if not w["in_precond"]:

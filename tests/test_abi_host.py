@@ -34,7 +34,7 @@ def test_strerror_and_last_error():
 
 def _args(n=64, levels=4, order=3, n_sub=16, agg=0, dtype=0, tile=0, sigma=0.1):
     Ls = (_abi.Layer * 1)(_abi.Layer(0.0, 1.0, 0.5, n))
-    Ws = (_abi.Wfs * 1)(_abi.Wfs(0, 0.0, 0.0, 90e3, n_sub, agg, -1, -1, sigma, None))
+    Ws = (_abi.Wfs * 1)(_abi.Wfs(0, 0.0, 0.0, 90e3, n_sub, agg, -1, -1, sigma, None, 0))
     pupil = _abi.Pupil(8.0, 0.0)
     opts = _abi.Options(1.0, 0.15, 25.0, dtype, 1, 0, 1, tile, 0)
     return pupil, Ls, Ws, _abi.Wavelet(0, order), levels, opts
