@@ -204,6 +204,16 @@ int wmcao_solve_multi(const wmcao_plan_t* plans, const void* const* slopes, void
                       const int* counts, int n_plans, int n_iter, int warm_start,
                       void* hip_stream);
 
+/* wmcao_solve_multi captured into a HIP graph and replayed.  The library keeps
+ * up to 64 captures, keyed by every argument (plans, buffers,
+ * counts, n_iter, warm_start, stream); a call with a known key replays without
+ * re-recording.  Buffers must stay valid while the plans live; destroying a
+ * plan drops the captures that use it.  hip_stream must not be the default
+ * stream. */
+int wmcao_solve_multi_graph(const wmcao_plan_t* plans, const void* const* slopes,
+                            void* const* coeffs, const int* counts, int n_plans, int n_iter,
+                            int warm_start, void* hip_stream);
+
 /* Capture the launches of wmcao_solve with these arguments into a HIP graph
  * owned by the plan, replacing any earlier capture, and replay it: later
  * wmcao_solve_graph calls with the same arguments replay without re-recording.
@@ -215,14 +225,15 @@ int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int b
 #define WMCAO_K_IDWT_COARSE 0   /* W^-1, low-pass block in LDS            */
 #define WMCAO_K_IDWT_TILE 1     /* W^-1, one tiled level                  */
 #define WMCAO_K_SENSOR 2        /* Gamma, C^-1, (I-T), Gamma^T            */
-#define WMCAO_K_FDWT_TILE 3     /* P^T + W one tiled level + alpha D, dot */
+#define WMCAO_K_FDWT_TILE 3     /* W one tiled level (+ sum of the P^T footprint images at level 1) + alpha D, dot */
 #define WMCAO_K_FDWT_COARSE 4   /* W coarse levels + alpha D, dot         */
 #define WMCAO_K_INIT 5          /* r0, p0                                 */
 #define WMCAO_K_UPDATE_R 6      /* r -= a q, <r, J^-1 r>                  */
 #define WMCAO_K_UPDATE_P 7      /* x += a p, p = J^-1 r + beta p          */
 #define WMCAO_K_REPLACE_R 8     /* r = b - A x                            */
 #define WMCAO_K_PROJECT 9       /* P: layers -> sensor node fields        */
-#define WMCAO_K_COUNT 10
+#define WMCAO_K_ADJOINT 10      /* P^T: node fields -> footprint images per sensor and layer */
+#define WMCAO_K_COUNT 11
 
 /* Per-kernel timing of later wmcao_solve / wmcao_apply_A calls on this plan:
  * with enable != 0 every launch is bracketed by HIP events on the launch

@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(HERE, "libwmcao.so")
 WMCAO_F32, WMCAO_F64 = 0, 1
 WMCAO_FRAME_OK, WMCAO_FRAME_CONVERGED, WMCAO_FRAME_BREAKDOWN = 0, 1, -7
 KERNELS = ["idwt_coarse", "idwt_tile", "sensor", "fdwt_tile", "fdwt_coarse", "init", "update_r",
-           "update_p", "replace_r", "project"]
+           "update_p", "replace_r", "project", "adjoint"]
 ERRORS = {-1: "INVALID_ARG", -2: "SIZE", -3: "FOOTPRINT", -4: "UNSUPPORTED", -5: "OOM",
           -6: "HIP", -7: "BREAKDOWN"}
 
@@ -66,8 +66,9 @@ def lib():
         L.wmcao_precond_diag.argtypes = [vp, vp, vp]
         L.wmcao_solve.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
         L.wmcao_solve_graph.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
-        L.wmcao_solve_multi.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
-                                        C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int, vp]
+        for name in ("wmcao_solve_multi", "wmcao_solve_multi_graph"):
+            getattr(L, name).argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                         C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int, vp]
         L.wmcao_profile_enable.argtypes = [vp, C.c_int]
         L.wmcao_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int),
                                          C.POINTER(C.c_double)]
@@ -81,7 +82,8 @@ def lib():
         for name in ("wmcao_plan", "wmcao_sizes", "wmcao_coeffs_to_layers",
                      "wmcao_layers_to_coeffs", "wmcao_forward_layers", "wmcao_rhs",
                      "wmcao_apply_A", "wmcao_precond_diag", "wmcao_solve", "wmcao_solve_graph",
-                     "wmcao_solve_multi", "wmcao_profile_enable", "wmcao_profile_read"):
+                     "wmcao_solve_multi", "wmcao_solve_multi_graph", "wmcao_profile_enable",
+                     "wmcao_profile_read"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -95,6 +97,7 @@ def check(rc, where):
 
 EXPORTED = ("wmcao_plan", "wmcao_sizes", "wmcao_coeffs_to_layers", "wmcao_layers_to_coeffs",
             "wmcao_forward_layers", "wmcao_rhs", "wmcao_apply_A", "wmcao_precond_diag",
-            "wmcao_solve", "wmcao_solve_multi", "wmcao_solve_graph", "wmcao_profile_enable",
+            "wmcao_solve", "wmcao_solve_multi", "wmcao_solve_multi_graph", "wmcao_solve_graph",
+            "wmcao_profile_enable",
             "wmcao_profile_read", "wmcao_axpby", "wmcao_plan_destroy",
             "wmcao_strerror", "wmcao_last_error")

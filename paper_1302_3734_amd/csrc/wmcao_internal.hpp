@@ -31,6 +31,8 @@ enum Vec : int {
     V_IN,         // caller's generic input
     V_OUT,        // caller's generic output
     V_U,          // sensor node fields of the projection, FP64 (scratch)
+    V_FP,         // per (sensor, layer) adjoint-projection footprint images (scratch)
+    V_SPART,      // per (sensor, node band) slope sums for tip/tilt and cells, FP64 (scratch)
     NV
 };
 
@@ -61,14 +63,10 @@ struct WfsInfo {
     const int* cell_count;  // [S] fine subapertures per cell
     const double* blocks;   // [S][3] (a, b, c) of the symmetric 2x2 block of C~^-1
     const int* maskmap;     // [n_sub^2] measurement of a fine subaperture or -1 (phase: [nn^2] per node)
+    int sp_off;             // first slope-sum record of the sensor in a V_SPART frame
+    int pad_;
+    double bsum[3];         // sums over the measurements of the noise-block entries a, b, c
 };
-
-// Adjoint-projection weights of one layer pixel row (or column) for one
-// sensor: the nodes f..f+c-1 touch it with weights pixw[woff..woff+c-1].
-struct PixTab {
-    int f, c, woff, pad;
-};
-
 
 struct PlanDev {
     int L, W, levels, dtype;
@@ -87,14 +85,25 @@ struct PlanDev {
     const int* jy0;
     const double* tx;       // bilinear weight of the right/upper pixel per node
     const double* ty;
-    const PixTab* pixx;     // per (sensor, layer) pixel rows: nodes touching them
-    const PixTab* pixy;     // per (sensor, layer) pixel columns
-    const double* pixw;     // weights referenced by pixx and pixy
+    // node i of sensor m sits at grid coordinate u = pa * i + pb[axis] on layer l
+    // (Sec. 2.1 with the cone factor): the forward and adjoint projections
+    // evaluate their bilinear weights from it.
+    double pa[WM_MAXW][WM_MAXL];
+    double pia[WM_MAXW][WM_MAXL];       // 1 / pa
+    double pb[2][WM_MAXW][WM_MAXL];
     const int* tmeta;       // per (layer, level-1 tile), one per layer if k0 = 0: bit m set
                             // if sensor m reaches the tile's pixel window
+    // adjoint-projection footprint of sensor m on layer l: pixel rows
+    // fp_x0 .. fp_x0 + fp_h - 1, columns fp_y0 .. fp_y0 + fp_w - 1; its image
+    // starts at fp_off in a V_FP frame; fp_rc + 2 * fp_tab holds (first node,
+    // node count) per footprint row, then per footprint column; fp_br rows per
+    // work item.
+    int fp_x0[WM_MAXW][WM_MAXL], fp_y0[WM_MAXW][WM_MAXL];
+    int fp_h[WM_MAXW][WM_MAXL], fp_w[WM_MAXW][WM_MAXL];
+    int fp_off[WM_MAXW][WM_MAXL], fp_tab[WM_MAXW][WM_MAXL], fp_br[WM_MAXW][WM_MAXL];
+    const int* fp_rc;
     int tmeta_off[WM_MAXL];
     int node_tab_off[WM_MAXW][WM_MAXL];
-    int pix_tab_off[WM_MAXW][WM_MAXL];
     const void* jac;        // [n] Jacobi diagonal, plan dtype
 };
 
@@ -139,7 +148,12 @@ template <class T>
 void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int in_vec,
                         int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s);
 template <class T>
-void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, hipStream_t s);
+void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, hipStream_t s);
+template <class T>
+void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, hipStream_t s);
+template <class T>
+void launch_adjoint(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
+                    int lds_bytes, hipStream_t s);
 template <class T>
 void launch_sensor(const JobArgs& a, const Item* items, int n, int mode, int in_vec, int out_vec,
                    int lds_bytes, hipStream_t s);
@@ -162,5 +176,8 @@ void launch_cast_from_double(const double* in, T* out, int64_t n, hipStream_t s)
 
 constexpr int VEC_CHUNK = 4096;   // elements per block of the vector kernels
 constexpr int PROJ_ROWS = 8;      // sensor node rows per block of the projection
+constexpr int SP_K = 2 * WM_MAXCELL;   // doubles per slope-sum record
+constexpr int ADJ_BAND = 32;      // footprint rows per adjoint work item (at most)
+constexpr int ADJ_LDS = 48 * 1024;   // LDS of the adjoint's row-pass buffer (at most)
 
 }  // namespace wm

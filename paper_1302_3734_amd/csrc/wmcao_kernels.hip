@@ -3,10 +3,15 @@
 //
 //   W^-1  : k_idwt_coarse (whole low-pass band in LDS) + k_idwt_tile (one
 //           level per launch, LDS tiles with a 2-coefficient halo)
-//   P, Gamma, C^-1, (I-T), Gamma^T : k_sensor (one block per sensor and frame,
-//           node field in LDS, deterministic block reductions for tip/tilt)
-//   P^T + W + alpha D + <p,Ap> : k_fdwt_tile (P^T gathered straight into the
-//           analysis tile, no atomics) + k_fdwt_coarse
+//   P     : k_project (bilinear samples of every layer at the sensor nodes,
+//           plus per-band slope sums for the tip/tilt means)
+//   Gamma, C^-1, (I-T), Gamma^T : k_weights (per band of node rows) in an
+//           apply; k_sensor (one block per sensor and frame) for the right
+//           side and the forward model
+//   P^T   : k_adjoint (separable footprint image per sensor and layer), summed
+//           over sensors in the first analysis level
+//   W + alpha D + <p,Ap> : k_fdwt_tile (level 1 adds up the footprint images,
+//           no atomics) + k_fdwt_coarse
 //   PCG vector updates with FP64 partial inner products: k_init, k_update_r,
 //           k_update_p, k_replace_r
 //   plan time: k_jacobi (separable closed form of the Jacobi diagonal)
@@ -52,6 +57,30 @@ __device__ double block_sum(double v, double* red) {
     }
     __syncthreads();
     return red[16];
+}
+
+// Four deterministic block sums at once (same tree as block_sum); red holds
+// 4 * 16 + 4 doubles.
+__device__ void block_sum4(double* v, double* red) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_down(v[k], o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[16 * k + wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) s += red[16 * threadIdx.x + i];
+        red[64 + threadIdx.x] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = red[64 + k];
 }
 
 __device__ double sum_slots(const double* p, int n, double* red) {
@@ -153,75 +182,34 @@ __device__ void ana_pass(Acc* A, int ld, int M, int along_y, const Acc* hf, cons
     __syncthreads();
 }
 
-// Adjoint projection P^T of the sensors that touch a window of PR x PC pixels
-// of layer l starting at (px0, py0) (periodic indices), accumulated into G
-// (row stride ldg, FP64).  P_ml = B_x (kron) B_y, so every pixel (r, c) takes
-// sum_a sum_b wx(a, r) wy(b, c) V[a][b] over the few nodes whose bilinear
-// stencil reaches it; the weights are the transposed bilinear samples,
-// tabulated per pixel row and column (nodes f..f+c-1, weights at woff).  A
-// thread owns one column and every rstep-th row of it, so each G entry has
-// one writer: no atomics and no barrier.  mask: bit m set if sensor m touches
-// the window.
+// Bilinear sample position of node i on one axis: lower pixel i0 (clamped to
+// [0, N-2]) and the weight t of pixel i0 + 1 (Sec. 2.1).  The forward and the
+// adjoint projection both evaluate it, so they are exact transposes.
+__device__ __forceinline__ void node_stencil(double pa, double pb, int i, int N, int& i0, Acc& t) {
+    const double u = fma(pa, static_cast<double>(i), pb);   // same rounding as the plan's tables
+    i0 = min(max(static_cast<int>(floor(u)), 0), N - 2);
+    t = u - i0;
+}
+
+// P^T over a window of PR x PC pixels of layer l starting at (px0, py0)
+// (periodic indices), written into G (row stride ldg, FP64): the sum, in
+// sensor order, of the footprint images of the sensors in mask (k_adjoint).
+// One writer per pixel; no atomics and no barrier.
 template <class T>
-__device__ void pt_gather_window(const PlanDev& P, const T* nodes, int l, int N, int px0, int py0,
+__device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, int px0, int py0,
                                  int PR, int PC, Acc* G, int ldg, unsigned mask) {
-    const int tid = threadIdx.x, bd = blockDim.x;
-    const double* pw = P.pixw;
-    int c0, r0, rstep, cstep;
-    if (PC <= bd) {
-        c0 = tid % PC;
-        r0 = tid / PC;
-        rstep = bd / PC;
-        cstep = PC;
-        if (r0 >= rstep) return;
-    } else {
-        c0 = tid;
-        r0 = 0;
-        rstep = 1;
-        cstep = bd;
-    }
-    for (int c = c0; c < PC; c += cstep) {
-        const int gy = (py0 + c) % N;
+    for (int e = threadIdx.x; e < PR * PC; e += blockDim.x) {
+        const int r = e / PC, c = e - (e / PC) * PC;
+        const int gx = (px0 + r) % N, gy = (py0 + c) % N;
+        Acc acc = 0;
         for (int m = 0; m < P.W; ++m) {
             if (!((mask >> m) & 1u)) continue;
-            const int po = P.pix_tab_off[m][l];
-            const PixTab cy = P.pixy[po + gy];
-            if (cy.c == 0) continue;
-            const PixTab* tx = P.pixx + po;
-            const int nn = P.wfs[m].nn;
-            const T* Vc = nodes + P.wfs[m].node_off + cy.f;
-            const int cyc = cy.c;
-            if (cyc <= 4) {
-                Acc wy[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) wy[q] = q < cyc ? pw[cy.woff + q] : 0.0;
-                for (int r = r0; r < PR; r += rstep) {
-                    const PixTab rx = tx[(px0 + r) % N];
-                    Acc acc = 0;
-                    for (int qa = 0; qa < rx.c; ++qa) {
-                        const T* vr = Vc + static_cast<int64_t>(rx.f + qa) * nn;
-                        Acc row = 0;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            if (q < cyc) row += wy[q] * static_cast<Acc>(vr[q]);
-                        acc += pw[rx.woff + qa] * row;
-                    }
-                    G[r * ldg + c] += acc;
-                }
-            } else {
-                for (int r = r0; r < PR; r += rstep) {
-                    const PixTab rx = tx[(px0 + r) % N];
-                    Acc acc = 0;
-                    for (int qa = 0; qa < rx.c; ++qa) {
-                        const T* vr = Vc + static_cast<int64_t>(rx.f + qa) * nn;
-                        Acc row = 0;
-                        for (int q = 0; q < cyc; ++q) row += pw[cy.woff + q] * static_cast<Acc>(vr[q]);
-                        acc += pw[rx.woff + qa] * row;
-                    }
-                    G[r * ldg + c] += acc;
-                }
-            }
+            const int xr = gx - P.fp_x0[m][l], yc = gy - P.fp_y0[m][l];
+            if (static_cast<unsigned>(xr) < static_cast<unsigned>(P.fp_h[m][l]) &&
+                static_cast<unsigned>(yc) < static_cast<unsigned>(P.fp_w[m][l]))
+                acc += static_cast<Acc>(img[P.fp_off[m][l] + xr * P.fp_w[m][l] + yc]);
         }
+        G[r * ldg + c] = acc;
     }
 }
 
@@ -361,8 +349,6 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     Acc hf[6], gf[6];
     load_filters(P, hf, gf);
     if (level == 1 && src == SRC_PT) {
-        for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) sA[e / PW][e % PW] = 0;
-        __syncthreads();
         pt_gather_window<T>(P, vptr<T>(J, in_vec, it.frame), it.a, N, px0, py0, PW, PW,
                             &sA[0][0], PW + 1,
                             static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a] + it.b]));
@@ -466,8 +452,6 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
         const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
         for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = in[e];
     } else {
-        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = 0;
-        __syncthreads();
         pt_gather_window<T>(P, vptr<T>(J, in_vec, it.frame), it.a, N, 0, 0, N, N, A, N,
                             static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a]]));
     }
@@ -499,37 +483,346 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
         if (threadIdx.x == 0) part_ptr(J, it.frame, PT_PQ)[it.slot] = s;
     }
 }
-
 // --------------------------------------------------------- projection ----
-// u_m = sum over layers of bilinear samples of the layer pixels at the sensor
-// nodes (Sec. 2.1, eq. (2) and the cone-effect projection), PROJ_ROWS node
-// rows per block, written in FP64 so that the Fried differences of the next
-// stage do not cancel single-precision digits.
+// P: sensor node field u_m = sum over layers of the bilinear samples of each
+// layer at the node's projected position (Sec. 2.1, cone factor for LGS), in
+// FP64.  One block per (frame, sensor, band of PROJ_ROWS node rows).  With
+// sums set (operator applies), the block also forms the Fried slopes of the
+// band's subapertures (Sec. 2.2; one extra halo node row) and writes their
+// sums for the tip/tilt projection and the low-order cells (one record per
+// band, reduced in a fixed order by k_weights).  u is kept in FP64 so that the
+// Fried differences do not cancel single-precision digits.
 template <class T>
 __global__ void __launch_bounds__(256)
-k_project(const JobArgs args, const Item* __restrict__ items, int in_vec) {
+k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int sums) {
+    __shared__ double su[(PROJ_ROWS + 1) * (WM_NSUB_MAX + 1)];
+    __shared__ double red[68];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const int m = it.a;
-    const int nn = P.wfs[m].nn;
+    const WfsInfo& w = P.wfs[m];
+    const int nn = w.nn;
     const int r0 = it.b * PROJ_ROWS;
     const int rows = min(PROJ_ROWS, nn - r0);
+    const bool slopes = sums && w.kind == 0;
+    const int rows_c = slopes ? min(PROJ_ROWS + 1, nn - r0) : rows;
     const T* phi = vptr<T>(J, in_vec, it.frame);
-    double* u = vptr<double>(J, V_U, it.frame) + P.wfs[m].node_off;
-    for (int e = threadIdx.x; e < rows * nn; e += blockDim.x) {
+    double* u = vptr<double>(J, V_U, it.frame) + w.node_off;
+    for (int e = threadIdx.x; e < rows_c * nn; e += blockDim.x) {
         const int i = r0 + e / nn, j = e % nn;
         Acc acc = 0;
-        for (int l = 0; l < P.L; ++l) {
-            const int no = P.node_tab_off[m][l];
-            const int i0 = P.ix0[no + i], j0 = P.jy0[no + j];
-            const Acc t = P.tx[no + i], s = P.ty[no + j];
-            const int N = P.layer[l].N;
-            const T* f = phi + P.layer[l].coff + static_cast<int64_t>(i0) * N + j0;
-            acc += (1.0 - t) * ((1.0 - s) * static_cast<Acc>(f[0]) + s * static_cast<Acc>(f[1])) +
-                   t * ((1.0 - s) * static_cast<Acc>(f[N]) + s * static_cast<Acc>(f[N + 1]));
+        // four layers per step: their samples are loaded before any is used
+        for (int l0 = 0; l0 < P.L; l0 += 4) {
+            Acc v[4][4], tw[4], sw[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int l = l0 + k;
+                if (l < P.L) {
+                    const int N = P.layer[l].N;
+                    int i0, j0;
+                    node_stencil(P.pa[m][l], P.pb[0][m][l], i, N, i0, tw[k]);
+                    node_stencil(P.pa[m][l], P.pb[1][m][l], j, N, j0, sw[k]);
+                    const T* f = phi + P.layer[l].coff + static_cast<int64_t>(i0) * N + j0;
+                    v[k][0] = f[0];
+                    v[k][1] = f[1];
+                    v[k][2] = f[N];
+                    v[k][3] = f[N + 1];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (l0 + k < P.L) {
+                    const Acc t = tw[k], s = sw[k];
+                    acc += (1.0 - t) * ((1.0 - s) * v[k][0] + s * v[k][1]) +
+                           t * ((1.0 - s) * v[k][2] + s * v[k][3]);
+                }
+            }
         }
-        u[i * nn + j] = acc;
+        if (e < rows * nn) u[i * nn + j] = acc;
+        if (slopes) su[e] = acc;
+    }
+    if (!slopes) return;
+    __syncthreads();
+    const int ns = w.n_sub;
+    double* rec = vptr<double>(J, V_SPART, it.frame) + w.sp_off + it.b * SP_K;
+    const int nsub_rows = min(PROJ_ROWS, min(ns - r0, rows_c - 1));
+    if (!w.agg) {
+        Acc p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+        for (int e = threadIdx.x; e < nsub_rows * ns; e += blockDim.x) {
+            const int li = e / ns, j = e % ns;
+            const int q = w.maskmap[(r0 + li) * ns + j];
+            if (q < 0) continue;
+            const Acc u00 = su[li * nn + j], u10 = su[(li + 1) * nn + j];
+            const Acc u01 = su[li * nn + j + 1], u11 = su[(li + 1) * nn + j + 1];
+            const Acc sx = 0.5 * ((u10 - u00) + (u11 - u01));
+            const Acc sy = 0.5 * ((u01 - u00) + (u11 - u10));
+            const double* bq = w.blocks + 3 * q;
+            p0 += sx;
+            p1 += sy;
+            p2 += bq[0] * sx + bq[1] * sy;
+            p3 += bq[1] * sx + bq[2] * sy;
+        }
+        double pv[4] = {p0, p1, p2, p3};
+        block_sum4(pv, red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rec[k] = pv[k];
+    } else {
+        // two cells per pass: x and y sums of cells c and c + 1
+        for (int c = 0; c < w.S; c += 2) {
+            double pv[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int e = threadIdx.x; e < nsub_rows * ns; e += blockDim.x) {
+                const int li = e / ns, j = e % ns;
+                const int k = w.maskmap[(r0 + li) * ns + j] - c;
+                if (k != 0 && k != 1) continue;
+                const Acc u00 = su[li * nn + j], u10 = su[(li + 1) * nn + j];
+                const Acc u01 = su[li * nn + j + 1], u11 = su[(li + 1) * nn + j + 1];
+                pv[2 * k] += 0.5 * ((u10 - u00) + (u11 - u01));
+                pv[2 * k + 1] += 0.5 * ((u01 - u00) + (u11 - u10));
+            }
+            block_sum4(pv, red);
+            if (threadIdx.x == 0) {
+                rec[2 * c] = pv[0];
+                rec[2 * c + 1] = pv[1];
+                if (c + 1 < w.S) {
+                    rec[2 * c + 2] = pv[2];
+                    rec[2 * c + 3] = pv[3];
+                }
+            }
+        }
+    }
+}
+
+// Gamma^T C^-1 (I - T) Gamma for one band of node rows of one sensor (Sec. 2.2,
+// eqs. (17)-(18)): the band's slope sums of every band give the tip/tilt means
+// (or the low-order cell averages); the Fried slopes of the subaperture rows
+// next to the band are formed again from u, weighted by the 2x2 blocks with
+// the means removed before and after, and Gamma^T maps them to the band's node
+// rows.  Phase sensors scale u at their nodes.  One block per (frame, sensor,
+// band), no atomics.
+//   plain:  w = B (s - mu) - nu,  mu = mean s,  nu = mean B (s - mu)
+//           = (sum B s - mu_x sum(a, b) - mu_y sum(b, c)) / S  (tip/tilt-removed
+//           sensors; mu = nu = 0 otherwise)
+//   cells:  cell slopes = cell sums / cell counts, then the same with per-cell
+//           blocks, divided by the cell count for the fine subapertures.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
+    __shared__ double su[(PROJ_ROWS + 2) * (WM_NSUB_MAX + 1)];
+    __shared__ double swx[(PROJ_ROWS + 1) * WM_NSUB_MAX], swy[(PROJ_ROWS + 1) * WM_NSUB_MAX];
+    __shared__ double cval[2 * WM_MAXCELL], cwx[WM_MAXCELL], cwy[WM_MAXCELL];
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    const int m = it.a;
+    const WfsInfo& w = P.wfs[m];
+    const int nn = w.nn, ns = w.n_sub;
+    const int r0 = it.b * PROJ_ROWS;
+    const int rows = min(PROJ_ROWS, nn - r0);
+    const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
+    T* vout = vptr<T>(J, out_vec, it.frame) + w.node_off;
+    if (w.kind == 1) {
+        for (int e = threadIdx.x; e < rows * nn; e += blockDim.x) {
+            const int node = r0 * nn + e;
+            const int q = w.maskmap[node];
+            vout[node] = static_cast<T>(q >= 0 ? w.blocks[3 * q] * ug[node] : 0.0);
+        }
+        return;
+    }
+    const int ua = max(r0 - 1, 0), ub = min(r0 + PROJ_ROWS, nn - 1);
+    for (int e = threadIdx.x; e < (ub - ua + 1) * nn; e += blockDim.x) su[e] = ug[ua * nn + e];
+    if (threadIdx.x == 0) {
+        const double* rec = vptr<double>(J, V_SPART, it.frame) + w.sp_off;
+        const int nb = (nn + PROJ_ROWS - 1) / PROJ_ROWS;
+        const double* blk = w.blocks;
+        if (!w.agg) {
+            double t[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < nb; ++b)
+                for (int k = 0; k < 4; ++k) t[k] += rec[b * SP_K + k];
+            double mx = 0.0, my = 0.0, nx = 0.0, ny = 0.0;
+            if (w.remove_tt) {
+                const double S = w.S_fine;
+                mx = t[0] / S;
+                my = t[1] / S;
+                nx = (t[2] - mx * w.bsum[0] - my * w.bsum[1]) / S;
+                ny = (t[3] - mx * w.bsum[1] - my * w.bsum[2]) / S;
+            }
+            cval[0] = mx;
+            cval[1] = my;
+            cval[2] = nx;
+            cval[3] = ny;
+        } else {
+            const int S = w.S;
+            double mx = 0.0, my = 0.0;
+            for (int c = 0; c < S; ++c) {
+                double px = 0.0, py = 0.0;
+                for (int b = 0; b < nb; ++b) {
+                    px += rec[b * SP_K + 2 * c];
+                    py += rec[b * SP_K + 2 * c + 1];
+                }
+                cval[2 * c] = px / w.cell_count[c];
+                cval[2 * c + 1] = py / w.cell_count[c];
+                mx += cval[2 * c];
+                my += cval[2 * c + 1];
+            }
+            if (w.remove_tt) {
+                mx /= S;
+                my /= S;
+            } else {
+                mx = my = 0.0;
+            }
+            double nx = 0.0, ny = 0.0;
+            for (int c = 0; c < S; ++c) {
+                const double ax = cval[2 * c] - mx, ay = cval[2 * c + 1] - my;
+                cwx[c] = blk[3 * c] * ax + blk[3 * c + 1] * ay;
+                cwy[c] = blk[3 * c + 1] * ax + blk[3 * c + 2] * ay;
+                nx += cwx[c];
+                ny += cwy[c];
+            }
+            if (w.remove_tt) {
+                nx /= S;
+                ny /= S;
+            } else {
+                nx = ny = 0.0;
+            }
+            for (int c = 0; c < S; ++c) {
+                cval[2 * c] = (cwx[c] - nx) / w.cell_count[c];
+                cval[2 * c + 1] = (cwy[c] - ny) / w.cell_count[c];
+            }
+        }
+    }
+    __syncthreads();
+    // weighted slopes of subaperture rows ia..ib (the rows next to the band)
+    const int ia = ua, ib = min(r0 + PROJ_ROWS - 1, ns - 1);
+    for (int e = threadIdx.x; e < (ib - ia + 1) * ns; e += blockDim.x) {
+        const int li = e / ns, j = e % ns;
+        const int i = ia + li;
+        const int q = w.maskmap[i * ns + j];
+        Acc wx = 0, wy = 0;
+        if (q >= 0) {
+            if (w.agg) {
+                wx = cval[2 * q];
+                wy = cval[2 * q + 1];
+            } else {
+                const int lu = i - ua;
+                const Acc u00 = su[lu * nn + j], u10 = su[(lu + 1) * nn + j];
+                const Acc u01 = su[lu * nn + j + 1], u11 = su[(lu + 1) * nn + j + 1];
+                const Acc sx = 0.5 * ((u10 - u00) + (u11 - u01)) - cval[0];
+                const Acc sy = 0.5 * ((u01 - u00) + (u11 - u10)) - cval[1];
+                const double* bq = w.blocks + 3 * q;
+                wx = bq[0] * sx + bq[1] * sy - cval[2];
+                wy = bq[1] * sx + bq[2] * sy - cval[3];
+            }
+        }
+        swx[e] = wx;
+        swy[e] = wy;
+    }
+    __syncthreads();
+    // Gamma^T: node (a, b) takes +-1/2 of the four subapertures around it
+    for (int e = threadIdx.x; e < rows * nn; e += blockDim.x) {
+        const int a = r0 + e / nn, b = e % nn;
+        const int up = (a - 1 - ia) * ns, dn = (a - ia) * ns;
+        Acc v = 0;
+        if (a >= 1 && b < ns) v += swx[up + b] - swy[up + b];
+        if (a < ns && b < ns) v -= swx[dn + b] + swy[dn + b];
+        if (a >= 1 && b >= 1) v += swx[up + b - 1] + swy[up + b - 1];
+        if (a < ns && b >= 1) v += swy[dn + b - 1] - swx[dn + b - 1];
+        vout[a * nn + b] = static_cast<T>(0.5 * v);
+    }
+}
+
+// ------------------------------------------------------- adjoint P^T ----
+// Footprint image of sensor m on layer l, g = B_x^T V B_y (Sec. 2.1), over a
+// band of footprint rows.  The node rows the band needs are copied to LDS in
+// one coalesced sweep; then T[r][b] = sum_a wx(a, r) V[a][b] for the band's
+// pixel rows and every node column (LDS, FP64), and g[r][c] = sum_b wy(b, c)
+// T[r][b].  The weights are the forward bilinear ones read backwards: node a
+// feeds pixel i0_a with 1 - t_a and pixel i0_a + 1 with t_a.  No atomics.
+// LDS: the staged node rows (storage type) and T, sized by the plan.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int out_vec) {
+    __shared__ int si0[WM_NSUB_MAX + 1], sj0[WM_NSUB_MAX + 1];
+    __shared__ double sti[WM_NSUB_MAX + 1], stj[WM_NSUB_MAX + 1];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Item it = items[blockIdx.x];
+    const JobPlan& J = args.jp[it.jp];
+    const PlanDev& P = *J.P;
+    const int m = it.a, l = it.b;
+    const int nn = P.wfs[m].nn, N = P.layer[l].N;
+    const int x0 = P.fp_x0[m][l], y0 = P.fp_y0[m][l];
+    const int Hf = P.fp_h[m][l], Wf = P.fp_w[m][l];
+    const int r0 = it.slot * P.fp_br[m][l], r1 = min(Hf, r0 + P.fp_br[m][l]);
+    const int BR = r1 - r0;
+    const int* rt = P.fp_rc + 2 * P.fp_tab[m][l];
+    const int* ct = rt + 2 * Hf;
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+        node_stencil(P.pa[m][l], P.pb[0][m][l], i, N, si0[i], sti[i]);
+        node_stencil(P.pa[m][l], P.pb[1][m][l], i, N, sj0[i], stj[i]);
+    }
+    // node rows the band reads (rows are monotone in the node index)
+    int alo = nn, ahi = -1;
+    for (int r = r0; r < r1; ++r)
+        if (rt[2 * r + 1] > 0) {
+            alo = min(alo, rt[2 * r]);
+            ahi = max(ahi, rt[2 * r] + rt[2 * r + 1] - 1);
+        }
+    T* out = vptr<T>(J, out_vec, it.frame) + P.fp_off[m][l];
+    if (ahi < alo) {
+        for (int e = threadIdx.x; e < BR * Wf; e += blockDim.x) out[r0 * Wf + e] = T(0);
+        return;
+    }
+    const int NR = ahi - alo + 1;
+    T* Vs = reinterpret_cast<T*>(smem_raw);
+    Acc* Tb = reinterpret_cast<Acc*>(smem_raw + ((static_cast<size_t>(NR) * nn * sizeof(T) + 15) & ~size_t(15)));
+    const T* V = vptr<T>(J, in_vec, it.frame) + P.wfs[m].node_off + static_cast<int64_t>(alo) * nn;
+    for (int e = threadIdx.x; e < NR * nn; e += blockDim.x) Vs[e] = V[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < BR * nn; e += blockDim.x) {
+        const int lr = e / nn, b = e - (e / nn) * nn;
+        const int r = r0 + lr, f = rt[2 * r], cnt = rt[2 * r + 1], gx = x0 + r;
+        Acc acc = 0;
+        for (int q = 0; q < cnt; ++q) {
+            const int a = f + q;
+            acc += (si0[a] == gx ? 1.0 - sti[a] : sti[a]) * static_cast<Acc>(Vs[(a - alo) * nn + b]);
+        }
+        Tb[e] = acc;
+    }
+    __syncthreads();
+    // a thread owns one footprint column: its node range and weights are read
+    // once, then every G-th row of the band
+    const int bd = blockDim.x;
+    const int G = Wf < bd ? bd / Wf : 1;
+    const int g = threadIdx.x / (Wf < bd ? Wf : bd);
+    const int cstep = Wf < bd ? Wf : bd;
+    if (g >= G) return;
+    for (int c = Wf < bd ? threadIdx.x % Wf : threadIdx.x; c < Wf; c += cstep) {
+        const int f = ct[2 * c], cnt = ct[2 * c + 1], gy = y0 + c;
+        if (cnt <= 4) {
+            Acc w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                w[q] = q < cnt ? (sj0[f + q] == gy ? 1.0 - stj[f + q] : stj[f + q]) : 0.0;
+            for (int lr = g; lr < BR; lr += G) {
+                const Acc* tr = Tb + lr * nn + f;
+                Acc acc = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q < cnt) acc += w[q] * tr[q];
+                out[(r0 + lr) * Wf + c] = static_cast<T>(acc);
+            }
+        } else {
+            for (int lr = g; lr < BR; lr += G) {
+                const Acc* tr = Tb + lr * nn;
+                Acc acc = 0;
+                for (int q = 0; q < cnt; ++q) {
+                    const int b = f + q;
+                    acc += (sj0[b] == gy ? 1.0 - stj[b] : stj[b]) * tr[b];
+                }
+                out[(r0 + lr) * Wf + c] = static_cast<T>(acc);
+            }
+        }
     }
 }
 
@@ -545,7 +838,7 @@ template <class T, int QM>
 __global__ void __launch_bounds__(1024)
 k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_vec, int out_vec) {
     __shared__ double red[17];
-    __shared__ double cellx[WM_MAXCELL], celly[WM_MAXCELL];
+    __shared__ double cellx[WM_MAXCELL], celly[WM_MAXCELL], cwx[WM_MAXCELL], cwy[WM_MAXCELL];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Acc* U = reinterpret_cast<Acc*>(smem_raw);
     const Item it = items[blockIdx.x];
@@ -654,19 +947,18 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
                 mx /= S;
                 my /= S;
             }
-            Acc wxs[WM_MAXCELL], wys[WM_MAXCELL];
             Acc nx = 0.0, ny = 0.0;
             for (int c = 0; c < S; ++c) {
                 const Acc ax = cellx[c] - mx, ay = celly[c] - my;
-                wxs[c] = blk[3 * c] * ax + blk[3 * c + 1] * ay;
-                wys[c] = blk[3 * c + 1] * ax + blk[3 * c + 2] * ay;
-                nx += wxs[c];
-                ny += wys[c];
+                cwx[c] = blk[3 * c] * ax + blk[3 * c + 1] * ay;
+                cwy[c] = blk[3 * c + 1] * ax + blk[3 * c + 2] * ay;
+                nx += cwx[c];
+                ny += cwy[c];
             }
             if (w.remove_tt) { nx /= S; ny /= S; } else { nx = ny = 0.0; }
             for (int c = 0; c < S; ++c) {
-                cellx[c] = (wxs[c] - nx) / w.cell_count[c];
-                celly[c] = (wys[c] - ny) / w.cell_count[c];
+                cellx[c] = (cwx[c] - nx) / w.cell_count[c];
+                celly[c] = (cwy[c] - ny) / w.cell_count[c];
             }
         }
         __syncthreads();
@@ -1225,9 +1517,22 @@ void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int
 }
 
 template <class T>
-void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, hipStream_t s) {
+void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(256), 0, s, a, items, in_vec);
+    hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(256), 0, s, a, items, in_vec, sums);
+}
+
+template <class T>
+void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_weights<T>, dim3(n), dim3(256), 0, s, a, items, out_vec);
+}
+
+template <class T>
+void launch_adjoint(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
+                    int lds_bytes, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_adjoint<T>, dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
 }
 
 template <class T>
@@ -1298,6 +1603,8 @@ void configure_kernels() {
     allow_full_lds(&k_idwt_coarse<double>);
     allow_full_lds(&k_fdwt_coarse<float>);
     allow_full_lds(&k_fdwt_coarse<double>);
+    allow_full_lds(&k_adjoint<float>);
+    allow_full_lds(&k_adjoint<double>);
     allow_full_lds(&k_sensor<float, 8>);
     allow_full_lds(&k_sensor<float, 16>);
     allow_full_lds(&k_sensor<double, 8>);
@@ -1310,7 +1617,9 @@ void configure_kernels() {
     template void launch_fdwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, int, hipStream_t); \
     template void launch_fdwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, hipStream_t); \
     template void launch_sensor<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
-    template void launch_project<T>(const JobArgs&, const Item*, int, int, hipStream_t);       \
+    template void launch_project<T>(const JobArgs&, const Item*, int, int, int, hipStream_t);  \
+    template void launch_weights<T>(const JobArgs&, const Item*, int, int, hipStream_t);       \
+    template void launch_adjoint<T>(const JobArgs&, const Item*, int, int, int, int, hipStream_t); \
     template void launch_init<T>(const JobArgs&, const Item*, int, int, hipStream_t);          \
     template void launch_update_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \
     template void launch_update_p<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \

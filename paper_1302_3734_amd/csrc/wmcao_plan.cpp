@@ -55,6 +55,9 @@ struct Sched {
     int n_sensor = 0;
     const Item* proj = nullptr;
     int n_proj = 0;
+    const Item* adj = nullptr;
+    int n_adj = 0;
+    int lds_adj = 0;
     const Item* vec = nullptr;
     int n_vec = 0;
     int maxk0 = 0;
@@ -66,7 +69,7 @@ struct Sched {
     double b_idwt_coarse = 0, b_idwt_tile[WM_MAXLEV + 1] = {};
     double b_fdwt_tile[2][WM_MAXLEV + 1] = {}, b_fdwt_coarse[2] = {};   // [plain, apply]
     double b_sensor[3] = {};                                              // [apply, rhs, fwd]
-    double b_project = 0;
+    double b_project = 0, b_adjoint = 0;
     double b_init = 0, b_update_r = 0, b_update_p = 0, b_replace = 0;
 };
 
@@ -141,13 +144,18 @@ struct wmcao_plan_s {
     void* vphi = nullptr;
     void* vll = nullptr;
     void* vnode = nullptr;
+    void* vfp = nullptr;
     double* vu = nullptr;
+    double* vspart = nullptr;
     double* part = nullptr;
     double* scal = nullptr;
     int* status = nullptr;
     double* jac_d = nullptr;
     int64_t n = 0, n_slopes = 0, n_nodes = 0, ll_size = 0;
     int64_t n_fp = 0;   // layer pixels some sensor node's bilinear stencil touches
+    int64_t n_fpimg = 0;  // values of the adjoint footprint images of one frame
+    int64_t n_spart = 0;  // doubles of the per-band slope sums of one frame
+    int lds_adjoint = 0;  // row-pass buffer of the adjoint kernel
     std::vector<int64_t> layer_off, slope_off;
     std::map<int, std::unique_ptr<Sched>> sched;
     // captured graph of one wmcao_solve_graph argument set
@@ -242,9 +250,9 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // partials into slots 0.. in the order level-1 tiles, level-2 tiles, ...,
 // coarse blocks; the vector passes use one slot per chunk.
 int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
-    std::vector<Item> coarse, sensor, vec, proj;
+    std::vector<Item> coarse, sensor, vec, proj, adj;
     std::vector<Item> tiled[WM_MAXLEV + 1];
-    int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0;
+    int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0, lds_a = 0;
     for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
         const wmcao_plan_s* P = jobs[jp].plan;
         for (int f = 0; f < jobs[jp].count; ++f) {
@@ -266,6 +274,13 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                 lds_i = std::max(lds_i, M0 * M0 * 8);
                 lds_f = std::max(lds_f, M0 * M0 * 8);
             }
+            for (int m = 0; m < P->W; ++m)
+                for (int l = 0; l < P->L; ++l) {
+                    const int br = P->host.fp_br[m][l];
+                    const int nb = br > 0 ? ceil_div(P->host.fp_h[m][l], br) : 0;
+                    for (int b = 0; b < nb; ++b) adj.push_back(Item{jp, f, m, l, b, 0, 0, 0});
+                }
+            lds_a = std::max(lds_a, P->lds_adjoint);
             for (int m = 0; m < P->W; ++m) {
                 sensor.push_back(Item{jp, f, m, 0, 0, 0, 0, 0});
                 const int nb = ceil_div(P->host.wfs[m].nn, PROJ_ROWS);
@@ -295,10 +310,12 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                 gathers_tile = gathers_tile || k == 1;
             }
         }
+        const double F = static_cast<double>(P->n_fpimg);
         for (int a = 0; a < 2; ++a) {
-            if (gathers_tile) S->b_fdwt_tile[a][1] += Q * e;
-            if (gathers_coarse) S->b_fdwt_coarse[a] += Q * e;
+            if (gathers_tile) S->b_fdwt_tile[a][1] += F * e;
+            if (gathers_coarse) S->b_fdwt_coarse[a] += F * e;
         }
+        S->b_adjoint += (Q + F) * e;
         const double u8 = 8.0 * jobs[jp].count;     // node fields of the projection are FP64
         S->b_project += P->n_fp * e + Q * u8;
         S->b_sensor[0] += Q * u8 + Q * e;
@@ -319,6 +336,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     add(sensor);
     add(vec);
     add(proj);
+    add(adj);
     for (int k = 1; k <= WM_MAXLEV; ++k) add(tiled[k]);
     S->buf = std::make_unique<DevBuf>();
     const size_t bytes = std::max<size_t>(all.size(), 1) * sizeof(Item);
@@ -334,8 +352,11 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     S->n_vec = static_cast<int>(vec.size());
     S->proj = base + offs[3];
     S->n_proj = static_cast<int>(proj.size());
+    S->adj = base + offs[4];
+    S->n_adj = static_cast<int>(adj.size());
+    S->lds_adj = lds_a;
     for (int k = 1; k <= WM_MAXLEV; ++k) {
-        S->tiled[k] = base + offs[3 + k];
+        S->tiled[k] = base + offs[4 + k];
         S->n_tiled[k] = static_cast<int>(tiled[k].size());
     }
     S->maxk0 = maxk0;
@@ -348,6 +369,18 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
 
 std::mutex g_multi_mu;
 std::map<std::vector<std::pair<const void*, int>>, std::unique_ptr<Sched>> g_multi_cache;
+
+// Captured multi-plan solves, keyed by every argument that the graph bakes in.
+struct MultiGraphKey {
+    std::vector<std::tuple<const void*, const void*, const void*, int>> args;   // plan, slopes, coeffs, count
+    int n_iter = 0, warm = 0;
+    void* stream = nullptr;
+    bool operator<(const MultiGraphKey& o) const {
+        return std::tie(args, n_iter, warm, stream) < std::tie(o.args, o.n_iter, o.warm, o.stream);
+    }
+};
+constexpr size_t MULTI_GRAPH_CACHE = 64;
+std::map<MultiGraphKey, hipGraphExec_t> g_multi_graphs;
 
 int get_sched(wmcao_plan_s* p, int batch, Sched** out) {
     auto it = p->sched.find(batch);
@@ -374,7 +407,11 @@ JobPlan make_jobplan(wmcao_plan_s* p, int nframes) {
     J.vec[V_LL] = p->vll;
     J.vec[V_NODE] = p->vnode;
     J.vec[V_U] = p->vu;
+    J.vec[V_FP] = p->vfp;
+    J.vec[V_SPART] = p->vspart;
+    J.stride[V_SPART] = p->n_spart;
     J.stride[V_U] = p->n_nodes;
+    J.stride[V_FP] = p->n_fpimg;
     for (int v : {V_X, V_B, V_R, V_P, V_Q, V_PHI}) J.stride[v] = p->n;
     J.stride[V_LL] = p->ll_size;
     J.stride[V_NODE] = p->n_nodes;
@@ -418,11 +455,12 @@ void run_fdwt(const JobArgs& a, const Sched& S, int src, int in_vec, int out_vec
 template <class T>
 void run_apply(const JobArgs& a, const Sched& S, int x_vec, int y_vec, hipStream_t s) {
     run_idwt<T>(a, S, x_vec, V_PHI, s);
-    timed(WMCAO_K_PROJECT, S.b_project, s, [&] { launch_project<T>(a, S.proj, S.n_proj, V_PHI, s); });
-    timed(WMCAO_K_SENSOR, S.b_sensor[0], s, [&] {
-        launch_sensor<T>(a, S.sensor, S.n_sensor, SM_APPLY, V_U, V_NODE, S.lds_sensor, s);
+    timed(WMCAO_K_PROJECT, S.b_project, s, [&] { launch_project<T>(a, S.proj, S.n_proj, V_PHI, 1, s); });
+    timed(WMCAO_K_SENSOR, S.b_sensor[0], s, [&] { launch_weights<T>(a, S.proj, S.n_proj, V_NODE, s); });
+    timed(WMCAO_K_ADJOINT, S.b_adjoint, s, [&] {
+        launch_adjoint<T>(a, S.adj, S.n_adj, V_NODE, V_FP, S.lds_adj, s);
     });
-    run_fdwt<T>(a, S, SRC_PT, V_NODE, y_vec, EPI_APPLY, x_vec, s);
+    run_fdwt<T>(a, S, SRC_PT, V_FP, y_vec, EPI_APPLY, x_vec, s);
 }
 
 template <class T>
@@ -430,7 +468,10 @@ void run_rhs(const JobArgs& a, const Sched& S, int slopes_vec, int b_vec, hipStr
     timed(WMCAO_K_SENSOR, S.b_sensor[1], s, [&] {
         launch_sensor<T>(a, S.sensor, S.n_sensor, SM_RHS, slopes_vec, V_NODE, S.lds_sensor, s);
     });
-    run_fdwt<T>(a, S, SRC_PT, V_NODE, b_vec, EPI_NONE, b_vec, s);
+    timed(WMCAO_K_ADJOINT, S.b_adjoint, s, [&] {
+        launch_adjoint<T>(a, S.adj, S.n_adj, V_NODE, V_FP, S.lds_adj, s);
+    });
+    run_fdwt<T>(a, S, SRC_PT, V_FP, b_vec, EPI_NONE, b_vec, s);
 }
 
 template <class T>
@@ -491,6 +532,63 @@ int enqueue_solve(wmcao_plan_s* p, const void* slopes, void* coeffs, int batch, 
         run_solve<float>(a, *S, n_iter, warm, p->resid_replace, s);
     else
         run_solve<double>(a, *S, n_iter, warm, p->resid_replace, s);
+    return check_launch();
+}
+
+// Multi-plan solve enqueue (caller holds g_multi_mu).  prepare_only: validate
+// and build the schedule without launching (before a graph capture).
+int enqueue_multi(const wmcao_plan_t* plans, const void* const* slopes, void* const* coeffs,
+                  const int* counts, int n_plans, int n_iter, int warm_start, hipStream_t s,
+                  bool prepare_only = false) {
+    if (!plans || !slopes || !coeffs || !counts) return fail(WMCAO_ERR_INVALID_ARG, "NULL argument");
+    if (n_plans < 1 || n_plans > WM_MAXJP) return fail(WMCAO_ERR_INVALID_ARG, "n_plans out of range");
+    if (n_iter < 0) return fail(WMCAO_ERR_INVALID_ARG, "n_iter < 0");
+    const wmcao_dtype dt = plans[0] ? plans[0]->dtype : WMCAO_F32;
+    std::vector<JobSpec> jobs;
+    for (int i = 0; i < n_plans; ++i) {
+        int rc = check_batch(plans[i], counts[i]);
+        if (rc) return rc;
+        if (plans[i]->dtype != dt) return fail(WMCAO_ERR_INVALID_ARG, "plans must share the dtype");
+        if (!slopes[i] || !coeffs[i]) return fail(WMCAO_ERR_INVALID_ARG, "NULL buffer");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(WMCAO_ERR_INVALID_ARG, "a plan appears twice");
+        jobs.push_back(JobSpec{plans[i], counts[i]});
+    }
+    // one schedule per distinct job shape, dropped when one of its plans is destroyed
+    std::vector<std::pair<const void*, int>> key;
+    for (auto& j : jobs) key.emplace_back(j.plan, j.count);
+    auto& cache = g_multi_cache;
+    std::vector<std::unique_lock<std::mutex>> locks;
+    for (auto& j : jobs) locks.emplace_back(j.plan->mu);
+    DevGuard g(plans[0]->device);
+    const int tile = plans[0]->tile;
+    for (auto& j : jobs)
+        if (j.plan->tile != tile) return fail(WMCAO_ERR_INVALID_ARG, "plans must share the tile size");
+    auto it = cache.find(key);
+    Sched* S = nullptr;
+    if (it == cache.end()) {
+        auto sp = std::make_unique<Sched>();
+        int rc = build_sched(jobs, tile, sp.get());
+        if (rc) return rc;
+        S = sp.get();
+        cache[key] = std::move(sp);
+    } else {
+        S = it->second.get();
+    }
+    if (prepare_only) return WMCAO_OK;
+    JobArgs a{};
+    a.njp = n_plans;
+    int rr = 0;
+    for (int i = 0; i < n_plans; ++i) {
+        a.jp[i] = make_jobplan(plans[i], counts[i]);
+        a.jp[i].vec[V_X] = coeffs[i];
+        a.jp[i].vec[V_SLOPES] = const_cast<void*>(slopes[i]);
+        rr = std::max(rr, plans[i]->resid_replace);
+    }
+    if (dt == WMCAO_F32)
+        run_solve<float>(a, *S, n_iter, warm_start, rr, s);
+    else
+        run_solve<double>(a, *S, n_iter, warm_start, rr, s);
     return check_launch();
 }
 
@@ -634,8 +732,8 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
 
     // ---- sensors --------------------------------------------------------
     std::vector<int> ix0, jy0;
-    std::vector<PixTab> pixx, pixy;
-    std::vector<double> pixw;
+    std::vector<char> hitx, hity;                 // per (sensor, layer): pixels reached
+    int pix_tab_off[WM_MAXW][WM_MAXL] = {};
     std::vector<double> txd, tyd, blocksd;
     int64_t soff = 0, noff = 0;
     p->slope_off.assign(1, 0);
@@ -728,6 +826,12 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         }
         I.soff = soff;
         I.boff = static_cast<int64_t>(blocksd.size() / 3) - I.S;
+        for (int k = 0; k < 3; ++k) {
+            I.bsum[k] = 0.0;
+            for (int q = 0; q < I.S; ++q) I.bsum[k] += blocksd[3 * (I.boff + q) + k];
+        }
+        I.sp_off = static_cast<int>(p->n_spart);
+        p->n_spart += static_cast<int64_t>(ceil_div(nn, PROJ_ROWS)) * SP_K;
         soff += (I.kind == 1 ? 1 : 2) * I.S;
         p->slope_off.push_back(soff);
         I.node_off = noff;
@@ -738,17 +842,22 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             const double s = w.is_lgs ? 1.0 - hl / w.lgs_height_m : 1.0;
             const int N = layers[l].n;
             const double d = layers[l].spacing_m;
+            // node i at x_i = (i - n_sub/2) d_sub, seen at s x_i + theta h; in
+            // grid units u = x / d + N/2 = pa i + pb
+            const double pa = s * dsub / d;
+            H.pa[m][l] = pa;
+            H.pia[m][l] = 1.0 / pa;
             H.node_tab_off[m][l] = static_cast<int>(ix0.size());
-            H.pix_tab_off[m][l] = static_cast<int>(pixx.size());
+            pix_tab_off[m][l] = static_cast<int>(hitx.size());
             for (int axis = 0; axis < 2; ++axis) {
                 const double theta = axis == 0 ? w.theta_x : w.theta_y;
+                const double pb = (theta * hl - s * (ns / 2.0) * dsub) / d + N / 2.0;
+                H.pb[axis][m][l] = pb;
                 std::vector<int>& i0v = axis == 0 ? ix0 : jy0;
                 std::vector<double>& tv = axis == 0 ? txd : tyd;
-                std::vector<PixTab>& pv = axis == 0 ? pixx : pixy;
                 const size_t base = i0v.size();
                 for (int i = 0; i < nn; ++i) {
-                    const double xi = (i - ns / 2.0) * dsub;
-                    const double u = (s * xi + theta * hl) / d + N / 2.0;
+                    const double u = std::fma(pa, static_cast<double>(i), pb);
                     if (!(u >= 0.0 && u <= N - 1.0))
                         return fail(WMCAO_ERR_FOOTPRINT, "sensor " + std::to_string(m) +
                                     " leaves layer " + std::to_string(l));
@@ -757,26 +866,13 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
                     i0v.push_back(i0);
                     tv.push_back(u - i0);
                 }
-                std::vector<int> first(N, -1), last(N, -2);
+                // pixel rows (columns) that some node's bilinear stencil reaches
+                std::vector<char>& hv = axis == 0 ? hitx : hity;
+                for (int px = 0; px < N; ++px) hv.push_back(0);
                 for (int i = 0; i < nn; ++i) {
                     const int i0 = i0v[base + i];
-                    for (int px : {i0, i0 + 1}) {
-                        if (first[px] < 0) first[px] = i;
-                        last[px] = i;
-                    }
-                }
-                for (int px = 0; px < N; ++px) {
-                    const int cnt = first[px] < 0 ? 0 : last[px] - first[px] + 1;
-                    PixTab t{};
-                    t.f = first[px] < 0 ? 0 : first[px];
-                    t.c = cnt;
-                    t.woff = static_cast<int>(pixw.size());
-                    for (int q = 0; q < cnt; ++q) {   // transpose of the bilinear weights
-                        const int a = t.f + q;
-                        const double tt = tv[base + a];
-                        pixw.push_back((i0v[base + a] == px) ? 1.0 - tt : tt);
-                    }
-                    pv.push_back(t);
+                    hv[hv.size() - N + i0] = 1;
+                    hv[hv.size() - N + i0 + 1] = 1;
                 }
             }
         }
@@ -799,6 +895,73 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     H.n_slopes = soff;
     H.n_nodes = noff;
 
+    // adjoint footprints (Sec. 2.1 read backwards): per (sensor, layer) the
+    // pixel rectangle the nodes' bilinear stencils reach, the node range that
+    // feeds each of its rows and columns, and the rows per work item that keep
+    // the staged node rows and the row-pass buffer within ADJ_LDS
+    std::vector<int> fprc;
+    for (int m = 0; m < n_wfs; ++m) {
+        const int nn = H.wfs[m].nn;
+        for (int l = 0; l < n_layers; ++l) {
+            const int N = layers[l].n, no = H.node_tab_off[m][l];
+            int lo[2], len[2];
+            const int tab = static_cast<int>(fprc.size() / 2);
+            for (int axis = 0; axis < 2; ++axis) {
+                const std::vector<int>& i0v = axis == 0 ? ix0 : jy0;
+                std::vector<int> first(N, -1), last(N, -2);
+                for (int i = 0; i < nn; ++i)
+                    for (int px : {i0v[no + i], i0v[no + i] + 1}) {
+                        if (first[px] < 0) first[px] = i;
+                        last[px] = i;
+                    }
+                int a = N, b = -1;
+                for (int px = 0; px < N; ++px)
+                    if (first[px] >= 0) {
+                        a = std::min(a, px);
+                        b = std::max(b, px);
+                    }
+                lo[axis] = b >= a ? a : 0;
+                len[axis] = b >= a ? b - a + 1 : 0;
+                for (int px = lo[axis]; px < lo[axis] + len[axis]; ++px) {
+                    fprc.push_back(first[px] < 0 ? 0 : first[px]);
+                    fprc.push_back(first[px] < 0 ? 0 : last[px] - first[px] + 1);
+                }
+            }
+            H.fp_x0[m][l] = lo[0];
+            H.fp_y0[m][l] = lo[1];
+            H.fp_h[m][l] = len[0];
+            H.fp_w[m][l] = len[1];
+            H.fp_tab[m][l] = tab;
+            H.fp_off[m][l] = static_cast<int>(p->n_fpimg);
+            p->n_fpimg += static_cast<int64_t>(len[0]) * len[1];
+            if (p->n_fpimg > (int64_t(1) << 30))
+                return fail(WMCAO_ERR_UNSUPPORTED, "adjoint footprint images too large");
+            int br = ADJ_BAND, need = 0;
+            for (; br >= 1; br /= 2) {
+                need = 0;
+                for (int r0 = 0; r0 < len[0]; r0 += br) {
+                    int alo = nn, ahi = -1;
+                    for (int r = r0; r < std::min(len[0], r0 + br); ++r) {
+                        const int f = fprc[2 * (tab + r)], c = fprc[2 * (tab + r) + 1];
+                        if (c > 0) {
+                            alo = std::min(alo, f);
+                            ahi = std::max(ahi, f + c - 1);
+                        }
+                    }
+                    const int rows = std::min(len[0], r0 + br) - r0;
+                    const int vbytes =
+                        ahi < alo ? 0 : ((ahi - alo + 1) * nn * static_cast<int>(p->esz) + 15) & ~15;
+                    need = std::max(need, vbytes + rows * nn * 8);
+                }
+                if (need <= ADJ_LDS) break;
+            }
+            if (br < 1)
+                return fail(WMCAO_ERR_UNSUPPORTED, "sensor footprint too wide for the adjoint projection");
+            H.fp_br[m][l] = br;
+            p->lds_adjoint = std::max(p->lds_adjoint, need);
+        }
+    }
+
     // ---- upload tables --------------------------------------------------
 #define UP(vec, dst)                                          \
     do {                                                      \
@@ -813,9 +976,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     }
     UP(ix0, H.ix0);
     UP(jy0, H.jy0);
-    UP(pixx, H.pixx);
-    UP(pixy, H.pixy);
-    UP(pixw, H.pixw);
+    UP(fprc, H.fp_rc);
     {
         // adjoint-projection records per (layer, level-1 tile), or per layer at k0 = 0
         std::vector<int> meta;
@@ -833,11 +994,11 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
                 }
                 unsigned mask = 0;
                 for (int m = 0; m < n_wfs; ++m) {
-                    const int po = H.pix_tab_off[m][l];
+                    const int po = pix_tab_off[m][l];
                     bool anyr = false, anyc = false;
                     for (int k = 0; k < W0; ++k) {
-                        anyr = anyr || pixx[po + (x0 + k) % N].c > 0;
-                        anyc = anyc || pixy[po + (y0 + k) % N].c > 0;
+                        anyr = anyr || hitx[po + (x0 + k) % N];
+                        anyc = anyc || hity[po + (y0 + k) % N];
                     }
                     if (anyr && anyc) mask |= 1u << m;
                 }
@@ -881,6 +1042,9 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     if (!(p->vphi = p->alloc(ve, &rc))) return rc;
     if (!(p->vll = p->alloc(static_cast<size_t>(p->ll_size) * B * p->esz, &rc))) return rc;
     if (!(p->vnode = p->alloc(static_cast<size_t>(p->n_nodes) * B * p->esz, &rc))) return rc;
+    if (!(p->vfp = p->alloc(static_cast<size_t>(p->n_fpimg) * B * p->esz, &rc))) return rc;
+    if (!(p->vspart = static_cast<double*>(p->alloc(static_cast<size_t>(p->n_spart) * B * 8, &rc))))
+        return rc;
     if (!(p->vu = static_cast<double*>(p->alloc(static_cast<size_t>(p->n_nodes) * B * 8, &rc)))) return rc;
     if (!(p->part = static_cast<double*>(p->alloc(sizeof(double) * NPT * H.slots * B, &rc)))) return rc;
     if (!(p->scal = static_cast<double*>(p->alloc(sizeof(double) * 2 * B, &rc)))) return rc;
@@ -976,10 +1140,10 @@ static int simple_call(wmcao_plan_t p, const void* in, void* out, int batch, voi
             a.jp[0].stride[V_IN] = p->n;
             a.jp[0].stride[V_OUT] = p->n_slopes;
             if (f32) {
-                launch_project<float>(a, S->proj, S->n_proj, V_IN, s);
+                launch_project<float>(a, S->proj, S->n_proj, V_IN, 0, s);
                 launch_sensor<float>(a, S->sensor, S->n_sensor, SM_FWD, V_U, V_OUT, S->lds_sensor, s);
             } else {
-                launch_project<double>(a, S->proj, S->n_proj, V_IN, s);
+                launch_project<double>(a, S->proj, S->n_proj, V_IN, 0, s);
                 launch_sensor<double>(a, S->sensor, S->n_sensor, SM_FWD, V_U, V_OUT, S->lds_sensor, s);
             }
             break;
@@ -1087,57 +1251,55 @@ int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int b
 int wmcao_solve_multi(const wmcao_plan_t* plans, const void* const* slopes, void* const* coeffs,
                       const int* counts, int n_plans, int n_iter, int warm_start,
                       void* hip_stream) {
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    return enqueue_multi(plans, slopes, coeffs, counts, n_plans, n_iter, warm_start,
+                         static_cast<hipStream_t>(hip_stream));
+}
+
+int wmcao_solve_multi_graph(const wmcao_plan_t* plans, const void* const* slopes,
+                            void* const* coeffs, const int* counts, int n_plans, int n_iter,
+                            int warm_start, void* hip_stream) {
+    if (!hip_stream) return fail(WMCAO_ERR_INVALID_ARG, "graph capture needs a non-default stream");
     if (!plans || !slopes || !coeffs || !counts) return fail(WMCAO_ERR_INVALID_ARG, "NULL argument");
     if (n_plans < 1 || n_plans > WM_MAXJP) return fail(WMCAO_ERR_INVALID_ARG, "n_plans out of range");
-    if (n_iter < 0) return fail(WMCAO_ERR_INVALID_ARG, "n_iter < 0");
-    const wmcao_dtype dt = plans[0] ? plans[0]->dtype : WMCAO_F32;
-    std::vector<JobSpec> jobs;
-    for (int i = 0; i < n_plans; ++i) {
-        int rc = check_batch(plans[i], counts[i]);
-        if (rc) return rc;
-        if (plans[i]->dtype != dt) return fail(WMCAO_ERR_INVALID_ARG, "plans must share the dtype");
-        if (!slopes[i] || !coeffs[i]) return fail(WMCAO_ERR_INVALID_ARG, "NULL buffer");
-        for (int j = 0; j < i; ++j)
-            if (plans[j] == plans[i]) return fail(WMCAO_ERR_INVALID_ARG, "a plan appears twice");
-        jobs.push_back(JobSpec{plans[i], counts[i]});
-    }
-    // one schedule per distinct job shape, dropped when one of its plans is destroyed
-    std::vector<std::pair<const void*, int>> key;
-    for (auto& j : jobs) key.emplace_back(j.plan, j.count);
     std::lock_guard<std::mutex> lk(g_multi_mu);
-    auto& cache = g_multi_cache;
-    std::vector<std::unique_lock<std::mutex>> locks;
-    for (auto& j : jobs) locks.emplace_back(j.plan->mu);
-    DevGuard g(plans[0]->device);
-    const int tile = plans[0]->tile;
-    for (auto& j : jobs)
-        if (j.plan->tile != tile) return fail(WMCAO_ERR_INVALID_ARG, "plans must share the tile size");
-    auto it = cache.find(key);
-    Sched* S = nullptr;
-    if (it == cache.end()) {
-        auto sp = std::make_unique<Sched>();
-        int rc = build_sched(jobs, tile, sp.get());
-        if (rc) return rc;
-        S = sp.get();
-        cache[key] = std::move(sp);
-    } else {
-        S = it->second.get();
-    }
-    JobArgs a{};
-    a.njp = n_plans;
-    int rr = 0;
-    for (int i = 0; i < n_plans; ++i) {
-        a.jp[i] = make_jobplan(plans[i], counts[i]);
-        a.jp[i].vec[V_X] = coeffs[i];
-        a.jp[i].vec[V_SLOPES] = const_cast<void*>(slopes[i]);
-        rr = std::max(rr, plans[i]->resid_replace);
-    }
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (dt == WMCAO_F32)
-        run_solve<float>(a, *S, n_iter, warm_start, rr, s);
-    else
-        run_solve<double>(a, *S, n_iter, warm_start, rr, s);
-    return check_launch();
+    MultiGraphKey key;
+    for (int i = 0; i < n_plans; ++i)
+        key.args.push_back(std::make_tuple(static_cast<const void*>(plans[i]), slopes[i],
+                                           static_cast<const void*>(coeffs[i]), counts[i]));
+    key.n_iter = n_iter;
+    key.warm = warm_start;
+    key.stream = hip_stream;
+    auto it = g_multi_graphs.find(key);
+    if (it == g_multi_graphs.end()) {
+        // build the schedule outside the capture (it allocates), then record
+        int rc = enqueue_multi(plans, slopes, coeffs, counts, n_plans, n_iter, warm_start, s,
+                               /*prepare_only=*/true);
+        if (rc) return rc;
+        if (g_multi_graphs.size() >= MULTI_GRAPH_CACHE) {
+            (void)hipGraphExecDestroy(g_multi_graphs.begin()->second);
+            g_multi_graphs.erase(g_multi_graphs.begin());
+        }
+        DevGuard g(plans[0]->device);
+        WM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_multi(plans, slopes, coeffs, counts, n_plans, n_iter, warm_start, s);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(WMCAO_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+        hipGraphExec_t ge = nullptr;
+        e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(WMCAO_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+        it = g_multi_graphs.emplace(key, ge).first;
+    }
+    DevGuard g(plans[0]->device);
+    WM_HIP(hipGraphLaunch(it->second, s));
+    return WMCAO_OK;
 }
 
 int wmcao_profile_enable(wmcao_plan_t plan, int enable) {
@@ -1200,6 +1362,16 @@ void wmcao_plan_destroy(wmcao_plan_t plan) {
             bool uses = false;
             for (auto& kv : it->first) uses = uses || kv.first == plan;
             if (uses) it = g_multi_cache.erase(it); else ++it;
+        }
+        for (auto it = g_multi_graphs.begin(); it != g_multi_graphs.end();) {
+            bool uses = false;
+            for (auto& t : it->first.args) uses = uses || std::get<0>(t) == plan;
+            if (uses) {
+                (void)hipGraphExecDestroy(it->second);
+                it = g_multi_graphs.erase(it);
+            } else {
+                ++it;
+            }
         }
     }
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);

@@ -178,8 +178,10 @@ class Plan:
         return coeffs
 
 
-def solve_multi(plans, slopes, coeffs, n_iter=10, warm_start=False):
-    """One packed PCG solve over frames of several plans (mixed sizes)."""
+def solve_multi(plans, slopes, coeffs, n_iter=10, warm_start=False, graph=False):
+    """One packed PCG solve over frames of several plans (mixed sizes).  With
+    graph=True the launches are captured once per argument set and replayed
+    (the buffers must then stay allocated while the plans live)."""
     k = len(plans)
     H = (C.c_void_p * k)(*[p.handle.value for p in plans])
     S = (C.c_void_p * k)()
@@ -192,6 +194,7 @@ def solve_multi(plans, slopes, coeffs, n_iter=10, warm_start=False):
         S[i] = slopes[i].data_ptr()
         X[i] = coeffs[i].data_ptr()
         N[i] = b
-    _abi.check(_abi.lib().wmcao_solve_multi(H, S, X, N, k, int(n_iter), int(bool(warm_start)),
-                                            _stream_ptr()), "wmcao_solve_multi")
+    name = "wmcao_solve_multi_graph" if graph else "wmcao_solve_multi"
+    _abi.check(getattr(_abi.lib(), name)(H, S, X, N, k, int(n_iter), int(bool(warm_start)),
+                                         _stream_ptr()), name)
     return coeffs

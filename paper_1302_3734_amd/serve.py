@@ -7,9 +7,11 @@ resident on the device together with the stream's warm-start coefficients
 oldest pending frame of every stream that has no frame on the GPU, as long as
 the bytes reserved by frames in flight stay within an HBM budget, and packs
 all admitted frames of all configurations into one multi-plan PCG launch
-(``wmcao_solve_multi``).  Launches alternate over several HIP streams (default
-priority) with one plan instance per (configuration, HIP stream), so a batch
-admitted while another is on the GPU runs alongside it.  A completion thread
+(``wmcao_solve_multi``, captured as a HIP graph per combination of
+configurations and frame counts and replayed from fixed staging buffers).
+Launches alternate over several HIP streams (default priority) with one plan
+instance per (configuration, HIP stream), so a batch admitted while another
+is on the GPU runs alongside it.  A completion thread
 stamps each frame when its launch's event completes; latency is arrival to
 completion.  Because every frame's reductions are private and ordered, a
 frame's result does not depend on the batch it was packed into.
@@ -58,10 +60,11 @@ class Server:
     (for invariance checks)."""
 
     def __init__(self, configs, streams, dtype="f32", n_iter=10, hip_streams=2,
-                 hbm_budget=None, keep_inputs=False):
+                 hbm_budget=None, keep_inputs=False, graphs=True):
         self.dtype = dtype
         self.n_iter = int(n_iter)
         self.keep_inputs = keep_inputs
+        self.graphs = graphs
         self.hip_streams = [torch.cuda.Stream() for _ in range(hip_streams)]
         count = collections.Counter(streams.values())
         # one plan per (configuration, HIP stream), batch = streams of that config
@@ -72,6 +75,11 @@ class Server:
         tdt = self.plans[next(iter(self.plans))][0].torch_dtype
         self.torch_dtype = tdt
         self.streams = {s: _Stream(s, c, self.n[c], tdt) for s, c in streams.items()}
+        # fixed staging buffers per (configuration, HIP stream): graph replays
+        # read the slopes and warm starts from, and leave the results in, them
+        self.stage = {c: [(torch.zeros(count[c], self.n_slopes[c], dtype=tdt, device="cuda"),
+                           torch.zeros(count[c], self.n[c], dtype=tdt, device="cuda"))
+                          for _ in range(hip_streams)] for c in self.plans}
         esz = torch.empty(0, dtype=tdt).element_size()
         # bytes a frame in flight reserves: slopes + state + the plan scratch of one frame
         self.frame_bytes = {c: esz * (self.n_slopes[c] + 7 * self.n[c]) for c in self.plans}
@@ -159,8 +167,15 @@ class Server:
                     stream.wait_event(f.ready)
             for cfg, frs in groups.items():
                 plan = self.plans[cfg][hs]
-                S = torch.cat([f.slopes for f in frs]) if len(frs) > 1 else frs[0].slopes
-                X = torch.cat([f.stream.x for f in frs]) if len(frs) > 1 else frs[0].stream.x
+                if self.graphs:
+                    Sb, Xb = self.stage[cfg][hs]
+                    S, X = Sb[:len(frs)], Xb[:len(frs)]
+                    for k, f in enumerate(frs):
+                        S[k].copy_(f.slopes[0])
+                        X[k].copy_(f.stream.x[0])
+                else:
+                    S = torch.cat([f.slopes for f in frs]) if len(frs) > 1 else frs[0].slopes
+                    X = torch.cat([f.stream.x for f in frs]) if len(frs) > 1 else frs[0].stream.x
                 if self.keep_inputs:
                     for f in frs:
                         f.x0 = f.stream.x.clone()
@@ -168,7 +183,8 @@ class Server:
                 slopes.append(S)
                 coeffs.append(X)
                 frames.append(frs)
-            solve_multi(plans, slopes, coeffs, n_iter=self.n_iter, warm_start=True)
+            solve_multi(plans, slopes, coeffs, n_iter=self.n_iter, warm_start=True,
+                        graph=self.graphs)
             results = []
             for X, frs in zip(coeffs, frames):
                 for k, f in enumerate(frs):

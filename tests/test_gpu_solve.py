@@ -229,5 +229,20 @@ def test_c4_mixed_sizes_one_launch():
         tol = fp32_tol(S, b, 10, S.jacobi_separable())
         say(f"[c4] {classes[i]['name']} errors {e} tol {tol}")
         assert all(ei < ti for ei, ti in zip(e, tol)), (classes[i]["name"], e, tol)
+    # the same packed solve captured as a graph: every replay equals the eager
+    # result, with eager library work and synchronisations between replays
+    outs = [torch.empty_like(c) for c in coeffs]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            for o in outs:
+                o.fill_(7.0)
+            solve_multi(plans, slopes, outs, n_iter=10, graph=True)
+        stream.synchronize()
+        for i, o in enumerate(outs):
+            assert torch.equal(o, coeffs[i]), (rep, classes[i]["name"])
+        plans[0].apply_A(coeffs[0])
+        torch.cuda.synchronize()
     for p in plans:
         p.close()
