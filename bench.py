@@ -109,7 +109,8 @@ def served_stream(duration_s, rate_hz, n_iter):
                                                  device="cuda")).float() for t in range(8)]
         cfgs[nm] = (cfg, sig)
         fwd.close()
-    srv = Server(cfgs, {nm: nm for nm in names}, dtype="f32", n_iter=n_iter, hip_streams=2)
+    srv = Server(cfgs, {nm: nm for nm in names}, dtype="f32", n_iter=n_iter, hip_streams=4,
+                 tile=16)
     arrivals = sorted((t, nm) for k, nm in enumerate(names)
                       for t in WL.poisson_arrivals(500 + k, rate_hz / len(names), duration_s))
     torch.cuda.synchronize()
@@ -117,8 +118,9 @@ def served_stream(duration_s, rate_hz, n_iter):
     cnt = {nm: 0 for nm in names}
     t0 = time.perf_counter()
     for t, nm in arrivals:
-        while time.perf_counter() - t0 < t:
-            pass
+        wait = t - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)          # releases the interpreter lock to the server threads
         futs.append(srv.submit(nm, pools[nm][cnt[nm] % 8]))
         cnt[nm] += 1
     for f in futs:
@@ -174,7 +176,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the per-frame FP64 comparison")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--cpu-frames", type=int, default=2)
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     args = ap.parse_args()
 

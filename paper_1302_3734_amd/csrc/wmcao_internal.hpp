@@ -42,6 +42,7 @@ enum Part : int { PT_PQ = 0, PT_RZ0, PT_RZ1, PT_RR0, PT_RR1, NPT };
 struct LayerInfo {
     int N;                          // pixels per side
     int k0;                         // levels done by tiled kernels (0..levels-1)
+    int fuse;                       // 1: the level-k0 synthesis tiles rebuild LL_k0 themselves
     int64_t coff;                   // offset in a coefficient / pixel frame vector
     int64_t ll_off[WM_MAXLEV + 1];  // offset of LL_k (k = 1..k0) in a frame's LL scratch
     double D[WM_MAXLEV];            // prior at scale index k (entry k-1), alpha not applied
@@ -96,8 +97,8 @@ struct PlanDev {
     // adjoint-projection footprint of sensor m on layer l: pixel rows
     // fp_x0 .. fp_x0 + fp_h - 1, columns fp_y0 .. fp_y0 + fp_w - 1; its image
     // starts at fp_off in a V_FP frame; fp_rc + 2 * fp_tab holds (first node,
-    // node count) per footprint row, then per footprint column; fp_br rows per
-    // work item.
+    // node count) per footprint row, then per footprint column, then (first,
+    // last) node row per band of fp_br rows (one work item each).
     int fp_x0[WM_MAXW][WM_MAXL], fp_y0[WM_MAXW][WM_MAXL];
     int fp_h[WM_MAXW][WM_MAXL], fp_w[WM_MAXW][WM_MAXL];
     int fp_off[WM_MAXW][WM_MAXL], fp_tab[WM_MAXW][WM_MAXL], fp_br[WM_MAXW][WM_MAXL];
@@ -140,7 +141,7 @@ void launch_idwt_coarse(const JobArgs& a, const Item* items, int n, int in_vec, 
                         int lds_bytes, hipStream_t s);
 template <class T>
 void launch_idwt_tile(const JobArgs& a, const Item* items, int n, int level, int in_vec,
-                      int out_vec, int tile, hipStream_t s);
+                      int out_vec, int tile, int lds_bytes, hipStream_t s);
 template <class T>
 void launch_fdwt_tile(const JobArgs& a, const Item* items, int n, int level, int src, int in_vec,
                       int out_vec, int epi, int aux_vec, int tile, hipStream_t s);
@@ -174,6 +175,7 @@ void launch_axpby(int64_t n, double a, const T* x, double b, const T* y, T* out,
 template <class T>
 void launch_cast_from_double(const double* in, T* out, int64_t n, hipStream_t s);
 
+constexpr int FUSE_LDS = 32 * 1024;   // largest low-pass block a synthesis tile rebuilds
 constexpr int VEC_CHUNK = 4096;   // elements per block of the vector kernels
 constexpr int PROJ_ROWS = 8;      // sensor node rows per block of the projection
 constexpr int SP_K = 2 * WM_MAXCELL;   // doubles per slope-sum record

@@ -109,74 +109,90 @@ __device__ __forceinline__ void load_filters(const PlanDev& P, Acc* hf, Acc* gf)
 
 // One in-place periodic synthesis step on the leading M x M block of A (row
 // stride ld), along y (columns within a row) or along x, staged through
-// registers: x_i = sum over the 3 coarse k with 0 <= i - 2k < 6 of
-// h[i-2k] lo_k + g[i-2k] hi_k.
+// registers.  A work item is one coarse position k of one line and yields the
+// output pair x[2k + par] = sum_t h[par + 2t] lo[k - t] + g[par + 2t] hi[k - t]
+// (par = 0, 1; indices mod M/2), so every filter tap is a compile-time index.
 __device__ void syn_pass(Acc* A, int ld, int M, int along_y, const Acc* hf, const Acc* gf) {
-    const int H = M >> 1, cnt = M * M;
-    Acc reg[WM_QMAX];
+    const int H = M >> 1, cnt = M * H;
+    Acc r0v[WM_QMAX / 2], r1v[WM_QMAX / 2];
 #pragma unroll
-    for (int r = 0; r < WM_QMAX; ++r) {
+    for (int r = 0; r < WM_QMAX / 2; ++r) {
         const int e = threadIdx.x + r * blockDim.x;
         if (e < cnt) {
-            const int row = e / M, col = e - (e / M) * M;
-            const int i = along_y ? col : row;
-            const int base = i >> 1, par = i & 1;
-            Acc acc = 0;
+            int line, k;
+            if (along_y) { line = e / H; k = e - line * H; } else { k = e / M; line = e - k * M; }
+            Acc x0 = 0, x1 = 0;
 #pragma unroll
             for (int t = 0; t < 3; ++t) {
-                int k = base - t;
-                if (k < 0) k += H;
-                const int n = par + 2 * t;
-                const Acc lo = along_y ? A[row * ld + k] : A[k * ld + col];
-                const Acc hi = along_y ? A[row * ld + H + k] : A[(H + k) * ld + col];
-                acc += hf[n] * lo + gf[n] * hi;
+                int kk = k - t;
+                if (kk < 0) kk += H;
+                const Acc lo = along_y ? A[line * ld + kk] : A[kk * ld + line];
+                const Acc hi = along_y ? A[line * ld + H + kk] : A[(H + kk) * ld + line];
+                x0 += hf[2 * t] * lo + gf[2 * t] * hi;
+                x1 += hf[2 * t + 1] * lo + gf[2 * t + 1] * hi;
             }
-            reg[r] = acc;
+            r0v[r] = x0;
+            r1v[r] = x1;
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < WM_QMAX; ++r) {
+    for (int r = 0; r < WM_QMAX / 2; ++r) {
         const int e = threadIdx.x + r * blockDim.x;
         if (e < cnt) {
-            const int row = e / M, col = e - (e / M) * M;
-            A[row * ld + col] = reg[r];
+            int line, k;
+            if (along_y) { line = e / H; k = e - line * H; } else { k = e / M; line = e - k * M; }
+            if (along_y) {
+                A[line * ld + 2 * k] = r0v[r];
+                A[line * ld + 2 * k + 1] = r1v[r];
+            } else {
+                A[(2 * k) * ld + line] = r0v[r];
+                A[(2 * k + 1) * ld + line] = r1v[r];
+            }
         }
     }
     __syncthreads();
 }
 
-// One in-place periodic analysis step: a_c = sum_n h_n x[(2c+n) mod M] into
-// the low half, d_c with g into the high half.
+// One in-place periodic analysis step: a work item is one coarse position c
+// of one line and yields a_c = sum_n h_n x[(2c+n) mod M] (low half) and
+// d_c = sum_n g_n x[(2c+n) mod M] (high half).
 __device__ void ana_pass(Acc* A, int ld, int M, int along_y, const Acc* hf, const Acc* gf) {
-    const int H = M >> 1, cnt = M * M;
-    Acc reg[WM_QMAX];
+    const int H = M >> 1, cnt = M * H;
+    Acc r0v[WM_QMAX / 2], r1v[WM_QMAX / 2];
 #pragma unroll
-    for (int r = 0; r < WM_QMAX; ++r) {
+    for (int r = 0; r < WM_QMAX / 2; ++r) {
         const int e = threadIdx.x + r * blockDim.x;
         if (e < cnt) {
-            const int row = e / M, col = e - (e / M) * M;
-            const int c = along_y ? col : row;
-            const bool hi = c >= H;
-            const int cc = hi ? c - H : c;
-            Acc acc = 0;
+            int line, c;
+            if (along_y) { line = e / H; c = e - line * H; } else { c = e / M; line = e - c * M; }
+            Acc lo = 0, hi = 0;
 #pragma unroll
             for (int n = 0; n < 6; ++n) {
-                int idx = 2 * cc + n;
+                int idx = 2 * c + n;
                 if (idx >= M) idx -= M;
-                const Acc v = along_y ? A[row * ld + idx] : A[idx * ld + col];
-                acc += (hi ? gf[n] : hf[n]) * v;
+                const Acc v = along_y ? A[line * ld + idx] : A[idx * ld + line];
+                lo += hf[n] * v;
+                hi += gf[n] * v;
             }
-            reg[r] = acc;
+            r0v[r] = lo;
+            r1v[r] = hi;
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < WM_QMAX; ++r) {
+    for (int r = 0; r < WM_QMAX / 2; ++r) {
         const int e = threadIdx.x + r * blockDim.x;
         if (e < cnt) {
-            const int row = e / M, col = e - (e / M) * M;
-            A[row * ld + col] = reg[r];
+            int line, c;
+            if (along_y) { line = e / H; c = e - line * H; } else { c = e / M; line = e - c * M; }
+            if (along_y) {
+                A[line * ld + c] = r0v[r];
+                A[line * ld + H + c] = r1v[r];
+            } else {
+                A[c * ld + line] = r0v[r];
+                A[(H + c) * ld + line] = r1v[r];
+            }
         }
     }
     __syncthreads();
@@ -192,24 +208,44 @@ __device__ __forceinline__ void node_stencil(double pa, double pb, int i, int N,
 }
 
 // P^T over a window of PR x PC pixels of layer l starting at (px0, py0)
-// (periodic indices), written into G (row stride ldg, FP64): the sum, in
-// sensor order, of the footprint images of the sensors in mask (k_adjoint).
-// One writer per pixel; no atomics and no barrier.
+// (periodic indices, px0 + PR < 2N), written into G (row stride ldg, FP64):
+// the sum, in sensor order, of the footprint images of the sensors in mask
+// (k_adjoint).  A thread owns one window column and every rstep-th row, so
+// each G entry has one writer: no atomics and no barrier.
 template <class T>
 __device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, int px0, int py0,
                                  int PR, int PC, Acc* G, int ldg, unsigned mask) {
-    for (int e = threadIdx.x; e < PR * PC; e += blockDim.x) {
-        const int r = e / PC, c = e - (e / PC) * PC;
-        const int gx = (px0 + r) % N, gy = (py0 + c) % N;
-        Acc acc = 0;
-        for (int m = 0; m < P.W; ++m) {
-            if (!((mask >> m) & 1u)) continue;
-            const int xr = gx - P.fp_x0[m][l], yc = gy - P.fp_y0[m][l];
-            if (static_cast<unsigned>(xr) < static_cast<unsigned>(P.fp_h[m][l]) &&
-                static_cast<unsigned>(yc) < static_cast<unsigned>(P.fp_w[m][l]))
-                acc += static_cast<Acc>(img[P.fp_off[m][l] + xr * P.fp_w[m][l] + yc]);
+    const int tid = threadIdx.x, bd = blockDim.x;
+    int c0, r0, rstep, cstep;
+    if (PC <= bd) {
+        c0 = tid % PC;
+        r0 = tid / PC;
+        rstep = bd / PC;
+        cstep = PC;
+        if (r0 >= rstep) return;
+    } else {
+        c0 = tid;
+        r0 = 0;
+        rstep = 1;
+        cstep = bd;
+    }
+    for (int c = c0; c < PC; c += cstep) {
+        int gy = py0 + c;
+        if (gy >= N) gy -= N;
+        for (int r = r0; r < PR; r += rstep) G[r * ldg + c] = 0;
+        for (unsigned mm = mask; mm; mm &= mm - 1) {
+            const int m = __ffs(static_cast<int>(mm)) - 1;
+            const int yc = gy - P.fp_y0[m][l], Wf = P.fp_w[m][l];
+            if (yc < 0 || yc >= Wf) continue;
+            const int x0 = P.fp_x0[m][l], Hf = P.fp_h[m][l];
+            const T* im = img + P.fp_off[m][l] + yc;
+            for (int r = r0; r < PR; r += rstep) {
+                int gx = px0 + r;
+                if (gx >= N) gx -= N;
+                const int xr = gx - x0;
+                if (xr >= 0 && xr < Hf) G[r * ldg + c] += static_cast<Acc>(im[xr * Wf]);
+            }
         }
-        G[r * ldg + c] = acc;
     }
 }
 
@@ -237,17 +273,13 @@ k_idwt_coarse(const JobArgs args, const Item* __restrict__ items, int in_vec, in
         syn_pass(A, M0, M, 0, hf, gf);   // undo the x step
         syn_pass(A, M0, M, 1, hf, gf);   // undo the y step
     }
-    T* dst;
-    int ld;
-    if (k0 > 0) {
-        dst = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[k0];
-        ld = M0;
+    if (k0 > 0) {   // low-pass band of the finest coarse level: FP64 scratch
+        double* dst = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[k0];
+        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) dst[e] = A[e];
     } else {
-        dst = vptr<T>(J, out_vec, it.frame) + Ly.coff;
-        ld = N;
+        T* dst = vptr<T>(J, out_vec, it.frame) + Ly.coff;
+        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) dst[e] = static_cast<T>(A[e]);
     }
-    for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x)
-        dst[static_cast<int64_t>(e / M0) * ld + (e % M0)] = static_cast<T>(A[e]);
 }
 
 // One synthesis level k <= k0 over a TS x TS output tile: reads the low-pass
@@ -271,56 +303,81 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
     Acc hf[6], gf[6];
     load_filters(P, hf, gf);
     const T* src = vptr<T>(J, in_vec, it.frame) + Ly.coff;
-    const T* ll = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[level];
+    const double* ll = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level];
+    if (level == Ly.k0 && Ly.fuse) {
+        // rebuild LL_k0 = the synthesis of levels J..k0+1 of the coarse block
+        // (Mallat top-left M0 x M0) in LDS; every tile of this level repeats it
+        extern __shared__ __align__(16) unsigned char smem_raw[];
+        Acc* Ac = reinterpret_cast<Acc*>(smem_raw);
+        const int M0 = H;
+        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x)
+            Ac[e] = src[static_cast<int64_t>(e / M0) * N + (e % M0)];
+        __syncthreads();
+        for (int lev = P.levels; lev > level; --lev) {
+            const int Mc = N >> (lev - 1);
+            syn_pass(Ac, M0, Mc, 0, hf, gf);
+            syn_pass(Ac, M0, Mc, 1, hf, gf);
+        }
+        ll = Ac;
+    }
     const int cx0 = (x0 >> 1) - 2, cy0 = (y0 >> 1) - 2;
     for (int e = threadIdx.x; e < CW * CW; e += blockDim.x) {
         const int a = e / CW, b = e % CW;
-        int gx = (cx0 + a) % H;
-        if (gx < 0) gx += H;
-        int gy = (cy0 + b) % H;
-        if (gy < 0) gy += H;
+        int gx = cx0 + a, gy = cy0 + b;   // periodic wrap (|offset| < 2H)
+        gx += gx < 0 ? H : 0;
+        gy += gy < 0 ? H : 0;
+        while (gx >= H) gx -= H;
+        while (gy >= H) gy -= H;
         sLL[a][b] = ll[gx * H + gy];
         sLH[a][b] = src[static_cast<int64_t>(gx) * N + H + gy];
         sHL[a][b] = src[static_cast<int64_t>(H + gx) * N + gy];
         sHH[a][b] = src[static_cast<int64_t>(H + gx) * N + H + gy];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < TS * CW; e += blockDim.x) {
-        const int li = e / CW, b = e % CW;
-        const int i = x0 + li;
-        const int base = (i >> 1) - cx0, par = i & 1;
-        Acc al = 0, ah = 0;
+    // along x: output rows 2p and 2p + 1 (x0 is even) from coarse rows p + 2 - t
+    for (int e = threadIdx.x; e < (TS / 2) * CW; e += blockDim.x) {
+        const int pr = e / CW, b = e % CW;
+        Acc al0 = 0, al1 = 0, ah0 = 0, ah1 = 0;
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-            const int k = base - t, n = par + 2 * t;
-            al += hf[n] * sLL[k][b] + gf[n] * sHL[k][b];
-            ah += hf[n] * sLH[k][b] + gf[n] * sHH[k][b];
+            const int k = pr + 2 - t;
+            const Acc ll_ = sLL[k][b], hl = sHL[k][b], lh = sLH[k][b], hh = sHH[k][b];
+            al0 += hf[2 * t] * ll_ + gf[2 * t] * hl;
+            al1 += hf[2 * t + 1] * ll_ + gf[2 * t + 1] * hl;
+            ah0 += hf[2 * t] * lh + gf[2 * t] * hh;
+            ah1 += hf[2 * t + 1] * lh + gf[2 * t + 1] * hh;
         }
-        sAL[li][b] = al;
-        sAH[li][b] = ah;
+        sAL[2 * pr][b] = al0;
+        sAL[2 * pr + 1][b] = al1;
+        sAH[2 * pr][b] = ah0;
+        sAH[2 * pr + 1][b] = ah1;
     }
     __syncthreads();
-    T* dst;
-    int ld;
-    if (level > 1) {
-        dst = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[level - 1];
-        ld = M;
-    } else {
-        dst = vptr<T>(J, out_vec, it.frame) + Ly.coff;
-        ld = N;
-    }
-    for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
-        const int li = e / TS, lj = e % TS;
-        const int i = x0 + li, j = y0 + lj;
-        if (i >= M || j >= M) continue;
-        const int base = (j >> 1) - cy0, par = j & 1;
-        Acc v = 0;
+    // level > 1: the next finer low-pass band, FP64 scratch; level 1: pixels
+    double* dll = level > 1 ? vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level - 1] : nullptr;
+    T* dst = vptr<T>(J, out_vec, it.frame) + Ly.coff;
+    const int ld = level > 1 ? M : N;
+    // along y: output columns 2q and 2q + 1 from coarse columns q + 2 - t
+    for (int e = threadIdx.x; e < TS * (TS / 2); e += blockDim.x) {
+        const int li = e / (TS / 2), q = e % (TS / 2);
+        const int i = x0 + li, j = y0 + 2 * q;
+        Acc v0 = 0, v1 = 0;
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-            const int k = base - t, n = par + 2 * t;
-            v += hf[n] * sAL[li][k] + gf[n] * sAH[li][k];
+            const int k = q + 2 - t;
+            const Acc lo = sAL[li][k], hi = sAH[li][k];
+            v0 += hf[2 * t] * lo + gf[2 * t] * hi;
+            v1 += hf[2 * t + 1] * lo + gf[2 * t + 1] * hi;
         }
-        dst[static_cast<int64_t>(i) * ld + j] = static_cast<T>(v);
+        if (i >= M || j >= M) continue;   // M is even, so j + 1 < M too
+        const int64_t o = static_cast<int64_t>(i) * ld + j;
+        if (level > 1) {
+            dll[o] = v0;
+            dll[o + 1] = v1;
+        } else {
+            dst[o] = static_cast<T>(v0);
+            dst[o + 1] = static_cast<T>(v1);
+        }
     }
 }
 
@@ -353,19 +410,17 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
                             &sA[0][0], PW + 1,
                             static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a] + it.b]));
     } else {
-        const T* in;
-        int ld;
-        if (level > 1) {
-            in = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[level - 1];
-            ld = M;
-        } else {
-            in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
-            ld = N;
-        }
+        // level > 1: the low-pass band of the level below (FP64 scratch)
+        const double* ind = level > 1 ? vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level - 1] : nullptr;
+        const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
+        const int ld = level > 1 ? M : N;
         for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) {
             const int a = e / PW, b = e % PW;
-            const int gx = (px0 + a) % M, gy = (py0 + b) % M;
-            sA[a][b] = in[static_cast<int64_t>(gx) * ld + gy];
+            int gx = px0 + a, gy = py0 + b;   // periodic wrap
+            while (gx >= M) gx -= M;
+            while (gy >= M) gy -= M;
+            const int64_t gi = static_cast<int64_t>(gx) * ld + gy;
+            sA[a][b] = level > 1 ? ind[gi] : static_cast<Acc>(in[gi]);
         }
     }
     __syncthreads();
@@ -385,7 +440,7 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     T* out = vptr<T>(J, out_vec, it.frame) + Ly.coff;
     const T* pv = (epi == EPI_APPLY) ? vptr<T>(J, aux_vec, it.frame) + Ly.coff : nullptr;
     const Acc aD = P.alpha * Ly.D[level - 1];
-    T* llo = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[level];
+    double* llo = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level];
     double acc = 0.0;
     for (int e = threadIdx.x; e < HT * HT; e += blockDim.x) {
         const int c1 = e / HT, c2 = e % HT;
@@ -400,7 +455,7 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
             hh += gf[n] * h;
         }
         if (X < H && Y < H) {
-            llo[X * H + Y] = static_cast<T>(ll);
+            llo[X * H + Y] = ll;
             const int64_t iLH = static_cast<int64_t>(X) * N + H + Y;
             const int64_t iHL = static_cast<int64_t>(H + X) * N + Y;
             const int64_t iHH = static_cast<int64_t>(H + X) * N + H + Y;
@@ -446,7 +501,7 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
     Acc hf[6], gf[6];
     load_filters(P, hf, gf);
     if (k0 > 0) {
-        const T* ll = vptr<T>(J, V_LL, it.frame) + Ly.ll_off[k0];
+        const double* ll = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[k0];
         for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = ll[e];
     } else if (src == SRC_PIX) {
         const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
@@ -493,37 +548,48 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
 // band, reduced in a fixed order by k_weights).  u is kept in FP64 so that the
 // Fried differences do not cancel single-precision digits.
 template <class T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int sums) {
     __shared__ double su[(PROJ_ROWS + 1) * (WM_NSUB_MAX + 1)];
     __shared__ double red[68];
+    // bilinear stencils of the block's node rows and of every node column, per layer
+    __shared__ int ri0[WM_MAXL][PROJ_ROWS + 1], cj0[WM_MAXL][WM_NSUB_MAX + 1];
+    __shared__ double rtw[WM_MAXL][PROJ_ROWS + 1], csw[WM_MAXL][WM_NSUB_MAX + 1];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const int m = it.a;
     const WfsInfo& w = P.wfs[m];
-    const int nn = w.nn;
+    const int nn = w.nn, L = P.L;
     const int r0 = it.b * PROJ_ROWS;
     const int rows = min(PROJ_ROWS, nn - r0);
     const bool slopes = sums && w.kind == 0;
     const int rows_c = slopes ? min(PROJ_ROWS + 1, nn - r0) : rows;
+    const int K = rows_c + nn;
+    for (int e = threadIdx.x; e < L * K; e += blockDim.x) {
+        const int l = e / K, k = e - (e / K) * K;
+        const int N = P.layer[l].N;
+        if (k < rows_c)
+            node_stencil(P.pa[m][l], P.pb[0][m][l], r0 + k, N, ri0[l][k], rtw[l][k]);
+        else
+            node_stencil(P.pa[m][l], P.pb[1][m][l], k - rows_c, N, cj0[l][k - rows_c],
+                         csw[l][k - rows_c]);
+    }
+    __syncthreads();
     const T* phi = vptr<T>(J, in_vec, it.frame);
     double* u = vptr<double>(J, V_U, it.frame) + w.node_off;
     for (int e = threadIdx.x; e < rows_c * nn; e += blockDim.x) {
-        const int i = r0 + e / nn, j = e % nn;
+        const int li = e / nn, j = e - (e / nn) * nn;
         Acc acc = 0;
         // four layers per step: their samples are loaded before any is used
-        for (int l0 = 0; l0 < P.L; l0 += 4) {
-            Acc v[4][4], tw[4], sw[4];
+        for (int l0 = 0; l0 < L; l0 += 4) {
+            Acc v[4][4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int l = l0 + k;
-                if (l < P.L) {
+                if (l < L) {
                     const int N = P.layer[l].N;
-                    int i0, j0;
-                    node_stencil(P.pa[m][l], P.pb[0][m][l], i, N, i0, tw[k]);
-                    node_stencil(P.pa[m][l], P.pb[1][m][l], j, N, j0, sw[k]);
-                    const T* f = phi + P.layer[l].coff + static_cast<int64_t>(i0) * N + j0;
+                    const T* f = phi + P.layer[l].coff + static_cast<int64_t>(ri0[l][li]) * N + cj0[l][j];
                     v[k][0] = f[0];
                     v[k][1] = f[1];
                     v[k][2] = f[N];
@@ -532,14 +598,15 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (l0 + k < P.L) {
-                    const Acc t = tw[k], s = sw[k];
+                const int l = l0 + k;
+                if (l < L) {
+                    const Acc t = rtw[l][li], s = csw[l][j];
                     acc += (1.0 - t) * ((1.0 - s) * v[k][0] + s * v[k][1]) +
                            t * ((1.0 - s) * v[k][2] + s * v[k][3]);
                 }
             }
         }
-        if (e < rows * nn) u[i * nn + j] = acc;
+        if (e < rows * nn) u[(r0 + li) * nn + j] = acc;
         if (slopes) su[e] = acc;
     }
     if (!slopes) return;
@@ -738,39 +805,40 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
 // one coalesced sweep; then T[r][b] = sum_a wx(a, r) V[a][b] for the band's
 // pixel rows and every node column (LDS, FP64), and g[r][c] = sum_b wy(b, c)
 // T[r][b].  The weights are the forward bilinear ones read backwards: node a
-// feeds pixel i0_a with 1 - t_a and pixel i0_a + 1 with t_a.  No atomics.
+// feeds pixel i0_a with 1 - t_a and pixel i0_a + 1 with t_a.  A pixel row or
+// column is fed by at most ADJ_TAPS consecutive nodes on the fast path (node
+// spacing of at least half a pixel); denser node grids take the general loop.
 // LDS: the staged node rows (storage type) and T, sized by the plan.
+constexpr int ADJ_TAPS = 4;
+
+__device__ __forceinline__ Acc adj_weight(double pa, double pb, int i, int N, int g) {
+    int i0;
+    Acc t;
+    node_stencil(pa, pb, i, N, i0, t);
+    return i0 == g ? 1.0 - t : (i0 + 1 == g ? t : 0.0);
+}
+
 template <class T>
 __global__ void __launch_bounds__(256)
 k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int out_vec) {
-    __shared__ int si0[WM_NSUB_MAX + 1], sj0[WM_NSUB_MAX + 1];
-    __shared__ double sti[WM_NSUB_MAX + 1], stj[WM_NSUB_MAX + 1];
+    __shared__ double wrow[ADJ_BAND][ADJ_TAPS];
+    __shared__ int frow[ADJ_BAND], crow[ADJ_BAND];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const int m = it.a, l = it.b;
     const int nn = P.wfs[m].nn, N = P.layer[l].N;
+    const double pa = P.pa[m][l], pbx = P.pb[0][m][l], pby = P.pb[1][m][l];
     const int x0 = P.fp_x0[m][l], y0 = P.fp_y0[m][l];
-    const int Hf = P.fp_h[m][l], Wf = P.fp_w[m][l];
-    const int r0 = it.slot * P.fp_br[m][l], r1 = min(Hf, r0 + P.fp_br[m][l]);
-    const int BR = r1 - r0;
+    const int Hf = P.fp_h[m][l], Wf = P.fp_w[m][l], br = P.fp_br[m][l];
+    const int r0 = it.slot * br, BR = min(Hf, r0 + br) - r0;
     const int* rt = P.fp_rc + 2 * P.fp_tab[m][l];
     const int* ct = rt + 2 * Hf;
-    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
-        node_stencil(P.pa[m][l], P.pb[0][m][l], i, N, si0[i], sti[i]);
-        node_stencil(P.pa[m][l], P.pb[1][m][l], i, N, sj0[i], stj[i]);
-    }
-    // node rows the band reads (rows are monotone in the node index)
-    int alo = nn, ahi = -1;
-    for (int r = r0; r < r1; ++r)
-        if (rt[2 * r + 1] > 0) {
-            alo = min(alo, rt[2 * r]);
-            ahi = max(ahi, rt[2 * r] + rt[2 * r + 1] - 1);
-        }
-    T* out = vptr<T>(J, out_vec, it.frame) + P.fp_off[m][l];
+    const int alo = ct[2 * Wf + 2 * it.slot], ahi = ct[2 * Wf + 2 * it.slot + 1];
+    T* out = vptr<T>(J, out_vec, it.frame) + P.fp_off[m][l] + r0 * Wf;
     if (ahi < alo) {
-        for (int e = threadIdx.x; e < BR * Wf; e += blockDim.x) out[r0 * Wf + e] = T(0);
+        for (int e = threadIdx.x; e < BR * Wf; e += blockDim.x) out[e] = T(0);
         return;
     }
     const int NR = ahi - alo + 1;
@@ -778,49 +846,67 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
     Acc* Tb = reinterpret_cast<Acc*>(smem_raw + ((static_cast<size_t>(NR) * nn * sizeof(T) + 15) & ~size_t(15)));
     const T* V = vptr<T>(J, in_vec, it.frame) + P.wfs[m].node_off + static_cast<int64_t>(alo) * nn;
     for (int e = threadIdx.x; e < NR * nn; e += blockDim.x) Vs[e] = V[e];
-    __syncthreads();
-    for (int e = threadIdx.x; e < BR * nn; e += blockDim.x) {
-        const int lr = e / nn, b = e - (e / nn) * nn;
-        const int r = r0 + lr, f = rt[2 * r], cnt = rt[2 * r + 1], gx = x0 + r;
-        Acc acc = 0;
-        for (int q = 0; q < cnt; ++q) {
-            const int a = f + q;
-            acc += (si0[a] == gx ? 1.0 - sti[a] : sti[a]) * static_cast<Acc>(Vs[(a - alo) * nn + b]);
-        }
-        Tb[e] = acc;
+    // row taps of the band: first staged row, count, weights
+    if (threadIdx.x < BR) {
+        const int r = r0 + threadIdx.x, f = rt[2 * r], cnt = rt[2 * r + 1];
+        frow[threadIdx.x] = cnt > 0 ? f - alo : 0;   // a row no node reaches reads row 0 with weight 0
+        crow[threadIdx.x] = cnt;
+#pragma unroll
+        for (int q = 0; q < ADJ_TAPS; ++q)
+            wrow[threadIdx.x][q] = q < cnt ? adj_weight(pa, pbx, f + q, N, x0 + r) : 0.0;
     }
     __syncthreads();
-    // a thread owns one footprint column: its node range and weights are read
-    // once, then every G-th row of the band
     const int bd = blockDim.x;
-    const int G = Wf < bd ? bd / Wf : 1;
-    const int g = threadIdx.x / (Wf < bd ? Wf : bd);
-    const int cstep = Wf < bd ? Wf : bd;
-    if (g >= G) return;
-    for (int c = Wf < bd ? threadIdx.x % Wf : threadIdx.x; c < Wf; c += cstep) {
+    // stage 1: a thread owns one node column and every G1-th band row
+    {
+        const int G1 = nn < bd ? bd / nn : 1, g1 = threadIdx.x / (nn < bd ? nn : bd);
+        const int b0 = nn < bd ? threadIdx.x % nn : threadIdx.x, bstep = nn < bd ? nn : bd;
+        if (g1 < G1)
+            for (int b = b0; b < nn; b += bstep)
+                for (int lr = g1; lr < BR; lr += G1) {
+                    const int f = frow[lr], cnt = crow[lr];
+                    Acc acc = 0;
+                    if (cnt <= ADJ_TAPS) {
+#pragma unroll
+                        for (int q = 0; q < ADJ_TAPS; ++q)
+                            acc += wrow[lr][q] * static_cast<Acc>(Vs[min(f + q, NR - 1) * nn + b]);
+                    } else {
+                        const int r = r0 + lr;
+                        for (int q = 0; q < cnt; ++q)
+                            acc += adj_weight(pa, pbx, alo + f + q, N, x0 + r) *
+                                   static_cast<Acc>(Vs[(f + q) * nn + b]);
+                    }
+                    Tb[lr * nn + b] = acc;
+                }
+    }
+    __syncthreads();
+    // stage 2: a thread owns one footprint column and every G2-th band row
+    const int G2 = Wf < bd ? bd / Wf : 1, g2 = threadIdx.x / (Wf < bd ? Wf : bd);
+    const int c0 = Wf < bd ? threadIdx.x % Wf : threadIdx.x, cstep = Wf < bd ? Wf : bd;
+    if (g2 >= G2) return;
+    for (int c = c0; c < Wf; c += cstep) {
         const int f = ct[2 * c], cnt = ct[2 * c + 1], gy = y0 + c;
-        if (cnt <= 4) {
-            Acc w[4];
+        if (cnt <= ADJ_TAPS) {
+            Acc w[ADJ_TAPS];
+            int ix[ADJ_TAPS];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                w[q] = q < cnt ? (sj0[f + q] == gy ? 1.0 - stj[f + q] : stj[f + q]) : 0.0;
-            for (int lr = g; lr < BR; lr += G) {
-                const Acc* tr = Tb + lr * nn + f;
-                Acc acc = 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (q < cnt) acc += w[q] * tr[q];
-                out[(r0 + lr) * Wf + c] = static_cast<T>(acc);
+            for (int q = 0; q < ADJ_TAPS; ++q) {
+                w[q] = q < cnt ? adj_weight(pa, pby, f + q, N, gy) : 0.0;
+                ix[q] = min(f + q, nn - 1);
             }
-        } else {
-            for (int lr = g; lr < BR; lr += G) {
+            for (int lr = g2; lr < BR; lr += G2) {
                 const Acc* tr = Tb + lr * nn;
                 Acc acc = 0;
-                for (int q = 0; q < cnt; ++q) {
-                    const int b = f + q;
-                    acc += (sj0[b] == gy ? 1.0 - stj[b] : stj[b]) * tr[b];
-                }
-                out[(r0 + lr) * Wf + c] = static_cast<T>(acc);
+#pragma unroll
+                for (int q = 0; q < ADJ_TAPS; ++q) acc += w[q] * tr[ix[q]];
+                out[lr * Wf + c] = static_cast<T>(acc);
+            }
+        } else {
+            for (int lr = g2; lr < BR; lr += G2) {
+                const Acc* tr = Tb + lr * nn;
+                Acc acc = 0;
+                for (int q = 0; q < cnt; ++q) acc += adj_weight(pa, pby, f + q, N, gy) * tr[f + q];
+                out[lr * Wf + c] = static_cast<T>(acc);
             }
         }
     }
@@ -1486,14 +1572,14 @@ void launch_idwt_coarse(const JobArgs& a, const Item* items, int n, int in_vec, 
 
 template <class T>
 void launch_idwt_tile(const JobArgs& a, const Item* items, int n, int level, int in_vec,
-                      int out_vec, int tile, hipStream_t s) {
+                      int out_vec, int tile, int lds_bytes, hipStream_t s) {
     if (n <= 0) return;
     if (tile == 16)
-        hipLaunchKernelGGL((k_idwt_tile<T, 16>), dim3(n), dim3(256), 0, s, a, items, level, in_vec, out_vec);
+        hipLaunchKernelGGL((k_idwt_tile<T, 16>), dim3(n), dim3(256), lds_bytes, s, a, items, level, in_vec, out_vec);
     else if (tile == 64)
-        hipLaunchKernelGGL((k_idwt_tile<T, 64>), dim3(n), dim3(256), 0, s, a, items, level, in_vec, out_vec);
+        hipLaunchKernelGGL((k_idwt_tile<T, 64>), dim3(n), dim3(256), lds_bytes, s, a, items, level, in_vec, out_vec);
     else
-        hipLaunchKernelGGL((k_idwt_tile<T, 32>), dim3(n), dim3(256), 0, s, a, items, level, in_vec, out_vec);
+        hipLaunchKernelGGL((k_idwt_tile<T, 32>), dim3(n), dim3(256), lds_bytes, s, a, items, level, in_vec, out_vec);
 }
 
 template <class T>
@@ -1519,7 +1605,7 @@ void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int
 template <class T>
 void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(256), 0, s, a, items, in_vec, sums);
+    hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(512), 0, s, a, items, in_vec, sums);
 }
 
 template <class T>
@@ -1601,6 +1687,12 @@ static void allow_full_lds(K* k) {
 void configure_kernels() {
     allow_full_lds(&k_idwt_coarse<float>);
     allow_full_lds(&k_idwt_coarse<double>);
+    allow_full_lds(&k_idwt_tile<float, 16>);
+    allow_full_lds(&k_idwt_tile<float, 32>);
+    allow_full_lds(&k_idwt_tile<float, 64>);
+    allow_full_lds(&k_idwt_tile<double, 16>);
+    allow_full_lds(&k_idwt_tile<double, 32>);
+    allow_full_lds(&k_idwt_tile<double, 64>);
     allow_full_lds(&k_fdwt_coarse<float>);
     allow_full_lds(&k_fdwt_coarse<double>);
     allow_full_lds(&k_adjoint<float>);
@@ -1613,7 +1705,7 @@ void configure_kernels() {
 
 #define WM_INSTANTIATE(T)                                                                       \
     template void launch_idwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, hipStream_t); \
-    template void launch_idwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
+    template void launch_idwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, int, hipStream_t); \
     template void launch_fdwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, int, hipStream_t); \
     template void launch_fdwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, hipStream_t); \
     template void launch_sensor<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \

@@ -47,8 +47,11 @@ struct DevBuf {
 struct Sched {
     // Item lists per stage, on the device.
     std::unique_ptr<DevBuf> buf;
-    const Item* coarse = nullptr;
+    const Item* coarse = nullptr;       // every layer (analysis)
     int n_coarse = 0;
+    const Item* coarse_syn = nullptr;   // layers whose synthesis tiles do not rebuild LL_k0
+    int n_coarse_syn = 0;
+    int lds_idwt_lvl[WM_MAXLEV + 1] = {};   // dynamic LDS of the level-k synthesis tiles
     const Item* tiled[WM_MAXLEV + 1] = {};
     int n_tiled[WM_MAXLEV + 1] = {};
     const Item* sensor = nullptr;
@@ -250,7 +253,8 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // partials into slots 0.. in the order level-1 tiles, level-2 tiles, ...,
 // coarse blocks; the vector passes use one slot per chunk.
 int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
-    std::vector<Item> coarse, sensor, vec, proj, adj;
+    std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj;
+    int lds_lvl[WM_MAXLEV + 1] = {};
     std::vector<Item> tiled[WM_MAXLEV + 1];
     int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0, lds_a = 0;
     for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
@@ -270,6 +274,9 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
             for (int l = 0; l < P->L; ++l) {
                 coarse.push_back(Item{jp, f, l, 0, slot++, 0, 0, 0});
                 const LayerInfo& Ly = P->host.layer[l];
+                if (!Ly.fuse) coarse_syn.push_back(coarse.back());
+                if (Ly.fuse)
+                    lds_lvl[Ly.k0] = std::max(lds_lvl[Ly.k0], (Ly.N >> Ly.k0) * (Ly.N >> Ly.k0) * 8);
                 const int N = Ly.N, M0 = N >> Ly.k0;
                 lds_i = std::max(lds_i, M0 * M0 * 8);
                 lds_f = std::max(lds_f, M0 * M0 * 8);
@@ -295,18 +302,21 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
         const double e = static_cast<double>(P->esz) * jobs[jp].count;
         const double Q = static_cast<double>(P->n_nodes), n = static_cast<double>(P->n);
         bool gathers_tile = false, gathers_coarse = false;
+        const double c8 = 8.0 * jobs[jp].count;     // low-pass scratch bands are FP64
         for (int l = 0; l < P->L; ++l) {
             const LayerInfo& Ly = P->host.layer[l];
-            const double M0 = Ly.N >> Ly.k0;
-            S->b_idwt_coarse += 2 * M0 * M0 * e;
-            S->b_fdwt_coarse[0] += (Ly.k0 ? 2 : 1) * M0 * M0 * e;
-            S->b_fdwt_coarse[1] += (Ly.k0 ? 3 : 2) * M0 * M0 * e;
+            const double M0 = Ly.N >> Ly.k0, B0 = M0 * M0;
+            if (Ly.fuse)   // the level-k0 tiles read the coarse block instead of LL_k0
+                S->b_idwt_tile[Ly.k0] += B0 * e - B0 * c8;
+            else
+                S->b_idwt_coarse += B0 * e + B0 * (Ly.k0 ? c8 : e);
+            for (int a = 0; a < 2; ++a) S->b_fdwt_coarse[a] += (Ly.k0 ? B0 * c8 : 0) + B0 * e + (a ? B0 * e : 0);
             gathers_coarse = gathers_coarse || Ly.k0 == 0;
             for (int k = 1; k <= Ly.k0; ++k) {
-                const double M = Ly.N >> (k - 1);
-                S->b_idwt_tile[k] += 2 * M * M * e;
-                S->b_fdwt_tile[0][k] += (k == 1 ? 1 : 2) * M * M * e;
-                S->b_fdwt_tile[1][k] += (k == 1 ? 1.75 : 2.75) * M * M * e;
+                const double M = Ly.N >> (k - 1), Hq = (M / 2) * (M / 2);
+                S->b_idwt_tile[k] += Hq * c8 + 3 * Hq * e + M * M * (k > 1 ? c8 : e);
+                for (int a = 0; a < 2; ++a)
+                    S->b_fdwt_tile[a][k] += (k > 1 ? M * M * c8 : 0) + Hq * c8 + 3 * Hq * e + (a ? 3 * Hq * e : 0);
                 gathers_tile = gathers_tile || k == 1;
             }
         }
@@ -333,6 +343,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
         all.insert(all.end(), v.begin(), v.end());
     };
     add(coarse);
+    add(coarse_syn);
     add(sensor);
     add(vec);
     add(proj);
@@ -346,17 +357,20 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     const Item* base = static_cast<const Item*>(S->buf->p);
     S->coarse = base + offs[0];
     S->n_coarse = static_cast<int>(coarse.size());
-    S->sensor = base + offs[1];
+    S->coarse_syn = base + offs[1];
+    S->n_coarse_syn = static_cast<int>(coarse_syn.size());
+    S->sensor = base + offs[2];
     S->n_sensor = static_cast<int>(sensor.size());
-    S->vec = base + offs[2];
+    S->vec = base + offs[3];
     S->n_vec = static_cast<int>(vec.size());
-    S->proj = base + offs[3];
+    S->proj = base + offs[4];
     S->n_proj = static_cast<int>(proj.size());
-    S->adj = base + offs[4];
+    S->adj = base + offs[5];
     S->n_adj = static_cast<int>(adj.size());
     S->lds_adj = lds_a;
+    for (int k = 0; k <= WM_MAXLEV; ++k) S->lds_idwt_lvl[k] = lds_lvl[k];
     for (int k = 1; k <= WM_MAXLEV; ++k) {
-        S->tiled[k] = base + offs[4 + k];
+        S->tiled[k] = base + offs[5 + k];
         S->n_tiled[k] = static_cast<int>(tiled[k].size());
     }
     S->maxk0 = maxk0;
@@ -428,12 +442,14 @@ JobPlan make_jobplan(wmcao_plan_s* p, int nframes) {
 // ------------------------------------------------------- stage drivers ----
 template <class T>
 void run_idwt(const JobArgs& a, const Sched& S, int in_vec, int out_vec, hipStream_t s) {
-    timed(WMCAO_K_IDWT_COARSE, S.b_idwt_coarse, s, [&] {
-        launch_idwt_coarse<T>(a, S.coarse, S.n_coarse, in_vec, out_vec, S.lds_idwt, s);
-    });
+    if (S.n_coarse_syn > 0)
+        timed(WMCAO_K_IDWT_COARSE, S.b_idwt_coarse, s, [&] {
+            launch_idwt_coarse<T>(a, S.coarse_syn, S.n_coarse_syn, in_vec, out_vec, S.lds_idwt, s);
+        });
     for (int k = S.maxk0; k >= 1; --k)
         timed(WMCAO_K_IDWT_TILE, S.b_idwt_tile[k], s, [&] {
-            launch_idwt_tile<T>(a, S.tiled[k], S.n_tiled[k], k, in_vec, out_vec, S.tile, s);
+            launch_idwt_tile<T>(a, S.tiled[k], S.n_tiled[k], k, in_vec, out_vec, S.tile,
+                                S.lds_idwt_lvl[k], s);
         });
 }
 
@@ -678,7 +694,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     p->max_batch = opts->max_batch;
     p->tile = opts->tile ? opts->tile : 32;
     // LDS of the whole-band wavelet block (FP64): 32 KB keeps it at <= 64 x 64
-    p->lds_budget = opts->lds_budget > 0 ? opts->lds_budget : 32 * 1024;
+    p->lds_budget = opts->lds_budget > 0 ? opts->lds_budget : 8 * 1024;
     p->lds_budget = std::min(p->lds_budget, 128 * 1024);
     p->resid_replace = opts->resid_replace_every;
     PlanDev& H = p->host;
@@ -708,6 +724,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         if (M0 * M0 * 8 > 128 * 1024 || M0 * M0 > 1024 * WM_QMAX)
             return fail(WMCAO_ERR_UNSUPPORTED, "layer too large for the wavelet kernels");
         Ly.k0 = k0;
+        Ly.fuse = k0 >= 1 && M0 * M0 * 8 <= FUSE_LDS;
         for (int k = 1; k <= k0; ++k) {
             Ly.ll_off[k] = lloff;
             lloff += static_cast<int64_t>(N >> k) * (N >> k);
@@ -958,6 +975,19 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             if (br < 1)
                 return fail(WMCAO_ERR_UNSUPPORTED, "sensor footprint too wide for the adjoint projection");
             H.fp_br[m][l] = br;
+            // node rows each band reads: (first, last), after the row and column records
+            for (int r0 = 0; r0 < len[0]; r0 += br) {
+                int alo = nn, ahi = -1;
+                for (int r = r0; r < std::min(len[0], r0 + br); ++r) {
+                    const int f = fprc[2 * (tab + r)], c = fprc[2 * (tab + r) + 1];
+                    if (c > 0) {
+                        alo = std::min(alo, f);
+                        ahi = std::max(ahi, f + c - 1);
+                    }
+                }
+                fprc.push_back(alo);
+                fprc.push_back(ahi);
+            }
             p->lds_adjoint = std::max(p->lds_adjoint, need);
         }
     }
@@ -1040,7 +1070,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     if (!(p->vp = p->alloc(ve, &rc))) return rc;
     if (!(p->vq = p->alloc(ve, &rc))) return rc;
     if (!(p->vphi = p->alloc(ve, &rc))) return rc;
-    if (!(p->vll = p->alloc(static_cast<size_t>(p->ll_size) * B * p->esz, &rc))) return rc;
+    if (!(p->vll = p->alloc(static_cast<size_t>(p->ll_size) * B * 8, &rc))) return rc;   // FP64
     if (!(p->vnode = p->alloc(static_cast<size_t>(p->n_nodes) * B * p->esz, &rc))) return rc;
     if (!(p->vfp = p->alloc(static_cast<size_t>(p->n_fpimg) * B * p->esz, &rc))) return rc;
     if (!(p->vspart = static_cast<double*>(p->alloc(static_cast<size_t>(p->n_spart) * B * 8, &rc))))

@@ -57,10 +57,11 @@ class Server:
     configs: {name: (cfg dict, sigmas)}; streams: {stream name: config name}.
     hbm_budget: bytes that frames in flight may reserve (default: half of the
     free device memory at start).  keep_inputs: keep each frame's warm start
-    (for invariance checks)."""
+    (for invariance checks).  graphs: replay captured launches.  tile: tile
+    edge of the wavelet kernels (0 = library default; 16 favours latency)."""
 
     def __init__(self, configs, streams, dtype="f32", n_iter=10, hip_streams=2,
-                 hbm_budget=None, keep_inputs=False, graphs=True):
+                 hbm_budget=None, keep_inputs=False, graphs=True, tile=0):
         self.dtype = dtype
         self.n_iter = int(n_iter)
         self.keep_inputs = keep_inputs
@@ -68,7 +69,8 @@ class Server:
         self.hip_streams = [torch.cuda.Stream() for _ in range(hip_streams)]
         count = collections.Counter(streams.values())
         # one plan per (configuration, HIP stream), batch = streams of that config
-        self.plans = {c: [Plan(cfg, sig, dtype=dtype, max_batch=count[c]) for _ in range(hip_streams)]
+        self.plans = {c: [Plan(cfg, sig, dtype=dtype, max_batch=count[c], tile=tile)
+                          for _ in range(hip_streams)]
                       for c, (cfg, sig) in configs.items() if count[c]}
         self.n = {c: p[0].n for c, p in self.plans.items()}
         self.n_slopes = {c: p[0].n_slopes for c, p in self.plans.items()}

@@ -62,19 +62,20 @@ def to_np(t):
 def fp32_spread(S, b, k, J=None, x0=None):
     """Rounding sensitivity of the oracle's k-step PCG iterate at FP32 level.
 
-    Runs the oracle's PCG (FP64 arithmetic) three times with FP32 rounding
-    inserted where an FP32 implementation stores values: (i) the CG vectors,
-    (ii) the CG vectors and the layer pixel fields, (iii) the right side, the
-    preconditioner, the layer fields and the adjoint node fields.  Returns
-    the largest deviation (e_x, per-layer e_phi, e_res) from the plain FP64
-    iterate: the band within which any FP32-storage implementation of the
-    same algorithm lands on this frame."""
+    Runs the oracle's PCG (FP64 arithmetic) with FP32 rounding inserted where
+    an FP32 implementation stores values: (i) the CG vectors, (ii) the CG
+    vectors and the layer pixel fields, (iii) the right side, the
+    preconditioner, the layer fields and the adjoint node fields, (iv) all of
+    these plus each sensor's adjoint contribution to each layer.  Returns the
+    largest deviation (e_x, per-layer e_phi, e_res) from the plain FP64
+    iterate: the band within which an FP32-storage implementation of the same
+    algorithm lands on this frame."""
     f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
     ident = lambda a: a
     x_ref, _ = O.pcg(S.apply_A, b, k, x0=x0, jacobi=J)
     Jd = np.ones(S.n) if J is None else J
 
-    def apply_rounded(c, rphi, rv):
+    def apply_rounded(c, rphi, rv, rimg):
         phi = S.to_layers(c)
         if rphi:
             phi = [f32(p) for p in phi]
@@ -85,22 +86,24 @@ def fp32_spread(S, b, k, J=None, x0=None):
             if rv:
                 v = f32(v)
             for l, g in enumerate(S._project_adjoint(sen, v)):
-                acc[l] += g
+                acc[l] += f32(g) if rimg else g
         return S.to_coeffs(acc) + S.alpha * S.D * c
 
     out = [0.0, 0.0, 0.0]
-    for rvec, rb, rphi, rv in ((True, False, False, False), (True, False, True, False),
-                               (False, True, True, True)):
+    for rvec, rb, rphi, rv, rimg in ((True, False, False, False, False),
+                                     (True, False, True, False, False),
+                                     (False, True, True, True, False),
+                                     (True, True, True, True, True)):
         R = f32 if rvec else ident
         bb = f32(b) if rb else b
         JJ = f32(Jd) if rb else Jd
         x = np.zeros_like(b) if x0 is None else R(x0)
-        r = R(bb - apply_rounded(x, rphi, rv)) if x0 is not None else R(bb)
+        r = R(bb - apply_rounded(x, rphi, rv, rimg)) if x0 is not None else R(bb)
         z = r / JJ
         p = R(z)
         rho = r @ z
         for _ in range(k):
-            q = R(apply_rounded(p, rphi, rv))
+            q = R(apply_rounded(p, rphi, rv, rimg))
             a = rho / (p @ q)
             x = R(x + a * p)
             r = R(r - a * q)
