@@ -29,6 +29,8 @@ sys.path.insert(0, ROOT)
 import workloads as WL  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_eelt_b32.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1302_3734_amd", "csrc", "wmcao_kernels.hip")
 N_FRAMES_ROT = 4            # distinct frozen-flow frames per stream in rotation
 
 
@@ -136,6 +138,36 @@ def served_stream(duration_s, rate_hz, n_iter):
             "mean_frames_per_launch": round(float(np.mean(srv.frames_in_launch)), 3)}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of a library kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by its
+    copy-kernel calibration factor), or None if there is none or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    meta, rows = {}, {}
+    for ln in lines:
+        if ln.startswith("#") and ":" in ln:
+            k, v = ln[1:].split(":", 1)
+            meta[k.strip()] = v.strip()
+        elif ln and not ln.startswith("#"):
+            f = ln.split()
+            if len(f) >= 3 and f[0].startswith("k_"):
+                rows[f[0]] = (float(f[1]), float(f[2]))
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    name = "k_" + kernel
+    if meta.get("kernel source sha256") != src or name not in rows:
+        return None
+    ff = float(meta.get("fetch calibration factor", "nan"))
+    fw = float(meta.get("write calibration factor", "nan"))
+    fetch, write = rows[name]
+    val = 1024.0 * (fetch * ff + write * fw)
+    return round(val) if math.isfinite(val) else None
+
+
 def onaxis_residual(cfg, layers_vec, truth_vec):
     """On-axis wavefront residual (rad RMS at 500 nm, piston removed) over the
     pupil nodes of the 84x84 grid, and its Marechal Strehl in K band (2.2 um).
@@ -178,6 +210,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with a 256 MiB device copy (byte-counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -359,12 +393,19 @@ def main():
         "p99_frame_latency_ms": round(p99, 4),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_us": round(1e6 * avg_s, 3),
+                     "traffic": measured_traffic(dom), "traffic_unit": "bytes per launch",
+                     "avg_launch_us": round(1e6 * avg_s, 3),
                      "algorithmic_bytes_per_launch": int(abytes)},
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
     out.update(result)
+    if args.calib_copy:
+        src_t = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
     p32.close()
 
