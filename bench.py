@@ -112,7 +112,7 @@ def served_stream(duration_s, rate_hz, n_iter):
         cfgs[nm] = (cfg, sig)
         fwd.close()
     srv = Server(cfgs, {nm: nm for nm in names}, dtype="f32", n_iter=n_iter, hip_streams=4,
-                 tile=16)
+                 tile=16, pack=True)
     arrivals = sorted((t, nm) for k, nm in enumerate(names)
                       for t in WL.poisson_arrivals(500 + k, rate_hz / len(names), duration_s))
     torch.cuda.synchronize()
@@ -168,6 +168,99 @@ def measured_traffic(kernel):
     return round(val) if math.isfinite(val) else None
 
 
+def _synthetic_slopes(cfg, plan, frames):
+    """Seeded screens through the library's forward model plus noise at the
+    configuration's level: [len(frames), n_slopes] FP64 on the device."""
+    import torch
+    out = []
+    so = plan.slope_offsets
+    sig = None
+    for t in frames:
+        v = np.concatenate([a.ravel() for a in WL.layer_screens(cfg, t)])
+        clean = plan.forward_layers(torch.tensor(v, device="cuda")[None])[0]
+        if sig is None:
+            sig = WL.sigmas_from_clean(cfg, clean.cpu().numpy(), so)
+            sv = torch.tensor(np.concatenate([np.full(so[m + 1] - so[m], sig[m])
+                                              for m in range(len(sig))]), device="cuda")
+        noise = torch.tensor(WL.noise_draw(cfg["cfg_id"], t, plan.n_slopes), device="cuda")
+        out.append(clean + sv * noise)
+    return torch.stack(out), sig
+
+
+def batched_small(n_frames=128, n_iter=10, reps=20):
+    """C3: independent 8 m frames (own seeded screens and noise) in one FP32
+    batched solve replayed as a HIP graph."""
+    import torch
+    from paper_1302_3734_amd import Plan
+    cfg = WL.config_c1()
+    fwd = Plan(cfg, [1.0] * len(cfg["wfs"]), dtype="f64", max_batch=1)
+    sl, sig = _synthetic_slopes(cfg, fwd, range(n_frames))
+    fwd.close()
+    plan = Plan(cfg, sig, dtype="f32", max_batch=n_frames)
+    s32 = sl.float().contiguous()
+    x = torch.zeros(n_frames, plan.n, dtype=torch.float32, device="cuda")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(3):
+            plan.solve(s32, x, n_iter=n_iter, graph=True, stream=st)
+    st.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        with torch.cuda.stream(st):
+            plan.solve(s32, x, n_iter=n_iter, graph=True, stream=st)
+        b.record(st)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    plan.close()
+    ms = statistics.median(ts)
+    return {"workload": "8 m, 3 NGS 16x16, 3 layers 64 px, db3 4 levels, 10 its from zero",
+            "frames_per_launch": n_frames, "ms_per_launch": round(ms, 4),
+            "frames_per_s": round(n_frames / ms * 1e3, 1), "mode": "FP32, hipGraph replay"}
+
+
+def mixed_batch(n_frames=64, n_iter=10, reps=10):
+    """C4: frames drawn uniformly from eight telescope classes, all packed into
+    one multi-plan solve (warm start) replayed as a HIP graph."""
+    import torch
+    from paper_1302_3734_amd import Plan, solve_multi
+    classes = WL.config_c4_classes()
+    pick = np.random.default_rng(np.random.SeedSequence([4, 0, 4])).integers(0, len(classes), n_frames)
+    counts = [int((pick == k).sum()) for k in range(len(classes))]
+    plans, slopes, coeffs = [], [], []
+    for k, cfg in enumerate(classes):
+        if counts[k] == 0:
+            continue
+        fwd = Plan(cfg, [1.0] * len(cfg["wfs"]), dtype="f64", max_batch=1)
+        sl, sig = _synthetic_slopes(cfg, fwd, range(counts[k]))
+        fwd.close()
+        p = Plan(cfg, sig, dtype="f32", max_batch=counts[k])
+        plans.append(p)
+        slopes.append(sl.float().contiguous())
+        coeffs.append(torch.zeros(counts[k], p.n, dtype=torch.float32, device="cuda"))
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(3):
+            solve_multi(plans, slopes, coeffs, n_iter=n_iter, warm_start=True, graph=True)
+    st.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        with torch.cuda.stream(st):
+            solve_multi(plans, slopes, coeffs, n_iter=n_iter, warm_start=True, graph=True)
+        b.record(st)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    for p in plans:
+        p.close()
+    ms = statistics.median(ts)
+    return {"workload": "8 classes {8, 16, 39, 42 m} x {LGS-only, NGS-only}, FP32, 10 warm its",
+            "frames_per_launch": n_frames, "counts": counts, "ms_per_launch": round(ms, 4),
+            "frames_per_s": round(n_frames / ms * 1e3, 1), "mode": "one packed launch, hipGraph replay"}
+
+
 def onaxis_residual(cfg, layers_vec, truth_vec):
     """On-axis wavefront residual (rad RMS at 500 nm, piston removed) over the
     pupil nodes of the 84x84 grid, and its Marechal Strehl in K band (2.2 um).
@@ -210,6 +303,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 128-frame 8 m batch and the mixed-size batch")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 256 MiB device copy (byte-counter calibration)")
     args = ap.parse_args()
@@ -368,6 +463,12 @@ def main():
             "strehl_K_fp64": round(strehl_a, 5), "strehl_K_fp32": round(strehl_b, 5),
             "strehl_rel_diff": abs(strehl_a - strehl_b) / strehl_a}
         p64.close()
+
+    if not args.no_extra:
+        result["c3_batched"] = batched_small()
+        print(f"[bench] c3 {result['c3_batched']}", flush=True)
+        result["c4_mixed"] = mixed_batch()
+        print(f"[bench] c4 {result['c4_mixed']}", flush=True)
 
     if args.serve_seconds > 0:
         result["served"] = served_stream(args.serve_seconds, args.serve_rate, IT)

@@ -17,8 +17,8 @@ import torch
 
 from .plan import Plan
 
-CANDIDATES = [(16, 64 * 1024), (32, 64 * 1024), (64, 64 * 1024),
-              (32, 160 * 1024), (64, 160 * 1024), (32, 16 * 1024)]
+CANDIDATES = [(16, 2 * 1024), (16, 8 * 1024), (32, 2 * 1024), (32, 8 * 1024),
+              (32, 32 * 1024), (64, 8 * 1024)]
 _lock = threading.Lock()
 
 

@@ -83,6 +83,13 @@ __device__ void block_sum4(double* v, double* red) {
     for (int k = 0; k < 4; ++k) v[k] = red[64 + k];
 }
 
+// Deterministic sum over one wavefront (fixed shuffle tree); lane 0 holds it.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
 __device__ double sum_slots(const double* p, int n, double* red) {
     double v = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
@@ -233,17 +240,33 @@ __device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, i
         int gy = py0 + c;
         if (gy >= N) gy -= N;
         for (int r = r0; r < PR; r += rstep) G[r * ldg + c] = 0;
-        for (unsigned mm = mask; mm; mm &= mm - 1) {
-            const int m = __ffs(static_cast<int>(mm)) - 1;
-            const int yc = gy - P.fp_y0[m][l], Wf = P.fp_w[m][l];
-            if (yc < 0 || yc >= Wf) continue;
-            const int x0 = P.fp_x0[m][l], Hf = P.fp_h[m][l];
-            const T* im = img + P.fp_off[m][l] + yc;
+        // two sensors per step (uniform indices): both images are loaded
+        // before either is added, in sensor order
+        unsigned mm = mask;
+        while (mm) {
+            const int ma = __ffs(static_cast<int>(mm)) - 1;
+            mm &= mm - 1;
+            const int mb = mm ? __ffs(static_cast<int>(mm)) - 1 : ma;
+            const bool hb = mm != 0;
+            if (hb) mm &= mm - 1;
+            const int yca = gy - P.fp_y0[ma][l], Wa = P.fp_w[ma][l];
+            const int ycb = gy - P.fp_y0[mb][l], Wb = P.fp_w[mb][l];
+            const bool ca = yca >= 0 && yca < Wa, cb = hb && ycb >= 0 && ycb < Wb;
+            const int xa = P.fp_x0[ma][l], Ha = P.fp_h[ma][l];
+            const int xb = P.fp_x0[mb][l], Hb = P.fp_h[mb][l];
+            const T* ia = img + P.fp_off[ma][l] + yca;
+            const T* ib = img + P.fp_off[mb][l] + ycb;
             for (int r = r0; r < PR; r += rstep) {
                 int gx = px0 + r;
                 if (gx >= N) gx -= N;
-                const int xr = gx - x0;
-                if (xr >= 0 && xr < Hf) G[r * ldg + c] += static_cast<Acc>(im[xr * Wf]);
+                const int ra = gx - xa, rb = gx - xb;
+                const bool la = ca && ra >= 0 && ra < Ha, lb = cb && rb >= 0 && rb < Hb;
+                const Acc va = la ? static_cast<Acc>(ia[ra * Wa]) : 0.0;
+                const Acc vb = lb ? static_cast<Acc>(ib[rb * Wb]) : 0.0;
+                Acc g = G[r * ldg + c];
+                if (la) g += va;
+                if (lb) g += vb;
+                G[r * ldg + c] = g;
             }
         }
     }
@@ -394,7 +417,6 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     constexpr int HT = TS / 2, PW = TS + 4;
     __shared__ Acc sA[PW][PW + 1];
     __shared__ Acc sL[PW][HT + 1], sH[PW][HT + 1];
-    __shared__ double red[17];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -405,6 +427,24 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     const int px0 = 2 * cx0, py0 = 2 * cy0;
     Acc hf[6], gf[6];
     load_filters(P, hf, gf);
+    // p at this thread's first epilogue coefficients, loaded before the window
+    // so that its latency overlaps the analysis
+    constexpr int PQ_PF = 2;
+    Acc pp[PQ_PF][3];
+    if (epi == EPI_APPLY) {
+        const T* pv0 = vptr<T>(J, aux_vec, it.frame) + Ly.coff;
+#pragma unroll
+        for (int q = 0; q < PQ_PF; ++q) {
+            const int e = threadIdx.x + q * blockDim.x;
+            const int X = cx0 + e / HT, Y = cy0 + e % HT;
+            pp[q][0] = pp[q][1] = pp[q][2] = 0.0;
+            if (e < HT * HT && X < H && Y < H) {
+                pp[q][0] = pv0[static_cast<int64_t>(X) * N + H + Y];
+                pp[q][1] = pv0[static_cast<int64_t>(H + X) * N + Y];
+                pp[q][2] = pv0[static_cast<int64_t>(H + X) * N + H + Y];
+            }
+        }
+    }
     if (level == 1 && src == SRC_PT) {
         pt_gather_window<T>(P, vptr<T>(J, in_vec, it.frame), it.a, N, px0, py0, PW, PW,
                             &sA[0][0], PW + 1,
@@ -442,7 +482,7 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     const Acc aD = P.alpha * Ly.D[level - 1];
     double* llo = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level];
     double acc = 0.0;
-    for (int e = threadIdx.x; e < HT * HT; e += blockDim.x) {
+    for (int e = threadIdx.x, q = 0; e < HT * HT; e += blockDim.x, ++q) {
         const int c1 = e / HT, c2 = e % HT;
         const int X = cx0 + c1, Y = cy0 + c2;
         Acc ll = 0, hl = 0, lh = 0, hh = 0;
@@ -460,7 +500,9 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
             const int64_t iHL = static_cast<int64_t>(H + X) * N + Y;
             const int64_t iHH = static_cast<int64_t>(H + X) * N + H + Y;
             if (epi == EPI_APPLY) {
-                const Acc p1 = pv[iLH], p2 = pv[iHL], p3 = pv[iHH];
+                const Acc p1 = q < PQ_PF ? pp[q][0] : static_cast<Acc>(pv[iLH]);
+                const Acc p2 = q < PQ_PF ? pp[q][1] : static_cast<Acc>(pv[iHL]);
+                const Acc p3 = q < PQ_PF ? pp[q][2] : static_cast<Acc>(pv[iHH]);
                 const T o1 = static_cast<T>(lh + aD * p1);
                 const T o2 = static_cast<T>(hl + aD * p2);
                 const T o3 = static_cast<T>(hh + aD * p3);
@@ -476,9 +518,9 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
             }
         }
     }
-    if (epi == EPI_APPLY) {
-        const double s = block_sum(acc, red);
-        if (threadIdx.x == 0) part_ptr(J, it.frame, PT_PQ)[it.slot] = s;
+    if (epi == EPI_APPLY) {   // one partial per wave, summed by the consumer in slot order
+        const double s = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) part_ptr(J, it.frame, PT_PQ)[it.slot + (threadIdx.x >> 6)] = s;
     }
 }
 
@@ -490,7 +532,6 @@ template <class T>
 __global__ void __launch_bounds__(1024)
 k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int in_vec,
               int out_vec, int epi, int aux_vec) {
-    __shared__ double red[17];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -533,9 +574,9 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
             out[gi] = static_cast<T>(v);
         }
     }
-    if (epi == EPI_APPLY) {
-        const double s = block_sum(acc, red);
-        if (threadIdx.x == 0) part_ptr(J, it.frame, PT_PQ)[it.slot] = s;
+    if (epi == EPI_APPLY) {   // one partial per wave, summed by the consumer in slot order
+        const double s = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) part_ptr(J, it.frame, PT_PQ)[it.slot + (threadIdx.x >> 6)] = s;
     }
 }
 // --------------------------------------------------------- projection ----

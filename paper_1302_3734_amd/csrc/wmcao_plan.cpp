@@ -250,8 +250,8 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Items for every stage of a job of several plans: frame-major order inside
 // each plan, plans in order.  The FDWT pass of one frame writes its <p, Ap>
-// partials into slots 0.. in the order level-1 tiles, level-2 tiles, ...,
-// coarse blocks; the vector passes use one slot per chunk.
+// partials, one per wave, into slots 0.. in the order level-1 tiles, level-2
+// tiles, ..., coarse blocks; the vector passes use one slot per chunk.
 int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj;
     int lds_lvl[WM_MAXLEV + 1] = {};
@@ -267,12 +267,16 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                     if (Ly.k0 < k) continue;
                     const int M = Ly.N >> (k - 1);
                     const int nt = ceil_div(M, tile);
-                    for (int t = 0; t < nt * nt; ++t) tiled[k].push_back(Item{jp, f, l, t, slot++, 0, 0, 0});
+                    for (int t = 0; t < nt * nt; ++t) {
+                        tiled[k].push_back(Item{jp, f, l, t, slot, 0, 0, 0});
+                        slot += PQ_TILE_SLOTS;   // one <p, Ap> partial per wave
+                    }
                     maxk0 = std::max(maxk0, k);
                 }
             }
             for (int l = 0; l < P->L; ++l) {
-                coarse.push_back(Item{jp, f, l, 0, slot++, 0, 0, 0});
+                coarse.push_back(Item{jp, f, l, 0, slot, 0, 0, 0});
+                slot += PQ_COARSE_SLOTS;
                 const LayerInfo& Ly = P->host.layer[l];
                 if (!Ly.fuse) coarse_syn.push_back(coarse.back());
                 if (Ly.fuse)
@@ -1055,9 +1059,9 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             for (int k = 1; k <= H.layer[l].k0; ++k) {
                 const int M = H.layer[l].N >> (k - 1);
                 const int nt = ceil_div(M, p->tile);
-                nf += nt * nt;
+                nf += nt * nt * PQ_TILE_SLOTS;
             }
-            nf += 1;
+            nf += PQ_COARSE_SLOTS;
         }
         H.n_fdwt_slots = nf;
         H.n_vec_slots = static_cast<int>((p->n + VEC_CHUNK - 1) / VEC_CHUNK);

@@ -58,14 +58,18 @@ class Server:
     hbm_budget: bytes that frames in flight may reserve (default: half of the
     free device memory at start).  keep_inputs: keep each frame's warm start
     (for invariance checks).  graphs: replay captured launches.  tile: tile
-    edge of the wavelet kernels (0 = library default; 16 favours latency)."""
+    edge of the wavelet kernels (0 = library default; 16 favours latency).
+    pack: put frames of several configurations into one launch (throughput);
+    otherwise each configuration's frames go to a launch of their own, which
+    runs alongside the others on its own HIP stream (latency)."""
 
     def __init__(self, configs, streams, dtype="f32", n_iter=10, hip_streams=2,
-                 hbm_budget=None, keep_inputs=False, graphs=True, tile=0):
+                 hbm_budget=None, keep_inputs=False, graphs=True, tile=0, pack=True):
         self.dtype = dtype
         self.n_iter = int(n_iter)
         self.keep_inputs = keep_inputs
         self.graphs = graphs
+        self.pack = pack
         self.hip_streams = [torch.cuda.Stream() for _ in range(hip_streams)]
         count = collections.Counter(streams.values())
         # one plan per (configuration, HIP stream), batch = streams of that config
@@ -82,6 +86,17 @@ class Server:
         self.stage = {c: [(torch.zeros(count[c], self.n_slopes[c], dtype=tdt, device="cuda"),
                            torch.zeros(count[c], self.n[c], dtype=tdt, device="cuda"))
                           for _ in range(hip_streams)] for c in self.plans}
+        if graphs:
+            # capture the one-configuration launches up front, so that no frame
+            # waits for a graph to be recorded
+            for c, ps in self.plans.items():
+                for hs, plan in enumerate(ps):
+                    Sb, Xb = self.stage[c][hs]
+                    with torch.cuda.stream(self.hip_streams[hs]):
+                        for k in range(1, count[c] + 1):
+                            solve_multi([plan], [Sb[:k]], [Xb[:k]], n_iter=self.n_iter,
+                                        warm_start=True, graph=True)
+            torch.cuda.synchronize()
         esz = torch.empty(0, dtype=tdt).element_size()
         # bytes a frame in flight reserves: slopes + state + the plan scratch of one frame
         self.frame_bytes = {c: esz * (self.n_slopes[c] + 7 * self.n[c]) for c in self.plans}
@@ -130,10 +145,13 @@ class Server:
     # ---- worker --------------------------------------------------------------
     def _admit(self):
         """Frames to launch now: the oldest pending frame of every idle stream,
-        within the HBM budget, grouped per configuration."""
+        within the HBM budget, grouped per configuration (one configuration per
+        launch unless packing)."""
         groups = collections.OrderedDict()
         for st in self.streams.values():
             if st.busy or not st.queue:
+                continue
+            if not self.pack and groups and st.cfg not in groups:
                 continue
             need = self.frame_bytes[st.cfg]
             if self.reserved + need > self.hbm_budget:

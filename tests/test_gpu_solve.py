@@ -119,25 +119,31 @@ def test_c2_warm_10_iterations(dt, kw):
 
 
 def test_c3_batched_fp32_per_frame_and_batch_invariance():
-    """Independent C1 frames in one batched FP32 solve (10 iterations): each
-    frame within 1e-5 of the FP64 oracle -- or, for frames so ill-conditioned
-    that FP32 storage alone moves the iterate further, within twice the
-    oracle's own FP32 rounding spread -- and bitwise equal to its solo solve."""
+    """128 independent C1 frames (own seeded screens and noise) in one batched
+    FP32 solve of 10 iterations captured as a HIP graph: sampled frames within
+    1e-5 of the FP64 oracle -- or, for frames so ill-conditioned that FP32
+    storage alone moves the iterate further, within twice the oracle's own FP32
+    rounding spread -- and bitwise equal to their solo solves."""
     require_gpu()
     import torch
     from paper_1302_3734_amd import Plan
     cfg = WL.config_c1()
-    B = 16
+    B = 128
     S0, sig, _, _ = setup(cfg)
     S = O.System(cfg, sig)
     J = S.jacobi_separable()
     slopes = np.stack([slopes_for(S, cfg, sig, f) for f in range(B)])
     s32 = to_dev(slopes, torch.float32)
     plan = Plan(cfg, sig, dtype="f32", max_batch=B)
-    say("[c3] batched solve")
-    X = to_np(plan.solve(s32, n_iter=10)).reshape(B, -1)
+    say("[c3] batched solve (graph)")
+    out = torch.zeros(B, plan.n, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.solve(s32, out, n_iter=10, graph=True, stream=stream)
+    stream.synchronize()
+    X = to_np(out).reshape(B, -1)
     worst = 0.0
-    for f in range(B):
+    for f in range(0, B, 11):
         s_in = to_np(s32[f]).ravel()
         b = S.rhs(s_in)
         x_ref, _ = O.pcg(S.apply_A, b, 10, jacobi=J)
@@ -148,7 +154,7 @@ def test_c3_batched_fp32_per_frame_and_batch_invariance():
         worst = max(worst, max(e))
         assert all(ei < ti for ei, ti in zip(e, tol)), (f, e, tol)
     say(f"[c3] worst error {worst:.2e}")
-    for f in (0, 5, B - 1):
+    for f in (0, 77, B - 1):
         xs = to_np(plan.solve(s32[f:f + 1].contiguous(), n_iter=10)).ravel()
         assert np.array_equal(xs, X[f]), f
     plan.close()
