@@ -588,6 +588,8 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
 // sums for the tip/tilt projection and the low-order cells (one record per
 // band, reduced in a fixed order by k_weights).  u is kept in FP64 so that the
 // Fried differences do not cancel single-precision digits.
+constexpr int PROJ_LB = 9;   // layers whose samples a thread loads together
+
 template <class T>
 __global__ void __launch_bounds__(512)
 k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int sums) {
@@ -622,11 +624,11 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
     for (int e = threadIdx.x; e < rows_c * nn; e += blockDim.x) {
         const int li = e / nn, j = e - (e / nn) * nn;
         Acc acc = 0;
-        // four layers per step: their samples are loaded before any is used
-        for (int l0 = 0; l0 < L; l0 += 4) {
-            Acc v[4][4];
+        // PROJ_LB layers per step: their samples are loaded before any is used
+        for (int l0 = 0; l0 < L; l0 += PROJ_LB) {
+            T v[PROJ_LB][4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < PROJ_LB; ++k) {
                 const int l = l0 + k;
                 if (l < L) {
                     const int N = P.layer[l].N;
@@ -638,12 +640,12 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
                 }
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < PROJ_LB; ++k) {
                 const int l = l0 + k;
                 if (l < L) {
                     const Acc t = rtw[l][li], s = csw[l][j];
-                    acc += (1.0 - t) * ((1.0 - s) * v[k][0] + s * v[k][1]) +
-                           t * ((1.0 - s) * v[k][2] + s * v[k][3]);
+                    acc += (1.0 - t) * ((1.0 - s) * static_cast<Acc>(v[k][0]) + s * static_cast<Acc>(v[k][1])) +
+                           t * ((1.0 - s) * static_cast<Acc>(v[k][2]) + s * static_cast<Acc>(v[k][3]));
                 }
             }
         }
@@ -720,6 +722,7 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     __shared__ double su[(PROJ_ROWS + 2) * (WM_NSUB_MAX + 1)];
     __shared__ double swx[(PROJ_ROWS + 1) * WM_NSUB_MAX], swy[(PROJ_ROWS + 1) * WM_NSUB_MAX];
     __shared__ double cval[2 * WM_MAXCELL], cwx[WM_MAXCELL], cwy[WM_MAXCELL];
+    __shared__ double srec[((WM_NSUB_MAX + 1 + PROJ_ROWS - 1) / PROJ_ROWS) * SP_K];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -740,14 +743,22 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     }
     const int ua = max(r0 - 1, 0), ub = min(r0 + PROJ_ROWS, nn - 1);
     for (int e = threadIdx.x; e < (ub - ua + 1) * nn; e += blockDim.x) su[e] = ug[ua * nn + e];
-    if (threadIdx.x == 0) {
+    // the band records of this sensor, gathered in parallel
+    const int nb = (nn + PROJ_ROWS - 1) / PROJ_ROWS;
+    const int K = w.agg ? 2 * w.S : 4;
+    {
         const double* rec = vptr<double>(J, V_SPART, it.frame) + w.sp_off;
-        const int nb = (nn + PROJ_ROWS - 1) / PROJ_ROWS;
+        for (int e = threadIdx.x; e < nb * K; e += blockDim.x)
+            srec[e] = rec[(e / K) * SP_K + e % K];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double* rec = srec;
         const double* blk = w.blocks;
         if (!w.agg) {
             double t[4] = {0.0, 0.0, 0.0, 0.0};
             for (int b = 0; b < nb; ++b)
-                for (int k = 0; k < 4; ++k) t[k] += rec[b * SP_K + k];
+                for (int k = 0; k < 4; ++k) t[k] += rec[b * K + k];
             double mx = 0.0, my = 0.0, nx = 0.0, ny = 0.0;
             if (w.remove_tt) {
                 const double S = w.S_fine;
@@ -766,8 +777,8 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
             for (int c = 0; c < S; ++c) {
                 double px = 0.0, py = 0.0;
                 for (int b = 0; b < nb; ++b) {
-                    px += rec[b * SP_K + 2 * c];
-                    py += rec[b * SP_K + 2 * c + 1];
+                    px += rec[b * K + 2 * c];
+                    py += rec[b * K + 2 * c + 1];
                 }
                 cval[2 * c] = px / w.cell_count[c];
                 cval[2 * c + 1] = py / w.cell_count[c];
