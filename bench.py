@@ -113,6 +113,8 @@ def served_stream(duration_s, rate_hz, n_iter):
         fwd.close()
     srv = Server(cfgs, {nm: nm for nm in names}, dtype="f32", n_iter=n_iter, hip_streams=4,
                  tile=16, pack=True)
+    switch = sys.getswitchinterval()
+    sys.setswitchinterval(1e-4)       # hand the interpreter lock to the server threads promptly
     arrivals = sorted((t, nm) for k, nm in enumerate(names)
                       for t in WL.poisson_arrivals(500 + k, rate_hz / len(names), duration_s))
     torch.cuda.synchronize()
@@ -128,12 +130,17 @@ def served_stream(duration_s, rate_hz, n_iter):
     for f in futs:
         f.result(timeout=120)
     elapsed = time.perf_counter() - t0
+    sys.setswitchinterval(switch)
     srv.close()
     lat = srv.latencies_ms()
+    wait, run = srv.waits_ms()
     return {"configs": names, "rate_hz": rate_hz, "duration_s": duration_s, "frames": len(lat),
             "frames_per_s": round(len(lat) / elapsed, 1),
             "p50_frame_latency_ms": round(pctl(lat, 0.5), 4),
             "p99_frame_latency_ms": round(pctl(lat, 0.99), 4),
+            "p99_queue_wait_ms": round(pctl(wait, 0.99), 4),
+            "p50_launch_to_result_ms": round(pctl(run, 0.5), 4),
+            "p99_launch_to_result_ms": round(pctl(run, 0.99), 4),
             "launches": srv.launches,
             "mean_frames_per_launch": round(float(np.mean(srv.frames_in_launch)), 3)}
 
@@ -413,29 +420,33 @@ def main():
     # ---- reconstruction check and the per-frame FP64 comparison -------------
     result = {}
     if not args.no_fp64:
-        p64 = Plan(cfg, sig, dtype="f64", max_batch=1)
-        x64 = torch.zeros(1, n, dtype=torch.float64, device="cuda")
-        p64.solve(slopes64[0, :1].contiguous(), x64, n_iter=30)
-        xs32 = torch.zeros(1, n, dtype=torch.float32, device="cuda")
-        p32.solve(slopes32[0, :1].contiguous(), xs32, n_iter=30)
-        torch.cuda.synchronize()
-        stream = torch.cuda.Stream()
-        lat64 = []
-        nf = 40
-        frames64 = [slopes64[1 + (i % N_FRAMES_ROT), :1].contiguous() for i in range(nf)]
-        buf = torch.empty_like(frames64[0])
-        with torch.cuda.stream(stream):
-            for i in range(nf):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                buf.copy_(frames64[i])
-                e0.record(stream)
-                p64.solve(buf, x64, n_iter=IT, warm_start=True, graph=True, stream=stream)
-                e1.record(stream)
-                lat64.append((e0, e1))
-        stream.synchronize()
-        l64 = sorted(a.elapsed_time(b) for a, b in lat64[2:])
-        fps64 = 1e3 / statistics.mean(l64)
-        p99_64 = pctl(l64, 0.99)
+        def per_frame(plan, frames_all, dt):
+            """Back-to-back single-frame warm solves of stream 0 (hipGraph
+            replay): frames/s and p99 latency."""
+            x1 = torch.zeros(1, n, dtype=dt, device="cuda")
+            plan.solve(frames_all[0, :1].contiguous(), x1, n_iter=30)
+            torch.cuda.synchronize()
+            stream = torch.cuda.Stream()
+            lat, nf = [], 40
+            frames = [frames_all[1 + (i % N_FRAMES_ROT), :1].contiguous() for i in range(nf)]
+            buf = torch.empty_like(frames[0])
+            with torch.cuda.stream(stream):
+                for i in range(nf):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    buf.copy_(frames[i])
+                    e0.record(stream)
+                    plan.solve(buf, x1, n_iter=IT, warm_start=True, graph=True, stream=stream)
+                    e1.record(stream)
+                    lat.append((e0, e1))
+            stream.synchronize()
+            ls = sorted(a.elapsed_time(b) for a, b in lat[2:])
+            return 1e3 / statistics.mean(ls), pctl(ls, 0.99)
+
+        p64 = Plan(cfg, sig, dtype="f64", max_batch=1, tile=16)
+        fps64, p99_64 = per_frame(p64, slopes64, torch.float64)
+        q32 = Plan(cfg, sig, dtype="f32", max_batch=1, tile=16)
+        fps32, p99_32 = per_frame(q32, slopes32, torch.float32)
+        q32.close()
         # equal reconstruction: FP32 and FP64 solves of stream 0 frame 1, both
         # warm-started from the same FP64 frame-0 reconstruction
         xa = torch.zeros(1, n, dtype=torch.float64, device="cuda")
@@ -451,7 +462,12 @@ def main():
         rms_0, _ = onaxis_residual(cfg, np.zeros_like(tr), tr)
         result["fp64_per_frame"] = {"frames_per_s": round(fps64, 2),
                                     "p99_frame_latency_ms": round(p99_64, 4),
-                                    "mode": "batch 1, hipGraph replay"}
+                                    "mode": "batch 1, hipGraph replay, tile 16"}
+        result["fp32_per_frame"] = {"frames_per_s": round(fps32, 2),
+                                    "p99_frame_latency_ms": round(p99_32, 4),
+                                    "mode": "batch 1, hipGraph replay, tile 16"}
+        print(f"[bench] per frame: FP64 {fps64:.1f} frames/s p99 {p99_64:.3f} ms; "
+              f"FP32 {fps32:.1f} frames/s p99 {p99_32:.3f} ms", flush=True)
         result["reconstruction"] = {
             "frame": "stream 0, frame 1, both warm-started from the FP64 30-iteration frame 0",
             "fp32_vs_fp64_coeff_rel_diff": float(

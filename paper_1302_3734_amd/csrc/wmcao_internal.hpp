@@ -73,6 +73,7 @@ struct PlanDev {
     int L, W, levels, dtype;
     int precond;
     int n_fdwt_slots;       // partial slots written by one wavelet-analysis pass per frame
+    int pq_base;            // first of the L per-layer <p, Ap> totals
     int n_vec_slots;        // partial slots written by one vector pass per frame
     int slots;              // stride of one partial segment
     int64_t n, n_slopes, n_nodes, ll_size;
@@ -176,8 +177,6 @@ template <class T>
 void launch_cast_from_double(const double* in, T* out, int64_t n, hipStream_t s);
 
 constexpr int FUSE_LDS = 32 * 1024;   // largest low-pass block a synthesis tile rebuilds
-constexpr int PQ_TILE_SLOTS = 4;      // <p, Ap> partials of a 256-thread analysis tile (one per wave)
-constexpr int PQ_COARSE_SLOTS = 16;   // ... of a 1024-thread whole-band analysis block
 constexpr int VEC_CHUNK = 4096;   // elements per block of the vector kernels
 constexpr int PROJ_ROWS = 8;      // sensor node rows per block of the projection
 constexpr int SP_K = 2 * WM_MAXCELL;   // doubles per slope-sum record

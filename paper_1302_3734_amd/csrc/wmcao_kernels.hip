@@ -83,13 +83,6 @@ __device__ void block_sum4(double* v, double* red) {
     for (int k = 0; k < 4; ++k) v[k] = red[64 + k];
 }
 
-// Deterministic sum over one wavefront (fixed shuffle tree); lane 0 holds it.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return v;
-}
-
 __device__ double sum_slots(const double* p, int n, double* red) {
     double v = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
@@ -417,6 +410,7 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     constexpr int HT = TS / 2, PW = TS + 4;
     __shared__ Acc sA[PW][PW + 1];
     __shared__ Acc sL[PW][HT + 1], sH[PW][HT + 1];
+    __shared__ double red[17];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -518,9 +512,9 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
             }
         }
     }
-    if (epi == EPI_APPLY) {   // one partial per wave, summed by the consumer in slot order
-        const double s = wave_sum(acc);
-        if ((threadIdx.x & 63) == 0) part_ptr(J, it.frame, PT_PQ)[it.slot + (threadIdx.x >> 6)] = s;
+    if (epi == EPI_APPLY) {
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) part_ptr(J, it.frame, PT_PQ)[it.slot] = s;
     }
 }
 
@@ -532,6 +526,7 @@ template <class T>
 __global__ void __launch_bounds__(1024)
 k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int in_vec,
               int out_vec, int epi, int aux_vec) {
+    __shared__ double red[17];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -574,9 +569,15 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
             out[gi] = static_cast<T>(v);
         }
     }
-    if (epi == EPI_APPLY) {   // one partial per wave, summed by the consumer in slot order
-        const double s = wave_sum(acc);
-        if ((threadIdx.x & 63) == 0) part_ptr(J, it.frame, PT_PQ)[it.slot + (threadIdx.x >> 6)] = s;
+    if (epi == EPI_APPLY) {
+        // this layer's total: its tile partials (pad0.., pad1 of them, summed
+        // in a fixed order) plus this block's own
+        double* pq = part_ptr(J, it.frame, PT_PQ);
+        double t = 0.0;
+        for (int i = threadIdx.x; i < it.pad1; i += blockDim.x) t += pq[it.pad0 + i];
+        const double tiles = block_sum(t, red);
+        const double own = block_sum(acc, red);
+        if (threadIdx.x == 0) pq[it.slot] = tiles + own;
     }
 }
 // --------------------------------------------------------- projection ----
@@ -1310,7 +1311,7 @@ k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
-    const double pq = sum_slots(part_ptr(J, it.frame, PT_PQ), P.n_fdwt_slots, red);
+    const double pq = sum_slots(part_ptr(J, it.frame, PT_PQ) + P.pq_base, P.L, red);
     const double rho = sum_slots(part_ptr(J, it.frame, PT_RZ0 + (iter & 1)), P.n_vec_slots, red);
     int st = J.status[it.frame];
     double a = 0.0;

@@ -249,9 +249,10 @@ struct JobSpec {
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Items for every stage of a job of several plans: frame-major order inside
-// each plan, plans in order.  The FDWT pass of one frame writes its <p, Ap>
-// partials, one per wave, into slots 0.. in the order level-1 tiles, level-2
-// tiles, ..., coarse blocks; the vector passes use one slot per chunk.
+// each plan, plans in order.  The FDWT pass of one frame writes one <p, Ap>
+// partial per tile, layer by layer; each layer's whole-band block adds its
+// layer's tile partials to its own and writes the layer total after them
+// (the consumer sums L totals); the vector passes use one slot per chunk.
 int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj;
     int lds_lvl[WM_MAXLEV + 1] = {};
@@ -260,23 +261,23 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
         const wmcao_plan_s* P = jobs[jp].plan;
         for (int f = 0; f < jobs[jp].count; ++f) {
-            int slot = 0;
-            for (int k = 1; k <= WM_MAXLEV; ++k) {
-                for (int l = 0; l < P->L; ++l) {
-                    const LayerInfo& Ly = P->host.layer[l];
-                    if (Ly.k0 < k) continue;
+            // <p, Ap> partials: one per analysis tile, numbered layer by layer,
+            // then one total per layer (written by the layer's whole-band block)
+            int slot = 0, first[WM_MAXL], cnt[WM_MAXL];
+            for (int l = 0; l < P->L; ++l) {
+                const LayerInfo& Ly = P->host.layer[l];
+                first[l] = slot;
+                for (int k = 1; k <= Ly.k0; ++k) {
                     const int M = Ly.N >> (k - 1);
                     const int nt = ceil_div(M, tile);
-                    for (int t = 0; t < nt * nt; ++t) {
-                        tiled[k].push_back(Item{jp, f, l, t, slot, 0, 0, 0});
-                        slot += PQ_TILE_SLOTS;   // one <p, Ap> partial per wave
-                    }
+                    for (int t = 0; t < nt * nt; ++t) tiled[k].push_back(Item{jp, f, l, t, slot++, 0, 0, 0});
                     maxk0 = std::max(maxk0, k);
                 }
+                cnt[l] = slot - first[l];
             }
+            const int tile_slots = slot;
             for (int l = 0; l < P->L; ++l) {
-                coarse.push_back(Item{jp, f, l, 0, slot, 0, 0, 0});
-                slot += PQ_COARSE_SLOTS;
+                coarse.push_back(Item{jp, f, l, 0, tile_slots + l, first[l], cnt[l], 0});
                 const LayerInfo& Ly = P->host.layer[l];
                 if (!Ly.fuse) coarse_syn.push_back(coarse.back());
                 if (Ly.fuse)
@@ -1059,11 +1060,11 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             for (int k = 1; k <= H.layer[l].k0; ++k) {
                 const int M = H.layer[l].N >> (k - 1);
                 const int nt = ceil_div(M, p->tile);
-                nf += nt * nt * PQ_TILE_SLOTS;
+                nf += nt * nt;
             }
-            nf += PQ_COARSE_SLOTS;
         }
-        H.n_fdwt_slots = nf;
+        H.pq_base = nf;   // per-layer totals follow the tile partials
+        H.n_fdwt_slots = nf + n_layers;
         H.n_vec_slots = static_cast<int>((p->n + VEC_CHUNK - 1) / VEC_CHUNK);
         H.slots = std::max(H.n_fdwt_slots, H.n_vec_slots);
     }

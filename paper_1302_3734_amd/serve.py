@@ -37,7 +37,8 @@ class _Stream:
 
 
 class _Frame:
-    __slots__ = ("stream", "slopes", "ready", "t_arrival", "t_done", "future", "index", "x0")
+    __slots__ = ("stream", "slopes", "ready", "t_arrival", "t_launch", "t_done", "future", "index",
+                 "x0")
 
     def __init__(self, stream, slopes, index):
         self.stream = stream
@@ -45,6 +46,7 @@ class _Frame:
         self.ready = torch.cuda.Event()
         self.ready.record()              # the slopes are complete on the caller's stream
         self.t_arrival = time.perf_counter()
+        self.t_launch = None
         self.t_done = None
         self.future = Future()
         self.index = index
@@ -180,6 +182,10 @@ class Server:
 
     def _launch(self, hs, groups):
         stream = self.hip_streams[hs]
+        t_launch = time.perf_counter()
+        for frs in groups.values():
+            for f in frs:
+                f.t_launch = t_launch
         plans, slopes, coeffs, frames = [], [], [], []
         with torch.cuda.stream(stream):
             for frs in groups.values():
@@ -246,11 +252,16 @@ class Server:
                     f.stream.busy = False
                     f.stream.frames_done += 1
                     self.reserved -= self.frame_bytes[f.stream.cfg]
-                    self.records.append((f.stream.name, f.index, f.t_arrival, t))
+                    self.records.append((f.stream.name, f.index, f.t_arrival, t, f.t_launch))
                 self.cv.notify_all()
             for f, x in results:
                 f.future.set_result((x, f.x0))
 
     # ---- statistics ------------------------------------------------------------
     def latencies_ms(self):
-        return [1e3 * (t1 - t0) for _, _, t0, t1 in self.records]
+        return [1e3 * (r[3] - r[2]) for r in self.records]
+
+    def waits_ms(self):
+        """Arrival to launch (queueing) and launch to completion, per frame."""
+        return ([1e3 * (r[4] - r[2]) for r in self.records],
+                [1e3 * (r[3] - r[4]) for r in self.records])
