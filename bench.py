@@ -86,11 +86,14 @@ def pctl(v, q):
     return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
 
 
-def served_stream(duration_s, rate_hz, n_iter):
+def served_stream(duration_s, rate_hz, n_iter, plain_fp64=False):
     """Poisson arrivals over four telescope configurations (8 m and 16 m
     NGS-only, 39 m and 42 m LGS-only), one stream each at rate_hz/4, served
-    with continuous batching in FP32; frozen-flow frames from a pool of 8 per
-    stream.  Returns latency percentiles and throughput."""
+    with continuous batching in FP32 (one HIP stream per configuration,
+    backlogs batched); frozen-flow frames from a pool of 8 per stream.  With
+    plain_fp64 the same arrivals are served the plain way instead: FP64, one
+    frame per launch, one launch at a time.  Returns latency percentiles and
+    throughput."""
     import torch
     from paper_1302_3734_amd import Plan
     from paper_1302_3734_amd.serve import Server
@@ -108,11 +111,17 @@ def served_stream(duration_s, rate_hz, n_iter):
         sv = torch.tensor(np.concatenate([np.full(so[m + 1] - so[m], sig[m])
                                           for m in range(len(sig))]), device="cuda")
         pools[nm] = [(lay[t] + sv * torch.tensor(WL.noise_draw(cfg["cfg_id"], t, fwd.n_slopes),
-                                                 device="cuda")).float() for t in range(8)]
+                                                 device="cuda")) for t in range(8)]
+        if not plain_fp64:
+            pools[nm] = [v.float() for v in pools[nm]]
         cfgs[nm] = (cfg, sig)
         fwd.close()
-    srv = Server(cfgs, {nm: nm for nm in names}, dtype="f32", n_iter=n_iter, hip_streams=4,
-                 tile=16, pack=True)
+    if plain_fp64:
+        srv = Server(cfgs, {nm: nm for nm in names}, dtype="f64", n_iter=n_iter, hip_streams=1,
+                     tile=16, pack=False, depth=1, max_frames=1)
+    else:
+        srv = Server(cfgs, {nm: nm for nm in names}, dtype="f32", n_iter=n_iter, hip_streams=4,
+                     tile=16, pack=True)
     switch = sys.getswitchinterval()
     sys.setswitchinterval(1e-4)       # hand the interpreter lock to the server threads promptly
     arrivals = sorted((t, nm) for k, nm in enumerate(names)
@@ -134,7 +143,9 @@ def served_stream(duration_s, rate_hz, n_iter):
     srv.close()
     lat = srv.latencies_ms()
     wait, run = srv.waits_ms()
-    return {"configs": names, "rate_hz": rate_hz, "duration_s": duration_s, "frames": len(lat),
+    return {"mode": ("plain FP64, one frame per launch, one launch at a time" if plain_fp64 else
+                     "FP32 continuous batching, one HIP stream per configuration"),
+            "configs": names, "rate_hz": rate_hz, "duration_s": duration_s, "frames": len(lat),
             "frames_per_s": round(len(lat) / elapsed, 1),
             "p50_frame_latency_ms": round(pctl(lat, 0.5), 4),
             "p99_frame_latency_ms": round(pctl(lat, 0.99), 4),
@@ -442,8 +453,32 @@ def main():
             ls = sorted(a.elapsed_time(b) for a, b in lat[2:])
             return 1e3 / statistics.mean(ls), pctl(ls, 0.99)
 
+        def burst(plan, frames_all, dt, nb):
+            """nb frames of different streams arriving at once, solved one
+            after another (batch 1): each frame's latency is the time from the
+            burst to its own result."""
+            x1 = torch.zeros(1, n, dtype=dt, device="cuda")
+            stream = torch.cuda.Stream()
+            frames = [frames_all[1 + (i % N_FRAMES_ROT), :1].contiguous() for i in range(nb)]
+            buf = torch.empty_like(frames[0])
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                ends = []
+                for i in range(nb):
+                    buf.copy_(frames[i])
+                    plan.solve(buf, x1, n_iter=IT, warm_start=True, graph=True, stream=stream)
+                    e = torch.cuda.Event(enable_timing=True)
+                    e.record(stream)
+                    ends.append(e)
+            stream.synchronize()
+            ls = sorted(e0.elapsed_time(e) for e in ends)
+            return pctl(ls, 0.5), pctl(ls, 0.99), ls[-1]
+
         p64 = Plan(cfg, sig, dtype="f64", max_batch=1, tile=16)
         fps64, p99_64 = per_frame(p64, slopes64, torch.float64)
+        b50, b99, bmax = burst(p64, slopes64, torch.float64, B)
         q32 = Plan(cfg, sig, dtype="f32", max_batch=1, tile=16)
         fps32, p99_32 = per_frame(q32, slopes32, torch.float32)
         q32.close()
@@ -468,6 +503,14 @@ def main():
                                     "mode": "batch 1, hipGraph replay, tile 16"}
         print(f"[bench] per frame: FP64 {fps64:.1f} frames/s p99 {p99_64:.3f} ms; "
               f"FP32 {fps32:.1f} frames/s p99 {p99_32:.3f} ms", flush=True)
+        result["burst"] = {
+            "frames": B,
+            "plain_fp64_p50_latency_ms": round(b50, 4), "plain_fp64_p99_latency_ms": round(b99, 4),
+            "plain_fp64_frames_per_s": round(1e3 * B / bmax, 2),
+            "batched_fp32_p99_latency_ms": round(p99, 4), "batched_fp32_frames_per_s": round(fps, 2),
+            "mode": "B frames at once: FP64 solved one by one (batch 1, graph) vs FP32 one batched step"}
+        print(f"[bench] burst of {B}: plain FP64 p99 {b99:.3f} ms; batched FP32 p99 {p99:.3f} ms",
+              flush=True)
         result["reconstruction"] = {
             "frame": "stream 0, frame 1, both warm-started from the FP64 30-iteration frame 0",
             "fp32_vs_fp64_coeff_rel_diff": float(
@@ -489,6 +532,10 @@ def main():
     if args.serve_seconds > 0:
         result["served"] = served_stream(args.serve_seconds, args.serve_rate, IT)
         print(f"[bench] served {result['served']}", flush=True)
+        if not args.no_fp64:
+            result["served_plain_fp64"] = served_stream(min(2.0, args.serve_seconds),
+                                                        args.serve_rate, IT, plain_fp64=True)
+            print(f"[bench] served plain FP64 {result['served_plain_fp64']}", flush=True)
 
     out = {
         "metric": "PCG frames/s and p99 frame latency at E-ELT scale; operator HBM GB/s vs peak",

@@ -303,7 +303,7 @@ k_idwt_coarse(const JobArgs args, const Item* __restrict__ items, int in_vec, in
 // input coefficients) on a (TS/2+2)^2 window, writes LL_{k-1} (scratch) or, at
 // k = 1, the layer pixels.
 template <class T, int TS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(TILE_NT)
 k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int in_vec,
             int out_vec) {
     constexpr int CW = TS / 2 + 2;
@@ -337,7 +337,8 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
         ll = Ac;
     }
     const int cx0 = (x0 >> 1) - 2, cy0 = (y0 >> 1) - 2;
-    for (int e = threadIdx.x; e < CW * CW; e += blockDim.x) {
+#pragma unroll
+    for (int e = threadIdx.x; e < CW * CW; e += TILE_NT) {
         const int a = e / CW, b = e % CW;
         int gx = cx0 + a, gy = cy0 + b;   // periodic wrap (|offset| < 2H)
         gx += gx < 0 ? H : 0;
@@ -351,7 +352,8 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
     }
     __syncthreads();
     // along x: output rows 2p and 2p + 1 (x0 is even) from coarse rows p + 2 - t
-    for (int e = threadIdx.x; e < (TS / 2) * CW; e += blockDim.x) {
+#pragma unroll
+    for (int e = threadIdx.x; e < (TS / 2) * CW; e += TILE_NT) {
         const int pr = e / CW, b = e % CW;
         Acc al0 = 0, al1 = 0, ah0 = 0, ah1 = 0;
 #pragma unroll
@@ -374,7 +376,8 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
     T* dst = vptr<T>(J, out_vec, it.frame) + Ly.coff;
     const int ld = level > 1 ? M : N;
     // along y: output columns 2q and 2q + 1 from coarse columns q + 2 - t
-    for (int e = threadIdx.x; e < TS * (TS / 2); e += blockDim.x) {
+#pragma unroll
+    for (int e = threadIdx.x; e < TS * (TS / 2); e += TILE_NT) {
         const int li = e / (TS / 2), q = e % (TS / 2);
         const int i = x0 + li, j = y0 + 2 * q;
         Acc v0 = 0, v1 = 0;
@@ -404,7 +407,7 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
 // through P^T (SRC_PT).  LL_k goes to scratch; the three detail bands go to
 // the output with, under EPI_APPLY, + alpha D_k p and a partial <p, out>.
 template <class T, int TS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(TILE_NT)
 k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int src, int in_vec,
             int out_vec, int epi, int aux_vec) {
     constexpr int HT = TS / 2, PW = TS + 4;
@@ -429,7 +432,7 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
         const T* pv0 = vptr<T>(J, aux_vec, it.frame) + Ly.coff;
 #pragma unroll
         for (int q = 0; q < PQ_PF; ++q) {
-            const int e = threadIdx.x + q * blockDim.x;
+            const int e = threadIdx.x + q * TILE_NT;
             const int X = cx0 + e / HT, Y = cy0 + e % HT;
             pp[q][0] = pp[q][1] = pp[q][2] = 0.0;
             if (e < HT * HT && X < H && Y < H) {
@@ -448,7 +451,8 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
         const double* ind = level > 1 ? vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level - 1] : nullptr;
         const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
         const int ld = level > 1 ? M : N;
-        for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) {
+#pragma unroll
+        for (int e = threadIdx.x; e < PW * PW; e += TILE_NT) {
             const int a = e / PW, b = e % PW;
             int gx = px0 + a, gy = py0 + b;   // periodic wrap
             while (gx >= M) gx -= M;
@@ -458,7 +462,8 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < PW * HT; e += blockDim.x) {
+#pragma unroll
+    for (int e = threadIdx.x; e < PW * HT; e += TILE_NT) {
         const int a = e / HT, c = e % HT;
         Acc lo = 0, hi = 0;
 #pragma unroll
@@ -476,7 +481,8 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     const Acc aD = P.alpha * Ly.D[level - 1];
     double* llo = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level];
     double acc = 0.0;
-    for (int e = threadIdx.x, q = 0; e < HT * HT; e += blockDim.x, ++q) {
+#pragma unroll
+    for (int e = threadIdx.x, q = 0; e < HT * HT; e += TILE_NT, ++q) {
         const int c1 = e / HT, c2 = e % HT;
         const int X = cx0 + c1, Y = cy0 + c2;
         Acc ll = 0, hl = 0, lh = 0, hh = 0;
@@ -1628,11 +1634,11 @@ void launch_idwt_tile(const JobArgs& a, const Item* items, int n, int level, int
                       int out_vec, int tile, int lds_bytes, hipStream_t s) {
     if (n <= 0) return;
     if (tile == 16)
-        hipLaunchKernelGGL((k_idwt_tile<T, 16>), dim3(n), dim3(256), lds_bytes, s, a, items, level, in_vec, out_vec);
+        hipLaunchKernelGGL((k_idwt_tile<T, 16>), dim3(n), dim3(TILE_NT), lds_bytes, s, a, items, level, in_vec, out_vec);
     else if (tile == 64)
-        hipLaunchKernelGGL((k_idwt_tile<T, 64>), dim3(n), dim3(256), lds_bytes, s, a, items, level, in_vec, out_vec);
+        hipLaunchKernelGGL((k_idwt_tile<T, 64>), dim3(n), dim3(TILE_NT), lds_bytes, s, a, items, level, in_vec, out_vec);
     else
-        hipLaunchKernelGGL((k_idwt_tile<T, 32>), dim3(n), dim3(256), lds_bytes, s, a, items, level, in_vec, out_vec);
+        hipLaunchKernelGGL((k_idwt_tile<T, 32>), dim3(n), dim3(TILE_NT), lds_bytes, s, a, items, level, in_vec, out_vec);
 }
 
 template <class T>
@@ -1640,11 +1646,11 @@ void launch_fdwt_tile(const JobArgs& a, const Item* items, int n, int level, int
                       int out_vec, int epi, int aux_vec, int tile, hipStream_t s) {
     if (n <= 0) return;
     if (tile == 16)
-        hipLaunchKernelGGL((k_fdwt_tile<T, 16>), dim3(n), dim3(256), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
+        hipLaunchKernelGGL((k_fdwt_tile<T, 16>), dim3(n), dim3(TILE_NT), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
     else if (tile == 64)
-        hipLaunchKernelGGL((k_fdwt_tile<T, 64>), dim3(n), dim3(256), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
+        hipLaunchKernelGGL((k_fdwt_tile<T, 64>), dim3(n), dim3(TILE_NT), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
     else
-        hipLaunchKernelGGL((k_fdwt_tile<T, 32>), dim3(n), dim3(256), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
+        hipLaunchKernelGGL((k_fdwt_tile<T, 32>), dim3(n), dim3(TILE_NT), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
 }
 
 template <class T>

@@ -3,18 +3,28 @@
 Telescope streams submit slope frames as they arrive.  Every stream belongs
 to a configuration whose plan (tables, Jacobi diagonal, scratch) stays
 resident on the device together with the stream's warm-start coefficients
-(the previous frame's reconstruction, Sec. 5.1).  A worker thread admits the
-oldest pending frame of every stream that has no frame on the GPU, as long as
-the bytes reserved by frames in flight stay within an HBM budget, and packs
-all admitted frames of all configurations into one multi-plan PCG launch
-(``wmcao_solve_multi``, captured as a HIP graph per combination of
-configurations and frame counts and replayed from fixed staging buffers).
-Launches alternate over several HIP streams (default priority) with one plan
-instance per (configuration, HIP stream), so a batch admitted while another
-is on the GPU runs alongside it.  A completion thread
-stamps each frame when its launch's event completes; latency is arrival to
-completion.  Because every frame's reductions are private and ordered, a
-frame's result does not depend on the batch it was packed into.
+(the previous frame's reconstruction, Sec. 5.1).
+
+Each configuration is bound to one HIP stream (a "lane"; default priority),
+and every launch of that configuration goes to its lane, so the host enqueues
+a launch as soon as its frames are admitted, without waiting for the previous
+launch to finish: stream order on the device hands each launch the warm
+starts its predecessor produced.  A worker thread admits, per lane, the
+pending frames of every telescope stream (oldest first, at most `max_frames`
+per stream) while the bytes reserved by frames in flight stay within an HBM
+budget and the lane holds fewer than `depth` launches, and batches them into
+one multi-plan PCG launch (``wmcao_solve_multi``, replayed as a captured HIP
+graph from fixed staging buffers).  The frames of one stream in one launch
+all start from the stream's most recent reconstruction, the result of the
+newest frame of its previous launch, and the newest of them becomes the next
+warm start: when frames arrive one by one, each starts from its predecessor's
+result; a backlog is solved as one batch rather than one frame after another.
+Lanes run side by side on the device, so frames of different configurations
+overlap.  A completion thread stamps each frame when its
+launch's event completes; latency is arrival to completion.  Because every
+frame's reductions are private and ordered, a frame's result does not depend
+on the batch it was packed into.  Result tensors are allocated on the lane's
+HIP stream and complete before their futures resolve.
 """
 import collections
 import threading
@@ -31,9 +41,8 @@ class _Stream:
         self.name = name
         self.cfg = cfg_name
         self.x = torch.zeros(1, n, dtype=dtype, device="cuda")   # warm-start state
-        self.queue = collections.deque()
-        self.busy = False
-        self.frames_done = 0
+        self.queue = collections.deque()                          # frames not yet launched
+        self.submitted = 0
 
 
 class _Frame:
@@ -57,60 +66,69 @@ class Server:
     """Serve PCG solves for telescope streams with continuous batching.
 
     configs: {name: (cfg dict, sigmas)}; streams: {stream name: config name}.
-    hbm_budget: bytes that frames in flight may reserve (default: half of the
-    free device memory at start).  keep_inputs: keep each frame's warm start
-    (for invariance checks).  graphs: replay captured launches.  tile: tile
-    edge of the wavelet kernels (0 = library default; 16 favours latency).
-    pack: put frames of several configurations into one launch (throughput);
-    otherwise each configuration's frames go to a launch of their own, which
-    runs alongside the others on its own HIP stream (latency)."""
+    hip_streams: number of lanes (default: one per configuration); configuration
+    i uses lane i mod hip_streams.  hbm_budget: bytes that frames in flight may
+    reserve (default: half of the free device memory at start).  depth: launches
+    a lane may hold in flight.  max_frames: frames of one telescope stream in
+    one launch.  keep_inputs: keep each frame's warm start (for
+    invariance checks).  graphs: replay captured launches.  tile: tile edge of
+    the wavelet kernels (0 = library default; 16 favours latency).  pack: when
+    a lane serves several configurations, put their frames into one launch;
+    otherwise one configuration per launch, in turn."""
 
-    def __init__(self, configs, streams, dtype="f32", n_iter=10, hip_streams=2,
-                 hbm_budget=None, keep_inputs=False, graphs=True, tile=0, pack=True):
+    def __init__(self, configs, streams, dtype="f32", n_iter=10, hip_streams=None,
+                 hbm_budget=None, keep_inputs=False, graphs=True, tile=0, pack=True, depth=2,
+                 max_frames=8):
         self.dtype = dtype
         self.n_iter = int(n_iter)
         self.keep_inputs = keep_inputs
         self.graphs = graphs
         self.pack = pack
-        self.hip_streams = [torch.cuda.Stream() for _ in range(hip_streams)]
-        count = collections.Counter(streams.values())
-        # one plan per (configuration, HIP stream), batch = streams of that config
-        self.plans = {c: [Plan(cfg, sig, dtype=dtype, max_batch=count[c], tile=tile)
-                          for _ in range(hip_streams)]
-                      for c, (cfg, sig) in configs.items() if count[c]}
-        self.n = {c: p[0].n for c, p in self.plans.items()}
-        self.n_slopes = {c: p[0].n_slopes for c, p in self.plans.items()}
-        tdt = self.plans[next(iter(self.plans))][0].torch_dtype
+        self.depth = max(1, int(depth))
+        self.max_frames = max(1, int(max_frames))
+        # frames of a configuration in one launch: max_frames per telescope stream
+        count = {c: k * self.max_frames for c, k in collections.Counter(streams.values()).items()}
+        names = [c for c in configs if count.get(c)]
+        n_lanes = min(len(names), int(hip_streams) if hip_streams else len(names))
+        self.lanes = [torch.cuda.Stream() for _ in range(n_lanes)]
+        self.lane_of = {c: i % n_lanes for i, c in enumerate(names)}
+        self.lane_cfgs = [[c for c in names if self.lane_of[c] == i] for i in range(n_lanes)]
+        # one plan per configuration (its launches are ordered on its lane),
+        # batch = the telescope streams of that configuration
+        self.plans = {c: Plan(configs[c][0], configs[c][1], dtype=dtype, max_batch=count[c],
+                              tile=tile) for c in names}
+        self.n = {c: p.n for c, p in self.plans.items()}
+        self.n_slopes = {c: p.n_slopes for c, p in self.plans.items()}
+        tdt = self.plans[names[0]].torch_dtype
         self.torch_dtype = tdt
         self.streams = {s: _Stream(s, c, self.n[c], tdt) for s, c in streams.items()}
-        # fixed staging buffers per (configuration, HIP stream): graph replays
-        # read the slopes and warm starts from, and leave the results in, them
-        self.stage = {c: [(torch.zeros(count[c], self.n_slopes[c], dtype=tdt, device="cuda"),
-                           torch.zeros(count[c], self.n[c], dtype=tdt, device="cuda"))
-                          for _ in range(hip_streams)] for c in self.plans}
+        self.cfg_streams = {c: [st for st in self.streams.values() if st.cfg == c] for c in names}
+        # fixed staging buffers per configuration: graph replays read the
+        # slopes and warm starts from, and leave the results in, them
+        self.stage = {c: (torch.zeros(count[c], self.n_slopes[c], dtype=tdt, device="cuda"),
+                          torch.zeros(count[c], self.n[c], dtype=tdt, device="cuda"))
+                      for c in names}
         if graphs:
             # capture the one-configuration launches up front, so that no frame
             # waits for a graph to be recorded
-            for c, ps in self.plans.items():
-                for hs, plan in enumerate(ps):
-                    Sb, Xb = self.stage[c][hs]
-                    with torch.cuda.stream(self.hip_streams[hs]):
-                        for k in range(1, count[c] + 1):
-                            solve_multi([plan], [Sb[:k]], [Xb[:k]], n_iter=self.n_iter,
-                                        warm_start=True, graph=True)
+            for c, plan in self.plans.items():
+                Sb, Xb = self.stage[c]
+                with torch.cuda.stream(self.lanes[self.lane_of[c]]):
+                    for k in range(1, count[c] + 1):
+                        solve_multi([plan], [Sb[:k]], [Xb[:k]], n_iter=self.n_iter,
+                                    warm_start=True, graph=True)
             torch.cuda.synchronize()
         esz = torch.empty(0, dtype=tdt).element_size()
         # bytes a frame in flight reserves: slopes + state + the plan scratch of one frame
-        self.frame_bytes = {c: esz * (self.n_slopes[c] + 7 * self.n[c]) for c in self.plans}
+        self.frame_bytes = {c: esz * (self.n_slopes[c] + 7 * self.n[c]) for c in names}
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info()
             hbm_budget = free // 2
         self.hbm_budget = int(hbm_budget)
         self.reserved = 0
         self.cv = threading.Condition()
-        self.inflight = collections.deque()
-        self.next_hs = 0
-        self.hs_busy = [False] * hip_streams
+        self.inflight = [collections.deque() for _ in self.lanes]   # per lane, in launch order
+        self.turn = [0] * n_lanes                                   # next configuration (no packing)
         self.running = True
         self.records = []
         self.launches = 0
@@ -123,13 +141,15 @@ class Server:
     # ---- client side ---------------------------------------------------------
     def submit(self, stream, slopes):
         """Queue one frame (device tensor of the plan dtype, n_slopes values);
-        returns a Future resolving to the reconstruction coefficients."""
+        returns a Future resolving to (reconstruction coefficients, warm start
+        or None)."""
         st = self.streams[stream]
         if slopes.dtype != self.torch_dtype or not slopes.is_cuda:
             slopes = slopes.to(device="cuda", dtype=self.torch_dtype)
         slopes = slopes.reshape(1, -1).contiguous()
         with self.cv:
-            fr = _Frame(st, slopes, st.frames_done + len(st.queue))
+            fr = _Frame(st, slopes, st.submitted)
+            st.submitted += 1
             st.queue.append(fr)
             self.cv.notify_all()
         return fr.future
@@ -140,122 +160,132 @@ class Server:
             self.cv.notify_all()
         self.worker.join()
         self.completer.join()
-        for ps in self.plans.values():
-            for p in ps:
-                p.close()
+        for p in self.plans.values():
+            p.close()
 
     # ---- worker --------------------------------------------------------------
-    def _admit(self):
-        """Frames to launch now: the oldest pending frame of every idle stream,
-        within the HBM budget, grouped per configuration (one configuration per
-        launch unless packing)."""
+    def _admit_lane(self, lane):
+        """Frames for one launch on a lane: the oldest pending frame of every
+        telescope stream of the lane's configurations (one configuration, in
+        turn, unless packing), within the HBM budget."""
+        cfgs = self.lane_cfgs[lane]
+        if not self.pack and len(cfgs) > 1:
+            order = cfgs[self.turn[lane]:] + cfgs[:self.turn[lane]]
+            for c in order:
+                if any(st.queue for st in self.cfg_streams[c]):
+                    cfgs = [c]
+                    self.turn[lane] = (self.lane_cfgs[lane].index(c) + 1) % len(self.lane_cfgs[lane])
+                    break
         groups = collections.OrderedDict()
-        for st in self.streams.values():
-            if st.busy or not st.queue:
-                continue
-            if not self.pack and groups and st.cfg not in groups:
-                continue
-            need = self.frame_bytes[st.cfg]
-            if self.reserved + need > self.hbm_budget:
-                continue
-            self.reserved += need
-            st.busy = True
-            groups.setdefault(st.cfg, []).append(st.queue.popleft())
+        for c in cfgs:
+            need = self.frame_bytes[c]
+            for st in self.cfg_streams[c]:
+                frs = []
+                while st.queue and len(frs) < self.max_frames and \
+                        self.reserved + need <= self.hbm_budget:
+                    self.reserved += need
+                    frs.append(st.queue.popleft())
+                if frs:
+                    groups.setdefault(c, []).append((st, frs))
         return groups
 
+    def _idle(self):
+        return not any(st.queue for st in self.streams.values()) and not any(self.inflight)
+
     def _loop(self):
+        pending = [0] * len(self.lanes)   # launches admitted but not yet in flight
         while True:
             with self.cv:
                 while True:
-                    free_hs = [i for i, b in enumerate(self.hs_busy) if not b]
-                    groups = self._admit() if free_hs else {}
-                    if groups:
+                    work = []
+                    for lane in range(len(self.lanes)):
+                        if len(self.inflight[lane]) + pending[lane] >= self.depth:
+                            continue
+                        groups = self._admit_lane(lane)
+                        if groups:
+                            work.append((lane, groups))
+                            pending[lane] += 1
+                    if work:
                         break
-                    if not self.running and not any(s.queue for s in self.streams.values()) \
-                            and not any(self.hs_busy):
+                    if not self.running and self._idle():
                         self.cv.notify_all()
                         return
                     self.cv.wait(timeout=0.05)
-                hs = free_hs[0]
-                self.hs_busy[hs] = True
-            self._launch(hs, groups)
+            for lane, groups in work:
+                self._launch(lane, groups)
+                pending[lane] -= 1
 
-    def _launch(self, hs, groups):
-        stream = self.hip_streams[hs]
+    def _launch(self, lane, groups):
+        stream = self.lanes[lane]
         t_launch = time.perf_counter()
-        for frs in groups.values():
-            for f in frs:
-                f.t_launch = t_launch
-        plans, slopes, coeffs, frames = [], [], [], []
+        plans, slopes, coeffs, spans = [], [], [], []
         with torch.cuda.stream(stream):
-            for frs in groups.values():
-                for f in frs:
-                    stream.wait_event(f.ready)
-            for cfg, frs in groups.items():
-                plan = self.plans[cfg][hs]
-                if self.graphs:
-                    Sb, Xb = self.stage[cfg][hs]
-                    S, X = Sb[:len(frs)], Xb[:len(frs)]
-                    for k, f in enumerate(frs):
-                        S[k].copy_(f.slopes[0])
-                        X[k].copy_(f.stream.x[0])
-                else:
-                    S = torch.cat([f.slopes for f in frs]) if len(frs) > 1 else frs[0].slopes
-                    X = torch.cat([f.stream.x for f in frs]) if len(frs) > 1 else frs[0].stream.x
-                if self.keep_inputs:
+            for per_stream in groups.values():
+                for st, frs in per_stream:
                     for f in frs:
-                        f.x0 = f.stream.x.clone()
-                plans.append(plan)
-                slopes.append(S)
-                coeffs.append(X)
-                frames.append(frs)
+                        f.t_launch = t_launch
+                        stream.wait_event(f.ready)
+                        f.slopes.record_stream(stream)   # read on the lane after the caller's work
+            for cfg, per_stream in groups.items():
+                Sb, Xb = self.stage[cfg]
+                k = 0
+                for st, frs in per_stream:
+                    m = len(frs)
+                    for i, f in enumerate(frs):
+                        Sb[k + i].copy_(f.slopes[0])
+                    # the stream's latest reconstruction (lane order) for all its frames
+                    Xb[k:k + m].copy_(st.x.expand(m, -1))
+                    if self.keep_inputs:
+                        x0 = st.x.clone()
+                        for f in frs:
+                            f.x0 = x0
+                    spans.append((cfg, st, frs, k))
+                    k += m
+                plans.append(self.plans[cfg])
+                slopes.append(Sb[:k])
+                coeffs.append(Xb[:k])
             solve_multi(plans, slopes, coeffs, n_iter=self.n_iter, warm_start=True,
                         graph=self.graphs)
             results = []
-            for X, frs in zip(coeffs, frames):
-                for k, f in enumerate(frs):
-                    if X is not f.stream.x:
-                        f.stream.x.copy_(X[k:k + 1])
-                    results.append((f, f.stream.x.clone()))
+            for cfg, st, frs, k in spans:
+                Xb = self.stage[cfg][1]
+                m = len(frs)
+                st.x.copy_(Xb[k + m - 1:k + m])   # the newest frame's result
+                res = Xb[k:k + m].clone()
+                for i, f in enumerate(frs):
+                    results.append((f, res[i:i + 1]))
             ev = torch.cuda.Event()
             ev.record(stream)
-        self.launches += 1
-        self.frames_in_launch.append(len(results))
         with self.cv:
-            self.inflight.append((ev, hs, results))
+            self.launches += 1
+            self.frames_in_launch.append(len(results))
+            self.inflight[lane].append((ev, results))
             self.cv.notify_all()
 
     def _complete(self):
         while True:
             with self.cv:
-                while not self.inflight:
-                    if not self.running and not any(s.queue for s in self.streams.values()) \
-                            and not any(self.hs_busy):
+                while not any(self.inflight):
+                    if not self.running and self._idle() and not self.worker.is_alive():
                         return
                     self.cv.wait(timeout=0.05)
-                pending = list(self.inflight)
-            done = None
-            for item in pending:
-                if item[0].query():
-                    done = item
-                    break
-            if done is None:
+                heads = [(lane, q[0]) for lane, q in enumerate(self.inflight) if q]
+            done = [(lane, item) for lane, item in heads if item[0].query()]
+            if not done:
                 time.sleep(2e-5)
                 continue
             t = time.perf_counter()
-            ev, hs, results = done
             with self.cv:
-                self.inflight.remove(done)
-                self.hs_busy[hs] = False
-                for f, _ in results:
-                    f.t_done = t
-                    f.stream.busy = False
-                    f.stream.frames_done += 1
-                    self.reserved -= self.frame_bytes[f.stream.cfg]
-                    self.records.append((f.stream.name, f.index, f.t_arrival, t, f.t_launch))
+                for lane, (ev, results) in done:
+                    self.inflight[lane].popleft()
+                    for f, _ in results:
+                        f.t_done = t
+                        self.reserved -= self.frame_bytes[f.stream.cfg]
+                        self.records.append((f.stream.name, f.index, f.t_arrival, t, f.t_launch))
                 self.cv.notify_all()
-            for f, x in results:
-                f.future.set_result((x, f.x0))
+            for lane, (ev, results) in done:
+                for f, x in results:
+                    f.future.set_result((x, f.x0))
 
     # ---- statistics ------------------------------------------------------------
     def latencies_ms(self):
