@@ -23,6 +23,7 @@
 // partial per block, summed by the consumer), so a frame's result does not
 // depend on what else is in the batch.
 #include <initializer_list>
+#include <type_traits>
 
 #include "wmcao_internal.hpp"
 
@@ -211,8 +212,11 @@ __device__ __forceinline__ void node_stencil(double pa, double pb, int i, int N,
 // (periodic indices, px0 + PR < 2N), written into G (row stride ldg, FP64):
 // the sum, in sensor order, of the footprint images of the sensors in mask
 // (k_adjoint).  A thread owns one window column and every rstep-th row, so
-// each G entry has one writer: no atomics and no barrier.
-template <class T>
+// each G entry has one writer: no atomics and no barrier.  Rows go in chunks
+// of RC held in registers, two sensors per step; every load goes to a valid
+// address (clamped) with the value selected afterwards, so the 2 RC loads of
+// a step are all in flight before the first is added.
+template <class T, int RC>
 __device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, int px0, int py0,
                                  int PR, int PC, Acc* G, int ldg, unsigned mask) {
     const int tid = threadIdx.x, bd = blockDim.x;
@@ -232,35 +236,49 @@ __device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, i
     for (int c = c0; c < PC; c += cstep) {
         int gy = py0 + c;
         if (gy >= N) gy -= N;
-        for (int r = r0; r < PR; r += rstep) G[r * ldg + c] = 0;
-        // two sensors per step (uniform indices): both images are loaded
-        // before either is added, in sensor order
-        unsigned mm = mask;
-        while (mm) {
-            const int ma = __ffs(static_cast<int>(mm)) - 1;
-            mm &= mm - 1;
-            const int mb = mm ? __ffs(static_cast<int>(mm)) - 1 : ma;
-            const bool hb = mm != 0;
-            if (hb) mm &= mm - 1;
-            const int yca = gy - P.fp_y0[ma][l], Wa = P.fp_w[ma][l];
-            const int ycb = gy - P.fp_y0[mb][l], Wb = P.fp_w[mb][l];
-            const bool ca = yca >= 0 && yca < Wa, cb = hb && ycb >= 0 && ycb < Wb;
-            const int xa = P.fp_x0[ma][l], Ha = P.fp_h[ma][l];
-            const int xb = P.fp_x0[mb][l], Hb = P.fp_h[mb][l];
-            const T* ia = img + P.fp_off[ma][l] + yca;
-            const T* ib = img + P.fp_off[mb][l] + ycb;
-            for (int r = r0; r < PR; r += rstep) {
-                int gx = px0 + r;
-                if (gx >= N) gx -= N;
-                const int ra = gx - xa, rb = gx - xb;
-                const bool la = ca && ra >= 0 && ra < Ha, lb = cb && rb >= 0 && rb < Hb;
-                const Acc va = la ? static_cast<Acc>(ia[ra * Wa]) : 0.0;
-                const Acc vb = lb ? static_cast<Acc>(ib[rb * Wb]) : 0.0;
-                Acc g = G[r * ldg + c];
-                if (la) g += va;
-                if (lb) g += vb;
-                G[r * ldg + c] = g;
+        for (int rb = r0; rb < PR; rb += RC * rstep) {
+            int gx[RC];
+            Acc g[RC];
+#pragma unroll
+            for (int k = 0; k < RC; ++k) {
+                const int r = rb + k * rstep;
+                gx[k] = px0 + r >= N ? px0 + r - N : px0 + r;
+                gx[k] = r < PR ? gx[k] : -1;   // a row past the window is in no footprint
+                g[k] = 0.0;
             }
+            unsigned mm = mask;
+            while (mm) {
+                const int ma = __ffs(static_cast<int>(mm)) - 1;
+                mm &= mm - 1;
+                const int mb = mm ? __ffs(static_cast<int>(mm)) - 1 : ma;
+                const bool hb = mm != 0;
+                if (hb) mm &= mm - 1;
+                const int yca = gy - P.fp_y0[ma][l], Wa = P.fp_w[ma][l];
+                const int ycb = gy - P.fp_y0[mb][l], Wb = P.fp_w[mb][l];
+                const bool ca = yca >= 0 && yca < Wa, cb = hb && ycb >= 0 && ycb < Wb;
+                const int xa = P.fp_x0[ma][l], Ha = P.fp_h[ma][l];
+                const int xb = P.fp_x0[mb][l], Hb = P.fp_h[mb][l];
+                const T* ia = img + P.fp_off[ma][l];
+                const T* ib = img + P.fp_off[mb][l];
+                T va[RC], vb[RC];
+                bool la[RC], lb[RC];
+#pragma unroll
+                for (int k = 0; k < RC; ++k) {
+                    const int ra = gx[k] - xa, rb2 = gx[k] - xb;
+                    la[k] = ca && ra >= 0 && ra < Ha;
+                    lb[k] = cb && rb2 >= 0 && rb2 < Hb;
+                    va[k] = ia[la[k] ? ra * Wa + yca : 0];
+                    vb[k] = ib[lb[k] ? rb2 * Wb + ycb : 0];
+                }
+#pragma unroll
+                for (int k = 0; k < RC; ++k) {
+                    if (la[k]) g[k] += static_cast<Acc>(va[k]);
+                    if (lb[k]) g[k] += static_cast<Acc>(vb[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < RC; ++k)
+                if (rb + k * rstep < PR) G[(rb + k * rstep) * ldg + c] = g[k];
         }
     }
 }
@@ -426,39 +444,56 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     load_filters(P, hf, gf);
     // p at this thread's first epilogue coefficients, loaded before the window
     // so that its latency overlaps the analysis
+    // Loads below go to clamped, always valid addresses with the value
+    // selected afterwards, so that none sits under a branch of its own (such
+    // a load is waited for at the branch's end, serialising the loop).
     constexpr int PQ_PF = 2;
-    Acc pp[PQ_PF][3];
-    if (epi == EPI_APPLY) {
-        const T* pv0 = vptr<T>(J, aux_vec, it.frame) + Ly.coff;
+    T pp[PQ_PF][3];
+    {
+        const T* pv0 = vptr<T>(J, aux_vec, it.frame) + Ly.coff;   // valid for every caller
 #pragma unroll
         for (int q = 0; q < PQ_PF; ++q) {
             const int e = threadIdx.x + q * TILE_NT;
-            const int X = cx0 + e / HT, Y = cy0 + e % HT;
-            pp[q][0] = pp[q][1] = pp[q][2] = 0.0;
-            if (e < HT * HT && X < H && Y < H) {
-                pp[q][0] = pv0[static_cast<int64_t>(X) * N + H + Y];
-                pp[q][1] = pv0[static_cast<int64_t>(H + X) * N + Y];
-                pp[q][2] = pv0[static_cast<int64_t>(H + X) * N + H + Y];
-            }
+            int X = cx0 + e / HT, Y = cy0 + e % HT;
+            const bool ok = e < HT * HT && X < H && Y < H;
+            X = ok ? X : 0;
+            Y = ok ? Y : 0;
+            pp[q][0] = pv0[static_cast<int64_t>(X) * N + H + Y];
+            pp[q][1] = pv0[static_cast<int64_t>(H + X) * N + Y];
+            pp[q][2] = pv0[static_cast<int64_t>(H + X) * N + H + Y];
         }
     }
+    constexpr int WIN_IT = (PW * PW + TILE_NT - 1) / TILE_NT;
     if (level == 1 && src == SRC_PT) {
-        pt_gather_window<T>(P, vptr<T>(J, in_vec, it.frame), it.a, N, px0, py0, PW, PW,
-                            &sA[0][0], PW + 1,
-                            static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a] + it.b]));
-    } else {
-        // level > 1: the low-pass band of the level below (FP64 scratch)
-        const double* ind = level > 1 ? vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level - 1] : nullptr;
-        const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
-        const int ld = level > 1 ? M : N;
+        // rows per thread of the PW x PW window, at most 8 per register chunk
+        constexpr int RPT = (PW + TILE_NT / PW - 1) / (TILE_NT / PW);
+        pt_gather_window<T, (RPT < 8 ? RPT : 8)>(P, vptr<T>(J, in_vec, it.frame), it.a, N, px0, py0,
+                                                 PW, PW, &sA[0][0], PW + 1,
+                                                 static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a] + it.b]));
+    } else if (level > 1) {
+        // the low-pass band of the level below (FP64 scratch)
+        const double* ind = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level - 1];
 #pragma unroll
-        for (int e = threadIdx.x; e < PW * PW; e += TILE_NT) {
+        for (int k = 0; k < WIN_IT; ++k) {
+            const int e0 = threadIdx.x + k * TILE_NT, e = min(e0, PW * PW - 1);
             const int a = e / PW, b = e % PW;
             int gx = px0 + a, gy = py0 + b;   // periodic wrap
             while (gx >= M) gx -= M;
             while (gy >= M) gy -= M;
-            const int64_t gi = static_cast<int64_t>(gx) * ld + gy;
-            sA[a][b] = level > 1 ? ind[gi] : static_cast<Acc>(in[gi]);
+            const double v = ind[static_cast<int64_t>(gx) * M + gy];
+            if (e0 < PW * PW) sA[a][b] = v;
+        }
+    } else {
+        const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
+#pragma unroll
+        for (int k = 0; k < WIN_IT; ++k) {
+            const int e0 = threadIdx.x + k * TILE_NT, e = min(e0, PW * PW - 1);
+            const int a = e / PW, b = e % PW;
+            int gx = px0 + a, gy = py0 + b;   // periodic wrap
+            while (gx >= M) gx -= M;
+            while (gy >= M) gy -= M;
+            const T v = in[static_cast<int64_t>(gx) * N + gy];
+            if (e0 < PW * PW) sA[a][b] = static_cast<Acc>(v);
         }
     }
     __syncthreads();
@@ -477,14 +512,17 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     }
     __syncthreads();
     T* out = vptr<T>(J, out_vec, it.frame) + Ly.coff;
-    const T* pv = (epi == EPI_APPLY) ? vptr<T>(J, aux_vec, it.frame) + Ly.coff : nullptr;
+    const T* pv = vptr<T>(J, aux_vec, it.frame) + Ly.coff;   // valid for every caller
     const Acc aD = P.alpha * Ly.D[level - 1];
     double* llo = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level];
     double acc = 0.0;
+    constexpr int EPI_IT = (HT * HT + TILE_NT - 1) / TILE_NT;
 #pragma unroll
-    for (int e = threadIdx.x, q = 0; e < HT * HT; e += TILE_NT, ++q) {
-        const int c1 = e / HT, c2 = e % HT;
+    for (int q = 0; q < EPI_IT; ++q) {
+        const int e = threadIdx.x + q * TILE_NT, ec = min(e, HT * HT - 1);
+        const int c1 = ec / HT, c2 = ec % HT;
         const int X = cx0 + c1, Y = cy0 + c2;
+        const bool ok = e < HT * HT && X < H && Y < H;
         Acc ll = 0, hl = 0, lh = 0, hh = 0;
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
@@ -494,15 +532,17 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
             lh += hf[n] * h;
             hh += gf[n] * h;
         }
-        if (X < H && Y < H) {
+        const int Xc = ok ? X : 0, Yc = ok ? Y : 0;
+        const int64_t iLH = static_cast<int64_t>(Xc) * N + H + Yc;
+        const int64_t iHL = static_cast<int64_t>(H + Xc) * N + Yc;
+        const int64_t iHH = static_cast<int64_t>(H + Xc) * N + H + Yc;
+        const T pr1 = q < PQ_PF ? pp[q][0] : pv[iLH];
+        const T pr2 = q < PQ_PF ? pp[q][1] : pv[iHL];
+        const T pr3 = q < PQ_PF ? pp[q][2] : pv[iHH];
+        if (ok) {
             llo[X * H + Y] = ll;
-            const int64_t iLH = static_cast<int64_t>(X) * N + H + Y;
-            const int64_t iHL = static_cast<int64_t>(H + X) * N + Y;
-            const int64_t iHH = static_cast<int64_t>(H + X) * N + H + Y;
             if (epi == EPI_APPLY) {
-                const Acc p1 = q < PQ_PF ? pp[q][0] : static_cast<Acc>(pv[iLH]);
-                const Acc p2 = q < PQ_PF ? pp[q][1] : static_cast<Acc>(pv[iHL]);
-                const Acc p3 = q < PQ_PF ? pp[q][2] : static_cast<Acc>(pv[iHH]);
+                const Acc p1 = pr1, p2 = pr2, p3 = pr3;
                 const T o1 = static_cast<T>(lh + aD * p1);
                 const T o2 = static_cast<T>(hl + aD * p2);
                 const T o3 = static_cast<T>(hh + aD * p3);
@@ -549,7 +589,7 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
         const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
         for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = in[e];
     } else {
-        pt_gather_window<T>(P, vptr<T>(J, in_vec, it.frame), it.a, N, 0, 0, N, N, A, N,
+        pt_gather_window<T, 4>(P, vptr<T>(J, in_vec, it.frame), it.a, N, 0, 0, N, N, A, N,
                             static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a]]));
     }
     __syncthreads();
@@ -1228,9 +1268,12 @@ __device__ __forceinline__ bool can_vec4(int64_t n, std::initializer_list<const 
     return bits == 0;
 }
 
-template <class T>
-__device__ __forceinline__ void ld4(const T* p, int64_t i, int64_t n, bool vec, Acc* v) {
-    if (vec) {
+// VEC is a compile-time flag so that no load sits under a run-time branch of
+// its own (a load inside a divergent branch is waited for at the branch's end,
+// which serialises the loads of a loop).
+template <bool VEC, class T>
+__device__ __forceinline__ void ld4(const T* p, int64_t i, int64_t n, Acc* v) {
+    if constexpr (VEC) {
         if constexpr (sizeof(T) == 4) {
             const float4 q = *reinterpret_cast<const float4*>(p + i);
             v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
@@ -1245,9 +1288,9 @@ __device__ __forceinline__ void ld4(const T* p, int64_t i, int64_t n, bool vec, 
     }
 }
 
-template <class T>
-__device__ __forceinline__ void st4(T* p, int64_t i, int64_t n, bool vec, const T* v) {
-    if (vec) {
+template <bool VEC, class T>
+__device__ __forceinline__ void st4(T* p, int64_t i, int64_t n, const T* v) {
+    if constexpr (VEC) {
         if constexpr (sizeof(T) == 4) {
             *reinterpret_cast<float4*>(p + i) = make_float4(v[0], v[1], v[2], v[3]);
         } else {
@@ -1279,27 +1322,36 @@ k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
     const bool vec = can_vec4(P.n, {x, b, q, r, p, jac});
     Acc rz = 0.0, rr = 0.0;
     const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
-    for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
-        const int64_t i = i0 + k;
-        if (i >= P.n) break;
-        Acc bv[4], qv[4], jv[4];
-        T rs[4], ps[4], zero[4] = {0, 0, 0, 0};
-        ld4(b, i, P.n, vec, bv);
-        ld4(jac, i, P.n, vec, jv);
-        if (warm) ld4(q, i, P.n, vec, qv);
+    const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
+    const bool pre_ = P.precond != 0;
+    auto sweep = [&](auto vec_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value;
+        for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
+            const int64_t i = i0 + k;
+            if (i >= n_) break;
+            Acc bv[4], qv[4], jv[4];
+            T rs[4], ps[4], zero[4] = {0, 0, 0, 0};
+            ld4<VEC>(b, i, n_, bv);
+            ld4<VEC>(jac, i, n_, jv);
+            if (warm) ld4<VEC>(q, i, n_, qv);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            rs[j] = static_cast<T>(warm ? bv[j] - qv[j] : bv[j]);
-            const Acc rv = rs[j];
-            const Acc z = (P.precond && i + j < P.n) ? rv / jv[j] : rv;
-            ps[j] = static_cast<T>(z);
-            rz += rv * z;
-            rr += rv * rv;
+            for (int j = 0; j < 4; ++j) {
+                rs[j] = static_cast<T>(warm ? bv[j] - qv[j] : bv[j]);
+                const Acc rv = rs[j];
+                const Acc z = (pre_ && i + j < n_) ? rv / jv[j] : rv;
+                ps[j] = static_cast<T>(z);
+                rz += rv * z;
+                rr += rv * rv;
+            }
+            st4<VEC>(r, i, n_, rs);
+            st4<VEC>(p, i, n_, ps);
+            if (!warm) st4<VEC>(x, i, n_, zero);
         }
-        st4(r, i, P.n, vec, rs);
-        st4(p, i, P.n, vec, ps);
-        if (!warm) st4(x, i, P.n, vec, zero);
-    }
+    };
+    if (vec)
+        sweep(std::true_type{});
+    else
+        sweep(std::false_type{});
     rz = block_sum(rz, red);
     rr = block_sum(rr, red);
     if (threadIdx.x == 0) {
@@ -1347,24 +1399,33 @@ k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
     const bool vec = can_vec4(P.n, {r, q, jac});
     Acc rz = 0.0, rr = 0.0;
     const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
-    for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
-        const int64_t i = i0 + k;
-        if (i >= P.n) break;
-        Acc rv[4], qv[4], jv[4];
-        T rs[4];
-        ld4(r, i, P.n, vec, rv);
-        ld4(q, i, P.n, vec, qv);
-        ld4(jac, i, P.n, vec, jv);
+    const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
+    const bool pre_ = P.precond != 0;
+    auto sweep = [&](auto vec_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value;
+        for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
+            const int64_t i = i0 + k;
+            if (i >= n_) break;
+            Acc rv[4], qv[4], jv[4];
+            T rs[4];
+            ld4<VEC>(r, i, n_, rv);
+            ld4<VEC>(q, i, n_, qv);
+            ld4<VEC>(jac, i, n_, jv);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            rs[j] = static_cast<T>(rv[j] - a * qv[j]);
-            const Acc v = rs[j];
-            const Acc z = (P.precond && i + j < P.n) ? v / jv[j] : v;
-            rz += v * z;
-            rr += v * v;
+            for (int j = 0; j < 4; ++j) {
+                rs[j] = static_cast<T>(rv[j] - a * qv[j]);
+                const Acc v = rs[j];
+                const Acc z = (pre_ && i + j < n_) ? v / jv[j] : v;
+                rz += v * z;
+                rr += v * v;
+            }
+            st4<VEC>(r, i, n_, rs);
         }
-        st4(r, i, P.n, vec, rs);
-    }
+    };
+    if (vec)
+        sweep(std::true_type{});
+    else
+        sweep(std::false_type{});
     rz = block_sum(rz, red);
     rr = block_sum(rr, red);
     if (threadIdx.x == 0) {
@@ -1406,24 +1467,33 @@ k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
     const T* jac = reinterpret_cast<const T*>(P.jac);
     const bool vec = can_vec4(P.n, {x, p, r, jac});
     const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
-    for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
-        const int64_t i = i0 + k;
-        if (i >= P.n) break;
-        Acc pv[4], xv[4], rv[4], jv[4];
-        T xs[4], ps[4];
-        ld4(p, i, P.n, vec, pv);
-        ld4(x, i, P.n, vec, xv);
-        ld4(r, i, P.n, vec, rv);
-        ld4(jac, i, P.n, vec, jv);
+    const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
+    const bool pre_ = P.precond != 0;
+    auto sweep = [&](auto vec_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value;
+        for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
+            const int64_t i = i0 + k;
+            if (i >= n_) break;
+            Acc pv[4], xv[4], rv[4], jv[4];
+            T xs[4], ps[4];
+            ld4<VEC>(p, i, n_, pv);
+            ld4<VEC>(x, i, n_, xv);
+            ld4<VEC>(r, i, n_, rv);
+            ld4<VEC>(jac, i, n_, jv);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            xs[j] = static_cast<T>(xv[j] + a * pv[j]);
-            const Acc z = (P.precond && i + j < P.n) ? rv[j] / jv[j] : rv[j];
-            ps[j] = static_cast<T>(z + beta * pv[j]);
+            for (int j = 0; j < 4; ++j) {
+                xs[j] = static_cast<T>(xv[j] + a * pv[j]);
+                const Acc z = (pre_ && i + j < n_) ? rv[j] / jv[j] : rv[j];
+                ps[j] = static_cast<T>(z + beta * pv[j]);
+            }
+            st4<VEC>(x, i, n_, xs);
+            st4<VEC>(p, i, n_, ps);
         }
-        st4(x, i, P.n, vec, xs);
-        st4(p, i, P.n, vec, ps);
-    }
+    };
+    if (vec)
+        sweep(std::true_type{});
+    else
+        sweep(std::false_type{});
 }
 
 // Residual replacement: r = b - A x (A x in V_Q), fresh partials for rho_i.
@@ -1442,24 +1512,33 @@ k_replace_r(const JobArgs args, const Item* __restrict__ items, int iter) {
     const bool vec = can_vec4(P.n, {b, q, r, jac});
     Acc rz = 0.0, rr = 0.0;
     const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
-    for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
-        const int64_t i = i0 + k;
-        if (i >= P.n) break;
-        Acc bv[4], qv[4], jv[4];
-        T rs[4];
-        ld4(b, i, P.n, vec, bv);
-        ld4(q, i, P.n, vec, qv);
-        ld4(jac, i, P.n, vec, jv);
+    const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
+    const bool pre_ = P.precond != 0;
+    auto sweep = [&](auto vec_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value;
+        for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
+            const int64_t i = i0 + k;
+            if (i >= n_) break;
+            Acc bv[4], qv[4], jv[4];
+            T rs[4];
+            ld4<VEC>(b, i, n_, bv);
+            ld4<VEC>(q, i, n_, qv);
+            ld4<VEC>(jac, i, n_, jv);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            rs[j] = static_cast<T>(bv[j] - qv[j]);
-            const Acc v = rs[j];
-            const Acc z = (P.precond && i + j < P.n) ? v / jv[j] : v;
-            rz += v * z;
-            rr += v * v;
+            for (int j = 0; j < 4; ++j) {
+                rs[j] = static_cast<T>(bv[j] - qv[j]);
+                const Acc v = rs[j];
+                const Acc z = (pre_ && i + j < n_) ? v / jv[j] : v;
+                rz += v * z;
+                rr += v * v;
+            }
+            st4<VEC>(r, i, n_, rs);
         }
-        st4(r, i, P.n, vec, rs);
-    }
+    };
+    if (vec)
+        sweep(std::true_type{});
+    else
+        sweep(std::false_type{});
     rz = block_sum(rz, red);
     rr = block_sum(rr, red);
     if (threadIdx.x == 0) {
