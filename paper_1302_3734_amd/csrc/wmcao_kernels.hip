@@ -645,6 +645,10 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
     // bilinear stencils of the block's node rows and of every node column, per layer
     __shared__ int ri0[WM_MAXL][PROJ_ROWS + 1], cj0[WM_MAXL][WM_NSUB_MAX + 1];
     __shared__ double rtw[WM_MAXL][PROJ_ROWS + 1], csw[WM_MAXL][WM_NSUB_MAX + 1];
+    // layer sizes and offsets, read before any store (the stores could alias
+    // the plan, which would otherwise be read again from memory in the loop)
+    __shared__ int lay_n[WM_MAXL];
+    __shared__ int64_t lay_off[WM_MAXL];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -656,6 +660,10 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
     const bool slopes = sums && w.kind == 0;
     const int rows_c = slopes ? min(PROJ_ROWS + 1, nn - r0) : rows;
     const int K = rows_c + nn;
+    if (threadIdx.x < L) {
+        lay_n[threadIdx.x] = P.layer[threadIdx.x].N;
+        lay_off[threadIdx.x] = P.layer[threadIdx.x].coff;
+    }
     for (int e = threadIdx.x; e < L * K; e += blockDim.x) {
         const int l = e / K, k = e - (e / K) * K;
         const int N = P.layer[l].N;
@@ -676,15 +684,13 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
             T v[PROJ_LB][4];
 #pragma unroll
             for (int k = 0; k < PROJ_LB; ++k) {
-                const int l = l0 + k;
-                if (l < L) {
-                    const int N = P.layer[l].N;
-                    const T* f = phi + P.layer[l].coff + static_cast<int64_t>(ri0[l][li]) * N + cj0[l][j];
-                    v[k][0] = f[0];
-                    v[k][1] = f[1];
-                    v[k][2] = f[N];
-                    v[k][3] = f[N + 1];
-                }
+                const int l = min(l0 + k, L - 1);   // past the last layer: a valid load, unused
+                const int N = lay_n[l];
+                const T* f = phi + lay_off[l] + static_cast<int64_t>(ri0[l][li]) * N + cj0[l][j];
+                v[k][0] = f[0];
+                v[k][1] = f[1];
+                v[k][2] = f[N];
+                v[k][3] = f[N + 1];
             }
 #pragma unroll
             for (int k = 0; k < PROJ_LB; ++k) {
@@ -944,7 +950,19 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
     T* Vs = reinterpret_cast<T*>(smem_raw);
     Acc* Tb = reinterpret_cast<Acc*>(smem_raw + ((static_cast<size_t>(NR) * nn * sizeof(T) + 15) & ~size_t(15)));
     const T* V = vptr<T>(J, in_vec, it.frame) + P.wfs[m].node_off + static_cast<int64_t>(alo) * nn;
-    for (int e = threadIdx.x; e < NR * nn; e += blockDim.x) Vs[e] = V[e];
+    {
+        // ADJ_PF loads in flight per thread: clamped addresses, predicated stores
+        constexpr int ADJ_PF = 8;
+        const int tot = NR * nn, bd0 = blockDim.x;
+        for (int e0 = threadIdx.x; e0 < tot; e0 += ADJ_PF * bd0) {
+            T v[ADJ_PF];
+#pragma unroll
+            for (int j = 0; j < ADJ_PF; ++j) v[j] = V[min(e0 + j * bd0, tot - 1)];
+#pragma unroll
+            for (int j = 0; j < ADJ_PF; ++j)
+                if (e0 + j * bd0 < tot) Vs[e0 + j * bd0] = v[j];
+        }
+    }
     // row taps of the band: first staged row, count, weights
     if (threadIdx.x < BR) {
         const int r = r0 + threadIdx.x, f = rt[2 * r], cnt = rt[2 * r + 1];
