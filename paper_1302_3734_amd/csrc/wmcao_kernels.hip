@@ -90,6 +90,24 @@ __device__ double sum_slots(const double* p, int n, double* red) {
     return block_sum(v, red);
 }
 
+// Three slot sums in one pass (same order as sum_slots for each; loads at
+// clamped addresses so that all three are in flight at once).  red: 68 doubles.
+__device__ void sum_slots3(const double* a, int na, const double* b, int nb, const double* c,
+                           int nc, double* out, double* red) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int n = max(na, max(nb, nc));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double x = a[min(i, na - 1)], y = b[min(i, nb - 1)], z = c[min(i, nc - 1)];
+        if (i < na) v[0] += x;
+        if (i < nb) v[1] += y;
+        if (i < nc) v[2] += z;
+    }
+    block_sum4(v, red);
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+}
+
 // Scale index k (1 = finest details, levels = coarsest details and low-pass)
 // of the Mallat coefficient (x, y) of an N x N layer.
 __device__ __forceinline__ int level_of(int x, int y, int N, int levels) {
@@ -1383,12 +1401,16 @@ k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
 template <class T>
 __global__ void __launch_bounds__(256)
 k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
-    __shared__ double red[17];
+    __shared__ double red[68];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
-    const double pq = sum_slots(part_ptr(J, it.frame, PT_PQ) + P.pq_base, P.L, red);
-    const double rho = sum_slots(part_ptr(J, it.frame, PT_RZ0 + (iter & 1)), P.n_vec_slots, red);
+    // <p, Ap>, rho_i and (first iteration) <r0, r0>, reduced together
+    double sums[3];
+    sum_slots3(part_ptr(J, it.frame, PT_PQ) + P.pq_base, P.L,
+               part_ptr(J, it.frame, PT_RZ0 + (iter & 1)), P.n_vec_slots,
+               part_ptr(J, it.frame, PT_RR0), iter == 0 ? P.n_vec_slots : 1, sums, red);
+    const double pq = sums[0], rho = sums[1];
     int st = J.status[it.frame];
     double a = 0.0;
     if (st == WMCAO_FRAME_OK) {
@@ -1400,7 +1422,7 @@ k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
             a = rho / pq;
     }
     if (iter == 0) {
-        const double rr0 = sum_slots(part_ptr(J, it.frame, PT_RR0), P.n_vec_slots, red);
+        const double rr0 = sums[2];
         if (it.b == 0 && threadIdx.x == 0) {
             J.alpha[2 * it.frame + 1] = sqrt(rr0);
             if (J.resid) J.resid[static_cast<int64_t>(it.frame) * J.resid_ld] = sqrt(rr0);
@@ -1456,7 +1478,7 @@ k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
 template <class T>
 __global__ void __launch_bounds__(256)
 k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
-    __shared__ double red[17];
+    __shared__ double red[68];
     const Item it = items[blockIdx.x];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -1467,13 +1489,15 @@ k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
         return;
     }
     const double a = J.alpha[2 * it.frame];
-    const double rho0 = sum_slots(part_ptr(J, it.frame, PT_RZ0 + (iter & 1)), P.n_vec_slots, red);
-    const double rho1 =
-        sum_slots(part_ptr(J, it.frame, PT_RZ0 + ((iter + 1) & 1)), P.n_vec_slots, red);
+    // rho_i, rho_{i+1} and <r, r>, reduced together
+    double sums[3];
+    sum_slots3(part_ptr(J, it.frame, PT_RZ0 + (iter & 1)), P.n_vec_slots,
+               part_ptr(J, it.frame, PT_RZ0 + ((iter + 1) & 1)), P.n_vec_slots,
+               part_ptr(J, it.frame, PT_RR0 + ((iter + 1) & 1)), P.n_vec_slots, sums, red);
+    const double rho0 = sums[0], rho1 = sums[1];
     const double beta = rho1 / rho0;
     if (it.b == 0) {
-        const double rr =
-            sum_slots(part_ptr(J, it.frame, PT_RR0 + ((iter + 1) & 1)), P.n_vec_slots, red);
+        const double rr = sums[2];
         if (threadIdx.x == 0) {
             J.alpha[2 * it.frame + 1] = sqrt(rr);
             if (J.resid) J.resid[static_cast<int64_t>(it.frame) * J.resid_ld + iter + 1] = sqrt(rr);
