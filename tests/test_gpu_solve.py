@@ -252,3 +252,68 @@ def test_c4_mixed_sizes_one_launch():
         torch.cuda.synchronize()
     for p in plans:
         p.close()
+
+
+def test_c2_batch32_bench_configuration_sampled_frames():
+    """The benchmark's launch: E-ELT (C2) FP32, 32 frames of their own seeded
+    noise in one eager solve with the default tiles, 10 warm iterations.
+    Sampled frames are checked against the FP64 oracle one by one (1e-5, or
+    twice the oracle's FP32 rounding spread) and are bitwise equal to their
+    solo solves."""
+    require_gpu()
+    import torch
+    from paper_1302_3734_amd import Plan
+    cfg = WL.config_c2()
+    B = 32
+    S, sig, s0, _ = setup(cfg, frame=0, seed_frame=0)
+    J = S.jacobi_separable()
+    x0, _ = O.pcg(S.apply_A, S.rhs(s0), 10, jacobi=J)      # a shared warm start
+    x0_in = to_np(to_dev(x0, torch.float32)).ravel()
+    slopes = np.stack([slopes_for(S, cfg, sig, 1 + f, seed_frame=0) for f in range(B)])
+    s32 = to_dev(slopes, torch.float32)
+    plan = Plan(cfg, sig, dtype="f32", max_batch=B)
+    X = to_dev(np.repeat(x0_in[None, :], B, axis=0), torch.float32)
+    say("[c2-b32] batched solve")
+    plan.solve(s32, X, n_iter=10, warm_start=True)
+    Xn = to_np(X).reshape(B, -1)
+    for f in (0, 15, B - 1):
+        s_in = to_np(s32[f]).ravel()
+        b = S.rhs(s_in)
+        x_ref, _ = O.pcg(S.apply_A, b, 10, x0=x0_in, jacobi=J)
+        e = _errors(S, Xn[f], x_ref, b)
+        tol = fp32_tol(S, b, 10, J, x0_in)
+        say(f"[c2-b32] frame {f}: e_x {e[0]:.2e} e_phi {e[1]:.2e} e_res {e[2]:.2e} "
+            f"tol {tol[0]:.1e} {tol[1]:.1e} {tol[2]:.1e}")
+        assert all(ei < ti for ei, ti in zip(e, tol)), (f, e, tol)
+    xs = to_dev(x0_in[None, :], torch.float32)
+    plan.solve(s32[15:16].contiguous(), xs, n_iter=10, warm_start=True)
+    assert np.array_equal(to_np(xs).ravel(), Xn[15])
+    plan.close()
+
+
+def test_edge_batches_and_zero_iterations():
+    """Batch 0 and batch > max_batch are rejected through the C ABI; zero
+    iterations leave a warm start untouched and give 0 from a cold start."""
+    require_gpu()
+    import ctypes as C
+    import torch
+    from paper_1302_3734_amd import Plan, _abi
+    cfg = WL.config_c1()
+    S, sig, s, _ = setup(cfg)
+    plan = Plan(cfg, sig, dtype="f32", max_batch=2)
+    sl = to_dev(np.stack([s, s]), torch.float32)
+    x = torch.full((2, plan.n), 0.5, dtype=torch.float32, device="cuda")
+    lib = _abi.lib()
+    for bad in (0, 3, -1):
+        rc = lib.wmcao_solve(plan.handle, C.c_void_p(sl.data_ptr()), C.c_void_p(x.data_ptr()),
+                             bad, 10, 1, None, None, None)
+        assert rc == -1, (bad, rc)                       # WMCAO_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert torch.all(x == 0.5)
+    plan.solve(sl, x, n_iter=0, warm_start=True)
+    torch.cuda.synchronize()
+    assert torch.all(x == 0.5)
+    plan.solve(sl, x, n_iter=0, warm_start=False)
+    torch.cuda.synchronize()
+    assert torch.all(x == 0.0)
+    plan.close()
