@@ -178,7 +178,7 @@ void launch_cast_from_double(const double* in, T* out, int64_t n, hipStream_t s)
 
 constexpr int FUSE_LDS = 32 * 1024;   // largest low-pass block a synthesis tile rebuilds
 constexpr int TILE_NT = 256;          // threads of a wavelet tile block
-constexpr int VEC_CHUNK = 4096;   // elements per block of the vector kernels
+constexpr int VEC_CHUNK = 2048;   // elements per block of the vector kernels
 constexpr int PROJ_ROWS = 8;      // sensor node rows per block of the projection
 constexpr int SP_K = 2 * WM_MAXCELL;   // doubles per slope-sum record
 constexpr int ADJ_BAND = 32;      // footprint rows per adjoint work item (at most)
