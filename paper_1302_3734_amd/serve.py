@@ -127,6 +127,10 @@ class Server:
         self.hbm_budget = int(hbm_budget)
         self.reserved = 0
         self.cv = threading.Condition()
+        # a launch may capture a new HIP graph on its lane; events recorded on
+        # that lane must not be queried meanwhile, so launching and polling
+        # take turns
+        self.hip_lock = threading.Lock()
         self.inflight = [collections.deque() for _ in self.lanes]   # per lane, in launch order
         self.turn = [0] * n_lanes                                   # next configuration (no packing)
         self.running = True
@@ -244,8 +248,9 @@ class Server:
                 plans.append(self.plans[cfg])
                 slopes.append(Sb[:k])
                 coeffs.append(Xb[:k])
-            solve_multi(plans, slopes, coeffs, n_iter=self.n_iter, warm_start=True,
-                        graph=self.graphs)
+            with self.hip_lock:
+                solve_multi(plans, slopes, coeffs, n_iter=self.n_iter, warm_start=True,
+                            graph=self.graphs)
             results = []
             for cfg, st, frs, k in spans:
                 Xb = self.stage[cfg][1]
@@ -270,7 +275,8 @@ class Server:
                         return
                     self.cv.wait(timeout=0.05)
                 heads = [(lane, q[0]) for lane, q in enumerate(self.inflight) if q]
-            done = [(lane, item) for lane, item in heads if item[0].query()]
+            with self.hip_lock:
+                done = [(lane, item) for lane, item in heads if item[0].query()]
             if not done:
                 time.sleep(2e-5)
                 continue

@@ -12,7 +12,10 @@ from tests.gpu_common import require_gpu, say, setup, slopes_for
 pytestmark = pytest.mark.gpu
 
 
-def test_served_mix_equals_alone():
+@pytest.mark.parametrize("lanes", [2, 1], ids=["lane-per-config", "one-packed-lane"])
+def test_served_mix_equals_alone(lanes):
+    """lanes=1 packs both configurations into one lane, so launches capture
+    new multi-plan graphs while frames are in flight."""
     require_gpu()
     import torch
     from paper_1302_3734_amd import Plan
@@ -26,7 +29,7 @@ def test_served_mix_equals_alone():
         pools[cfg["name"]] = [torch.tensor(slopes_for(S, cfg, sig, f), dtype=torch.float32,
                                            device="cuda") for f in range(6)]
     streams = {"a": "C1", "b": "C1", "c": "C4-8m-lgs"}
-    srv = Server(cfgs, streams, dtype="f32", n_iter=6, hip_streams=2, keep_inputs=True)
+    srv = Server(cfgs, streams, dtype="f32", n_iter=6, hip_streams=lanes, keep_inputs=True)
     futs = []
     say("[serve] submitting")
     for f in range(6):
