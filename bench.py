@@ -186,15 +186,22 @@ def measured_traffic(kernel):
     return round(val) if math.isfinite(val) else None
 
 
-def _synthetic_slopes(cfg, plan, frames):
+def _synthetic_slopes(cfg, plan, frames, seeds=None, sig=None):
     """Seeded screens through the library's forward model plus noise at the
-    configuration's level: [len(frames), n_slopes] FP64 on the device."""
+    configuration's level: [len(frames), n_slopes] FP64 on the device.  With
+    seeds, frame frames[i] is advanced by frozen flow from frame seeds[i];
+    otherwise every frame has screens of its own.  sig: noise levels (default:
+    from the first frame's clean slopes)."""
     import torch
     out = []
     so = plan.slope_offsets
-    sig = None
-    for t in frames:
-        v = np.concatenate([a.ravel() for a in WL.layer_screens(cfg, t)])
+    sv = None
+    if sig is not None:
+        sv = torch.tensor(np.concatenate([np.full(so[m + 1] - so[m], sig[m])
+                                          for m in range(len(sig))]), device="cuda")
+    for i, t in enumerate(frames):
+        sd = None if seeds is None else seeds[i]
+        v = np.concatenate([a.ravel() for a in WL.layer_screens(cfg, t, seed_frame=sd)])
         clean = plan.forward_layers(torch.tensor(v, device="cuda")[None])[0]
         if sig is None:
             sig = WL.sigmas_from_clean(cfg, clean.cpu().numpy(), so)
@@ -279,12 +286,12 @@ def mixed_batch(n_frames=64, n_iter=10, reps=10):
             "frames_per_s": round(n_frames / ms * 1e3, 1), "mode": "one packed launch, hipGraph replay"}
 
 
-def onaxis_residual(cfg, layers_vec, truth_vec):
-    """On-axis wavefront residual (rad RMS at 500 nm, piston removed) over the
-    pupil nodes of the 84x84 grid, and its Marechal Strehl in K band (2.2 um).
-    At zero field angle the 0.5 m nodes coincide with 0.5 m layer pixels, so
-    the on-axis wavefront is a plain sum of layer samples."""
-    n_sub, D, eps = 84, cfg["diameter"], cfg["obstruction"]
+def onaxis_wavefront(cfg, layers_vec, n_sub=84):
+    """On-axis wavefront at the pupil nodes of an 84x84 grid (rad at 500 nm)
+    and the mask of nodes inside the annular pupil.  At zero field angle the
+    0.5 m nodes coincide with 0.5 m layer pixels of every layer, so the
+    wavefront is a plain sum of layer samples."""
+    D, eps = cfg["diameter"], cfg["obstruction"]
     d = D / n_sub
     c = (np.arange(n_sub) + 0.5 - n_sub / 2.0) * d
     r2 = c[:, None] ** 2 + c[None, :] ** 2
@@ -293,18 +300,87 @@ def onaxis_residual(cfg, layers_vec, truth_vec):
     for di in (0, 1):
         for dj in (0, 1):
             nodes[di:di + n_sub, dj:dj + n_sub] |= act
-    diff = np.asarray(layers_vec, dtype=np.float64) - np.asarray(truth_vec, dtype=np.float64)
+    vec = np.asarray(layers_vec, dtype=np.float64)
     w = np.zeros((n_sub + 1, n_sub + 1))
     off = 0
     for L in cfg["layers"]:
         N = L["n"]
-        lay = diff[off:off + N * N].reshape(N, N)
+        lay = vec[off:off + N * N].reshape(N, N)
         o = N // 2 - n_sub // 2
         w += lay[o:o + n_sub + 1, o:o + n_sub + 1]
         off += N * N
-    v = w[nodes] - w[nodes].mean()
+    return w, nodes
+
+
+def onaxis_residual(cfg, layers_vec, truth_vec, truth_cfg=None):
+    """On-axis wavefront residual (rad RMS at 500 nm, piston removed) over the
+    pupil nodes, and its Marechal Strehl in K band (2.2 um).  The truth may
+    live on another layer set (truth_cfg)."""
+    w, nodes = onaxis_wavefront(cfg, layers_vec)
+    wt, _ = onaxis_wavefront(truth_cfg or cfg, truth_vec)
+    v = (w - wt)[nodes]
+    v = v - v.mean()
     rms = float(np.sqrt(np.mean(v ** 2)))
     return rms, float(np.exp(-(rms * 0.5 / 2.2) ** 2))
+
+
+def iteration_sweep(frames=(1, 11, 21, 31), iters=(1, 2, 3, 4, 6, 8, 10, 15, 20)):
+    """Speed/quality trade-off of the paper's three solvers on the same E-ELT
+    frames (Sec. 5.2-5.3; a synthetic stand-in for its iteration study): nine
+    layers with Jacobi PCG, nine layers with plain CG, three layers at the
+    mirror altitudes with Jacobi PCG.  Each solves in FP64 for several
+    iteration counts, from zero and warm-started from the same variant's
+    30-iteration reconstruction of the previous frame (the paper's warm
+    restart); the on-axis residual and K-band Strehl against the nine truth
+    screens are averaged over the frames.  Time: one frame, hipGraph replay,
+    at the variant's own iteration count."""
+    import torch
+    from paper_1302_3734_amd import Plan
+    base = WL.config_c2()
+    fwd = Plan(base, [1.0] * len(base["wfs"]), dtype="f64", max_batch=1)
+    # one frozen-flow sequence per frame: frame t follows frame t - 1 of the
+    # sequence seeded at t - 1
+    seeds = [t - 1 for t in frames]
+    sl, sig = _synthetic_slopes(base, fwd, frames, seeds)
+    prev, _ = _synthetic_slopes(base, fwd, seeds, seeds, sig)
+    fwd.close()
+    truths = [np.concatenate([a.ravel() for a in WL.layer_screens(base, t, seed_frame=t - 1)])
+              for t in frames]
+    out = {"frames": list(frames), "iterations": list(iters)}
+    for name in ("C2", "C2-cg9", "C2-dm3"):
+        cfg = WL.config_by_name(name)
+        plan = Plan(cfg, sig, dtype="f64", max_batch=len(frames), tile=16,
+                    precond=bool(cfg.get("precond", True)))
+        x_prev = torch.zeros(len(frames), plan.n, dtype=torch.float64, device="cuda")
+        plan.solve(prev, x_prev, n_iter=30)
+        res = {"cold": ([], []), "warm": ([], [])}
+        for k in iters:
+            for mode in ("cold", "warm"):
+                x = x_prev.clone() if mode == "warm" else torch.zeros_like(x_prev)
+                plan.solve(sl, x, n_iter=k, warm_start=mode == "warm")
+                lay = plan.coeffs_to_layers(x).cpu().numpy().reshape(len(frames), -1)
+                r = [onaxis_residual(cfg, lay[i], truths[i], base) for i in range(len(frames))]
+                res[mode][0].append(round(float(np.mean([a for a, _ in r])), 5))
+                res[mode][1].append(round(float(np.mean([b for _, b in r])), 5))
+        its = int(cfg["n_iter"])
+        x1 = torch.zeros(1, plan.n, dtype=torch.float64, device="cuda")
+        s1 = sl[:1].contiguous()
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            for _ in range(3):
+                plan.solve(s1, x1, n_iter=its, graph=True, stream=st)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            for _ in range(20):
+                plan.solve(s1, x1, n_iter=its, graph=True, stream=st)
+            b.record(st)
+        st.synchronize()
+        out[name] = {"layers": len(cfg["layers"]), "preconditioner": bool(cfg.get("precond", True)),
+                     "paper_iterations": its, "ms_per_frame_fp64": round(a.elapsed_time(b) / 20, 4),
+                     "onaxis_rms_rad_cold": res["cold"][0], "strehl_K_cold": res["cold"][1],
+                     "onaxis_rms_rad_warm": res["warm"][0], "strehl_K_warm": res["warm"][1]}
+        plan.close()
+    return out
 
 
 def main():
@@ -528,6 +604,15 @@ def main():
         print(f"[bench] c3 {result['c3_batched']}", flush=True)
         result["c4_mixed"] = mixed_batch()
         print(f"[bench] c4 {result['c4_mixed']}", flush=True)
+
+    if not args.no_extra:
+        result["iteration_sweep"] = iteration_sweep()
+        sw = result["iteration_sweep"]
+        for name in ("C2", "C2-cg9", "C2-dm3"):
+            v = sw[name]
+            print(f"[bench] sweep {name}: {v['layers']} layers, {v['paper_iterations']} its "
+                  f"{v['ms_per_frame_fp64']:.3f} ms/frame; Strehl_K warm by its {v['strehl_K_warm']}; "
+                  f"cold {v['strehl_K_cold']}", flush=True)
 
     if args.serve_seconds > 0:
         result["served"] = served_stream(args.serve_seconds, args.serve_rate, IT)
