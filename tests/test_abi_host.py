@@ -60,6 +60,20 @@ def test_invalid_plans_rejected_on_host(kw, code):
     assert L.wmcao_last_error()
 
 
+def test_layer_and_sensor_limits_rejected_on_host():
+    """17 layers or 33 sensors exceed the plan's tables (16 and 32)."""
+    L = _abi.lib()
+    pupil, _, Ws, wav, levels, opts = _args()
+    h = C.c_void_p()
+    Ls17 = (_abi.Layer * 17)(*[_abi.Layer(500.0 * k, 1.0 / 17, 0.5, 64) for k in range(17)])
+    assert L.wmcao_plan(C.byref(pupil), Ls17, 17, Ws, 1, wav, levels, C.byref(opts), C.byref(h)) == -1
+    assert not h.value
+    pupil, Ls, _, wav, levels, opts = _args()
+    Ws33 = (_abi.Wfs * 33)(*[_abi.Wfs(0, 0.0, 0.0, 90e3, 16, 0, -1, -1, 0.1, None, 0) for _ in range(33)])
+    assert L.wmcao_plan(C.byref(pupil), Ls, 1, Ws33, 33, wav, levels, C.byref(opts), C.byref(h)) == -1
+    assert not h.value
+
+
 def test_null_arguments_rejected():
     L = _abi.lib()
     assert L.wmcao_solve(None, None, None, 1, 1, 0, None, None, None) == -1

@@ -10,7 +10,7 @@ import pytest
 import oracle as O
 import workloads as WL
 from tests.gpu_common import maxrel, rel, require_gpu, say, setup, to_dev, to_np
-from tests.tiny import tiny_config, tiny_ragged_config
+from tests.tiny import tiny_config, tiny_max_config, tiny_ragged_config
 
 pytestmark = pytest.mark.gpu
 
@@ -28,6 +28,8 @@ CASES = [
     ("tiny-f32", tiny_config, "f32", {}),
     ("ragged-tiled-f64", tiny_ragged_config, "f64", {"tile": 16, "lds_budget": 1024}),
     ("ragged-tiled-f32", tiny_ragged_config, "f32", {"tile": 16, "lds_budget": 512}),
+    ("max-f64", tiny_max_config, "f64", {}),
+    ("max-f32", tiny_max_config, "f32", {"tile": 16}),
     ("c1-f64", WL.config_c1, "f64", {}),
     ("c1-tiled-f64", WL.config_c1, "f64", {"tile": 32, "lds_budget": 2048}),
     ("c2-f64", WL.config_c2, "f64", {}),

@@ -32,3 +32,22 @@ def tiny_ragged_config():
     cfg["cfg_id"] = 901
     cfg["layers"] = _layers([0.0, 6e3], [0.7, 0.3], [40, 48])
     return _check(cfg)
+
+
+def tiny_max_config():
+    """The library's maximum sizes on a small pupil: 16 layers of 32x32 at
+    0..15 km and 32 sensors (24 LGS, 7 high-order NGS, one 2x2 low-order
+    NGS) of 8x8 subapertures within half an arcminute."""
+    cfg = tiny_config(tt=False)
+    cfg = copy.deepcopy(cfg)
+    cfg["name"] = "tiny-max"
+    cfg["cfg_id"] = 902
+    alts = [1e3 * k for k in range(16)]
+    w = [2.0 ** (-k / 4.0) for k in range(16)]
+    tot = sum(w)
+    cfg["layers"] = _layers(alts, [x / tot for x in w], [32] * 16)
+    wfs = [_wfs(True, t, 8) for t in ring_angles(24, 0.5)]
+    wfs += [_wfs(False, t, 8) for t in ring_angles(7, 0.3)]
+    wfs.append(_wfs(False, (0.1 * ARCMIN, -0.2 * ARCMIN), 8, tt_aggregate=2))
+    cfg["wfs"] = wfs
+    return _check(cfg)
