@@ -217,6 +217,28 @@ __device__ void ana_pass(Acc* A, int ld, int M, int along_y, const Acc* hf, cons
     __syncthreads();
 }
 
+// Item of this block.  A launch deals its work-groups to the 8 XCDs in turn
+// (block b to XCD b mod 8), and every XCD has its own L2.  The lists hold a
+// frame's items together, so XCD x takes the x-th contiguous share of the
+// list: blocks that read the same frame data (layer pixels, node rows, tile
+// halos, footprint images) then meet in one L2 instead of fetching it eight
+// times.  The map is a bijection on [0, gridDim.x); results do not depend on
+// it, because every partial sum is stored by item, not by block.
+__device__ __forceinline__ int xcd_item() {
+    const int b = blockIdx.x, n = gridDim.x;
+    const int x = b & 7, q = b >> 3, base = n >> 3, rem = n & 7;
+    return x * base + min(x, rem) + q;
+}
+
+// Item of a block of the streaming vector sweeps (no data shared between
+// blocks of one frame).  Launches of at least VEC_PLAIN_MIN blocks keep the
+// plain order, which measured faster at batch 32 (5,824 blocks); smaller ones
+// take the XCD shares, faster at batch 1 (182 blocks).
+constexpr int VEC_PLAIN_MIN = 1024;
+__device__ __forceinline__ int vec_item() {
+    return static_cast<int>(gridDim.x) >= VEC_PLAIN_MIN ? static_cast<int>(blockIdx.x) : xcd_item();
+}
+
 // Bilinear sample position of node i on one axis: lower pixel i0 (clamped to
 // [0, N-2]) and the weight t of pixel i0 + 1 (Sec. 2.1).  The forward and the
 // adjoint projection both evaluate it, so they are exact transposes.
@@ -307,7 +329,7 @@ __device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, i
 template <class T>
 __global__ void __launch_bounds__(1024)
 k_idwt_coarse(const JobArgs args, const Item* __restrict__ items, int in_vec, int out_vec) {
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const LayerInfo& Ly = P.layer[it.a];
@@ -345,7 +367,7 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
     constexpr int CW = TS / 2 + 2;
     __shared__ Acc sLL[CW][CW + 1], sLH[CW][CW + 1], sHL[CW][CW + 1], sHH[CW][CW + 1];
     __shared__ Acc sAL[TS][CW + 1], sAH[TS][CW + 1];
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const LayerInfo& Ly = P.layer[it.a];
@@ -450,7 +472,7 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     __shared__ Acc sA[PW][PW + 1];
     __shared__ Acc sL[PW][HT + 1], sH[PW][HT + 1];
     __shared__ double red[17];
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const LayerInfo& Ly = P.layer[it.a];
@@ -591,7 +613,7 @@ __global__ void __launch_bounds__(1024)
 k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int in_vec,
               int out_vec, int epi, int aux_vec) {
     __shared__ double red[17];
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const LayerInfo& Ly = P.layer[it.a];
@@ -667,7 +689,7 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
     // the plan, which would otherwise be read again from memory in the loop)
     __shared__ int lay_n[WM_MAXL];
     __shared__ int64_t lay_off[WM_MAXL];
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const int m = it.a;
@@ -794,7 +816,7 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     __shared__ double swx[(PROJ_ROWS + 1) * WM_NSUB_MAX], swy[(PROJ_ROWS + 1) * WM_NSUB_MAX];
     __shared__ double cval[2 * WM_MAXCELL], cwx[WM_MAXCELL], cwy[WM_MAXCELL];
     __shared__ double srec[((WM_NSUB_MAX + 1 + PROJ_ROWS - 1) / PROJ_ROWS) * SP_K];
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const int m = it.a;
@@ -947,7 +969,7 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
     __shared__ double wrow[ADJ_BAND][ADJ_TAPS];
     __shared__ int frow[ADJ_BAND], crow[ADJ_BAND];
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const int m = it.a, l = it.b;
@@ -1062,7 +1084,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
     __shared__ double cellx[WM_MAXCELL], celly[WM_MAXCELL], cwx[WM_MAXCELL], cwy[WM_MAXCELL];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Acc* U = reinterpret_cast<Acc*>(smem_raw);
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const int m = it.a;
@@ -1346,7 +1368,7 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
     __shared__ double red[17];
-    const Item it = items[blockIdx.x];
+    const Item it = items[vec_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     T* x = vptr<T>(J, V_X, it.frame);
@@ -1402,7 +1424,7 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
     __shared__ double red[68];
-    const Item it = items[blockIdx.x];
+    const Item it = items[vec_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     // <p, Ap>, rho_i and (first iteration) <r0, r0>, reduced together
@@ -1479,7 +1501,7 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
     __shared__ double red[68];
-    const Item it = items[blockIdx.x];
+    const Item it = items[vec_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const int st = J.status[it.frame];
@@ -1543,7 +1565,7 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_replace_r(const JobArgs args, const Item* __restrict__ items, int iter) {
     __shared__ double red[17];
-    const Item it = items[blockIdx.x];
+    const Item it = items[vec_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     if (J.status[it.frame] != WMCAO_FRAME_OK) return;
