@@ -152,7 +152,8 @@ void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int
 template <class T>
 void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, hipStream_t s);
 template <class T>
-void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, hipStream_t s);
+void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, int lds_bytes,
+                    hipStream_t s);
 template <class T>
 void launch_adjoint(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
                     int lds_bytes, hipStream_t s);
@@ -180,8 +181,15 @@ constexpr int FUSE_LDS = 32 * 1024;   // largest low-pass block a synthesis tile
 constexpr int TILE_NT = 256;          // threads of a wavelet tile block
 constexpr int VEC_CHUNK = 2048;   // elements per block of the vector kernels
 constexpr int PROJ_ROWS = 8;      // sensor node rows per block of the projection
+
+// Dynamic LDS of k_weights for a sensor of nn nodes and ns subapertures per
+// side: the band's node rows with one halo row on each side and the weighted
+// x and y slopes of the subaperture rows next to the band (FP64).
+constexpr int weights_lds_bytes(int nn, int ns) {
+    return ((PROJ_ROWS + 2) * nn + 2 * (PROJ_ROWS + 1) * ns) * 8;
+}
 constexpr int SP_K = 2 * WM_MAXCELL;   // doubles per slope-sum record
 constexpr int ADJ_BAND = 32;      // footprint rows per adjoint work item (at most)
-constexpr int ADJ_LDS = 48 * 1024;   // LDS of the adjoint's row-pass buffer (at most)
+constexpr int ADJ_LDS = 32 * 1024;   // LDS of the adjoint's row-pass buffer (at most)
 
 }  // namespace wm

@@ -812,8 +812,9 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
 template <class T>
 __global__ void __launch_bounds__(256)
 k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
-    __shared__ double su[(PROJ_ROWS + 2) * (WM_NSUB_MAX + 1)];
-    __shared__ double swx[(PROJ_ROWS + 1) * WM_NSUB_MAX], swy[(PROJ_ROWS + 1) * WM_NSUB_MAX];
+    // su, swx, swy: dynamic LDS of weights_lds_bytes(nn, ns) for this sensor
+    // (the launch gives the largest over its sensors)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double cval[2 * WM_MAXCELL], cwx[WM_MAXCELL], cwy[WM_MAXCELL];
     __shared__ double srec[((WM_NSUB_MAX + 1 + PROJ_ROWS - 1) / PROJ_ROWS) * SP_K];
     const Item it = items[xcd_item()];
@@ -824,6 +825,9 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     const int nn = w.nn, ns = w.n_sub;
     const int r0 = it.b * PROJ_ROWS;
     const int rows = min(PROJ_ROWS, nn - r0);
+    double* su = reinterpret_cast<double*>(smem_raw);
+    double* swx = su + (PROJ_ROWS + 2) * nn;
+    double* swy = swx + (PROJ_ROWS + 1) * ns;
     const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
     T* vout = vptr<T>(J, out_vec, it.frame) + w.node_off;
     if (w.kind == 1) {
@@ -1811,9 +1815,10 @@ void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int 
 }
 
 template <class T>
-void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, hipStream_t s) {
+void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, int lds_bytes,
+                    hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_weights<T>, dim3(n), dim3(256), 0, s, a, items, out_vec);
+    hipLaunchKernelGGL(k_weights<T>, dim3(n), dim3(256), lds_bytes, s, a, items, out_vec);
 }
 
 template <class T>
@@ -1912,7 +1917,7 @@ void configure_kernels() {
     template void launch_fdwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, hipStream_t); \
     template void launch_sensor<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
     template void launch_project<T>(const JobArgs&, const Item*, int, int, int, hipStream_t);  \
-    template void launch_weights<T>(const JobArgs&, const Item*, int, int, hipStream_t);       \
+    template void launch_weights<T>(const JobArgs&, const Item*, int, int, int, hipStream_t);       \
     template void launch_adjoint<T>(const JobArgs&, const Item*, int, int, int, int, hipStream_t); \
     template void launch_init<T>(const JobArgs&, const Item*, int, int, hipStream_t);          \
     template void launch_update_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \

@@ -67,6 +67,7 @@ struct Sched {
     int lds_idwt = 0;      // dynamic LDS of the whole-band synthesis
     int lds_fdwt = 0;      // dynamic LDS of the whole-band analysis (+ gather tables)
     int lds_sensor = 0;
+    int lds_weights = 0;   // dynamic LDS of k_weights
     int tile = 32;
     // algorithmic bytes one launch of each stage moves (all frames of the job)
     double b_idwt_coarse = 0, b_idwt_tile[WM_MAXLEV + 1] = {};
@@ -257,7 +258,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj;
     int lds_lvl[WM_MAXLEV + 1] = {};
     std::vector<Item> tiled[WM_MAXLEV + 1];
-    int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0, lds_a = 0;
+    int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0, lds_a = 0, lds_w = 0;
     for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
         const wmcao_plan_s* P = jobs[jp].plan;
         for (int f = 0; f < jobs[jp].count; ++f) {
@@ -299,6 +300,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                 for (int b = 0; b < nb; ++b) proj.push_back(Item{jp, f, m, b, 0, 0, 0, 0});
                 const int nn = P->host.wfs[m].nn;
                 lds_s = std::max(lds_s, static_cast<int>(nn * nn * sizeof(double)));
+                lds_w = std::max(lds_w, weights_lds_bytes(nn, P->host.wfs[m].n_sub));
             }
             const int nch = static_cast<int>((P->n + VEC_CHUNK - 1) / VEC_CHUNK);
             for (int c = 0; c < nch; ++c) vec.push_back(Item{jp, f, 0, c, c, 0, 0, 0});
@@ -382,6 +384,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     S->lds_idwt = lds_i;
     S->lds_fdwt = lds_f;
     S->lds_sensor = lds_s;
+    S->lds_weights = lds_w;
     S->tile = tile;
     return WMCAO_OK;
 }
@@ -477,7 +480,8 @@ template <class T>
 void run_apply(const JobArgs& a, const Sched& S, int x_vec, int y_vec, hipStream_t s) {
     run_idwt<T>(a, S, x_vec, V_PHI, s);
     timed(WMCAO_K_PROJECT, S.b_project, s, [&] { launch_project<T>(a, S.proj, S.n_proj, V_PHI, 1, s); });
-    timed(WMCAO_K_SENSOR, S.b_sensor[0], s, [&] { launch_weights<T>(a, S.proj, S.n_proj, V_NODE, s); });
+    timed(WMCAO_K_SENSOR, S.b_sensor[0], s,
+          [&] { launch_weights<T>(a, S.proj, S.n_proj, V_NODE, S.lds_weights, s); });
     timed(WMCAO_K_ADJOINT, S.b_adjoint, s, [&] {
         launch_adjoint<T>(a, S.adj, S.n_adj, V_NODE, V_FP, S.lds_adj, s);
     });
