@@ -156,7 +156,7 @@ void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, int
                     hipStream_t s);
 template <class T>
 void launch_adjoint(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
-                    int lds_bytes, hipStream_t s);
+                    int lds_bytes, int taps, hipStream_t s);
 template <class T>
 void launch_sensor(const JobArgs& a, const Item* items, int n, int mode, int in_vec, int out_vec,
                    int lds_bytes, hipStream_t s);

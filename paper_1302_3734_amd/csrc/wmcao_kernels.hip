@@ -955,10 +955,10 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
 // pixel rows and every node column (LDS, FP64), and g[r][c] = sum_b wy(b, c)
 // T[r][b].  The weights are the forward bilinear ones read backwards: node a
 // feeds pixel i0_a with 1 - t_a and pixel i0_a + 1 with t_a.  A pixel row or
-// column is fed by at most ADJ_TAPS consecutive nodes on the fast path (node
-// spacing of at least half a pixel); denser node grids take the general loop.
-// LDS: the staged node rows (storage type) and T, sized by the plan.
-constexpr int ADJ_TAPS = 4;
+// column is fed by at most TAPS consecutive nodes on the fast path; TAPS (2
+// to 4) is the largest count the plans of the launch need (3 for node spacings
+// from 2/3 of a pixel up), and any row or column fed by more takes the general
+// loop.  LDS: the staged node rows (storage type) and T, sized by the plan.
 
 __device__ __forceinline__ Acc adj_weight(double pa, double pb, int i, int N, int g) {
     int i0;
@@ -967,10 +967,10 @@ __device__ __forceinline__ Acc adj_weight(double pa, double pb, int i, int N, in
     return i0 == g ? 1.0 - t : (i0 + 1 == g ? t : 0.0);
 }
 
-template <class T>
+template <class T, int TAPS>
 __global__ void __launch_bounds__(256)
 k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int out_vec) {
-    __shared__ double wrow[ADJ_BAND][ADJ_TAPS];
+    __shared__ double wrow[ADJ_BAND][TAPS];
     __shared__ int frow[ADJ_BAND], crow[ADJ_BAND];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Item it = items[xcd_item()];
@@ -1013,7 +1013,7 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
         frow[threadIdx.x] = cnt > 0 ? f - alo : 0;   // a row no node reaches reads row 0 with weight 0
         crow[threadIdx.x] = cnt;
 #pragma unroll
-        for (int q = 0; q < ADJ_TAPS; ++q)
+        for (int q = 0; q < TAPS; ++q)
             wrow[threadIdx.x][q] = q < cnt ? adj_weight(pa, pbx, f + q, N, x0 + r) : 0.0;
     }
     __syncthreads();
@@ -1027,9 +1027,9 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
                 for (int lr = g1; lr < BR; lr += G1) {
                     const int f = frow[lr], cnt = crow[lr];
                     Acc acc = 0;
-                    if (cnt <= ADJ_TAPS) {
+                    if (cnt <= TAPS) {
 #pragma unroll
-                        for (int q = 0; q < ADJ_TAPS; ++q)
+                        for (int q = 0; q < TAPS; ++q)
                             acc += wrow[lr][q] * static_cast<Acc>(Vs[min(f + q, NR - 1) * nn + b]);
                     } else {
                         const int r = r0 + lr;
@@ -1047,11 +1047,11 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
     if (g2 >= G2) return;
     for (int c = c0; c < Wf; c += cstep) {
         const int f = ct[2 * c], cnt = ct[2 * c + 1], gy = y0 + c;
-        if (cnt <= ADJ_TAPS) {
-            Acc w[ADJ_TAPS];
-            int ix[ADJ_TAPS];
+        if (cnt <= TAPS) {
+            Acc w[TAPS];
+            int ix[TAPS];
 #pragma unroll
-            for (int q = 0; q < ADJ_TAPS; ++q) {
+            for (int q = 0; q < TAPS; ++q) {
                 w[q] = q < cnt ? adj_weight(pa, pby, f + q, N, gy) : 0.0;
                 ix[q] = min(f + q, nn - 1);
             }
@@ -1059,7 +1059,7 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
                 const Acc* tr = Tb + lr * nn;
                 Acc acc = 0;
 #pragma unroll
-                for (int q = 0; q < ADJ_TAPS; ++q) acc += w[q] * tr[ix[q]];
+                for (int q = 0; q < TAPS; ++q) acc += w[q] * tr[ix[q]];
                 out[lr * Wf + c] = static_cast<T>(acc);
             }
         } else {
@@ -1823,9 +1823,14 @@ void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, int
 
 template <class T>
 void launch_adjoint(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
-                    int lds_bytes, hipStream_t s) {
+                    int lds_bytes, int taps, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_adjoint<T>, dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
+    if (taps <= 2)
+        hipLaunchKernelGGL((k_adjoint<T, 2>), dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
+    else if (taps == 3)
+        hipLaunchKernelGGL((k_adjoint<T, 3>), dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
+    else
+        hipLaunchKernelGGL((k_adjoint<T, 4>), dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
 }
 
 template <class T>
@@ -1902,8 +1907,12 @@ void configure_kernels() {
     allow_full_lds(&k_idwt_tile<double, 64>);
     allow_full_lds(&k_fdwt_coarse<float>);
     allow_full_lds(&k_fdwt_coarse<double>);
-    allow_full_lds(&k_adjoint<float>);
-    allow_full_lds(&k_adjoint<double>);
+    allow_full_lds(&k_adjoint<float, 2>);
+    allow_full_lds(&k_adjoint<float, 3>);
+    allow_full_lds(&k_adjoint<float, 4>);
+    allow_full_lds(&k_adjoint<double, 2>);
+    allow_full_lds(&k_adjoint<double, 3>);
+    allow_full_lds(&k_adjoint<double, 4>);
     allow_full_lds(&k_sensor<float, 8>);
     allow_full_lds(&k_sensor<float, 16>);
     allow_full_lds(&k_sensor<double, 8>);
@@ -1918,7 +1927,7 @@ void configure_kernels() {
     template void launch_sensor<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
     template void launch_project<T>(const JobArgs&, const Item*, int, int, int, hipStream_t);  \
     template void launch_weights<T>(const JobArgs&, const Item*, int, int, int, hipStream_t);       \
-    template void launch_adjoint<T>(const JobArgs&, const Item*, int, int, int, int, hipStream_t); \
+    template void launch_adjoint<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
     template void launch_init<T>(const JobArgs&, const Item*, int, int, hipStream_t);          \
     template void launch_update_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \
     template void launch_update_p<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \

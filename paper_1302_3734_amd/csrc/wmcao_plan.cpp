@@ -61,6 +61,7 @@ struct Sched {
     const Item* adj = nullptr;
     int n_adj = 0;
     int lds_adj = 0;
+    int adj_taps = 2;      // fast-path taps of the adjoint (largest over the plans)
     const Item* vec = nullptr;
     int n_vec = 0;
     int maxk0 = 0;
@@ -160,6 +161,7 @@ struct wmcao_plan_s {
     int64_t n_fpimg = 0;  // values of the adjoint footprint images of one frame
     int64_t n_spart = 0;  // doubles of the per-band slope sums of one frame
     int lds_adjoint = 0;  // row-pass buffer of the adjoint kernel
+    int adj_taps = 2;     // most nodes feeding one footprint row or column (2 to 4)
     std::vector<int64_t> layer_off, slope_off;
     std::map<int, std::unique_ptr<Sched>> sched;
     // captured graph of one wmcao_solve_graph argument set
@@ -258,7 +260,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj;
     int lds_lvl[WM_MAXLEV + 1] = {};
     std::vector<Item> tiled[WM_MAXLEV + 1];
-    int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0, lds_a = 0, lds_w = 0;
+    int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0, lds_a = 0, lds_w = 0, taps_a = 2;
     for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
         const wmcao_plan_s* P = jobs[jp].plan;
         for (int f = 0; f < jobs[jp].count; ++f) {
@@ -294,6 +296,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                     for (int b = 0; b < nb; ++b) adj.push_back(Item{jp, f, m, l, b, 0, 0, 0});
                 }
             lds_a = std::max(lds_a, P->lds_adjoint);
+            taps_a = std::max(taps_a, P->adj_taps);
             for (int m = 0; m < P->W; ++m) {
                 sensor.push_back(Item{jp, f, m, 0, 0, 0, 0, 0});
                 const int nb = ceil_div(P->host.wfs[m].nn, PROJ_ROWS);
@@ -375,6 +378,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     S->adj = base + offs[5];
     S->n_adj = static_cast<int>(adj.size());
     S->lds_adj = lds_a;
+    S->adj_taps = taps_a;
     for (int k = 0; k <= WM_MAXLEV; ++k) S->lds_idwt_lvl[k] = lds_lvl[k];
     for (int k = 1; k <= WM_MAXLEV; ++k) {
         S->tiled[k] = base + offs[5 + k];
@@ -483,7 +487,7 @@ void run_apply(const JobArgs& a, const Sched& S, int x_vec, int y_vec, hipStream
     timed(WMCAO_K_SENSOR, S.b_sensor[0], s,
           [&] { launch_weights<T>(a, S.proj, S.n_proj, V_NODE, S.lds_weights, s); });
     timed(WMCAO_K_ADJOINT, S.b_adjoint, s, [&] {
-        launch_adjoint<T>(a, S.adj, S.n_adj, V_NODE, V_FP, S.lds_adj, s);
+        launch_adjoint<T>(a, S.adj, S.n_adj, V_NODE, V_FP, S.lds_adj, S.adj_taps, s);
     });
     run_fdwt<T>(a, S, SRC_PT, V_FP, y_vec, EPI_APPLY, x_vec, s);
 }
@@ -494,7 +498,7 @@ void run_rhs(const JobArgs& a, const Sched& S, int slopes_vec, int b_vec, hipStr
         launch_sensor<T>(a, S.sensor, S.n_sensor, SM_RHS, slopes_vec, V_NODE, S.lds_sensor, s);
     });
     timed(WMCAO_K_ADJOINT, S.b_adjoint, s, [&] {
-        launch_adjoint<T>(a, S.adj, S.n_adj, V_NODE, V_FP, S.lds_adj, s);
+        launch_adjoint<T>(a, S.adj, S.n_adj, V_NODE, V_FP, S.lds_adj, S.adj_taps, s);
     });
     run_fdwt<T>(a, S, SRC_PT, V_FP, b_vec, EPI_NONE, b_vec, s);
 }
@@ -951,6 +955,8 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
                 for (int px = lo[axis]; px < lo[axis] + len[axis]; ++px) {
                     fprc.push_back(first[px] < 0 ? 0 : first[px]);
                     fprc.push_back(first[px] < 0 ? 0 : last[px] - first[px] + 1);
+                    // rows or columns fed by more than 4 nodes take the general loop
+                    p->adj_taps = std::min(4, std::max(p->adj_taps, fprc.back()));
                 }
             }
             H.fp_x0[m][l] = lo[0];
