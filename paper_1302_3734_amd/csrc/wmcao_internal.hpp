@@ -190,6 +190,7 @@ constexpr int weights_lds_bytes(int nn, int ns) {
 }
 constexpr int SP_K = 2 * WM_MAXCELL;   // doubles per slope-sum record
 constexpr int ADJ_BAND = 32;      // footprint rows per adjoint work item (at most)
+constexpr int ADJ_TAPS_MAX = 4;   // most fast-path taps of the adjoint
 constexpr int ADJ_LDS = 32 * 1024;   // LDS of the adjoint's row-pass buffer (at most)
 
 }  // namespace wm

@@ -286,29 +286,37 @@ __device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, i
                 gx[k] = r < PR ? gx[k] : -1;   // a row past the window is in no footprint
                 g[k] = 0.0;
             }
-            unsigned mm = mask;
+            // the mask is the same for every lane: keep it (and the sensor
+            // indices drawn from it) in scalar registers, so the footprint
+            // fields below are scalar loads
+            unsigned mm = __builtin_amdgcn_readfirstlane(mask);
             while (mm) {
-                const int ma = __ffs(static_cast<int>(mm)) - 1;
+                const int ma = __builtin_amdgcn_readfirstlane(__ffs(static_cast<int>(mm)) - 1);
                 mm &= mm - 1;
-                const int mb = mm ? __ffs(static_cast<int>(mm)) - 1 : ma;
+                const int mb = __builtin_amdgcn_readfirstlane(mm ? __ffs(static_cast<int>(mm)) - 1 : ma);
                 const bool hb = mm != 0;
                 if (hb) mm &= mm - 1;
                 const int yca = gy - P.fp_y0[ma][l], Wa = P.fp_w[ma][l];
                 const int ycb = gy - P.fp_y0[mb][l], Wb = P.fp_w[mb][l];
-                const bool ca = yca >= 0 && yca < Wa, cb = hb && ycb >= 0 && ycb < Wb;
+                // one unsigned compare per bound pair: negative offsets wrap high
+                const bool ca = static_cast<unsigned>(yca) < static_cast<unsigned>(Wa);
+                const bool cb = hb && static_cast<unsigned>(ycb) < static_cast<unsigned>(Wb);
                 const int xa = P.fp_x0[ma][l], Ha = P.fp_h[ma][l];
                 const int xb = P.fp_x0[mb][l], Hb = P.fp_h[mb][l];
-                const T* ia = img + P.fp_off[ma][l];
-                const T* ib = img + P.fp_off[mb][l];
+                // image bases are uniform; byte offsets within an image fit 32 bits
+                const char* ia = reinterpret_cast<const char*>(img + P.fp_off[ma][l]);
+                const char* ib = reinterpret_cast<const char*>(img + P.fp_off[mb][l]);
                 T va[RC], vb[RC];
                 bool la[RC], lb[RC];
 #pragma unroll
                 for (int k = 0; k < RC; ++k) {
                     const int ra = gx[k] - xa, rb2 = gx[k] - xb;
-                    la[k] = ca && ra >= 0 && ra < Ha;
-                    lb[k] = cb && rb2 >= 0 && rb2 < Hb;
-                    va[k] = ia[la[k] ? ra * Wa + yca : 0];
-                    vb[k] = ib[lb[k] ? rb2 * Wb + ycb : 0];
+                    la[k] = ca && static_cast<unsigned>(ra) < static_cast<unsigned>(Ha);
+                    lb[k] = cb && static_cast<unsigned>(rb2) < static_cast<unsigned>(Hb);
+                    const uint32_t oa = la[k] ? static_cast<uint32_t>(ra * Wa + yca) * sizeof(T) : 0u;
+                    const uint32_t ob = lb[k] ? static_cast<uint32_t>(rb2 * Wb + ycb) * sizeof(T) : 0u;
+                    va[k] = *reinterpret_cast<const T*>(ia + oa);
+                    vb[k] = *reinterpret_cast<const T*>(ib + ob);
                 }
 #pragma unroll
                 for (int k = 0; k < RC; ++k) {
@@ -970,8 +978,9 @@ __device__ __forceinline__ Acc adj_weight(double pa, double pb, int i, int N, in
 template <class T, int TAPS>
 __global__ void __launch_bounds__(256)
 k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int out_vec) {
-    __shared__ double wrow[ADJ_BAND][TAPS];
-    __shared__ int frow[ADJ_BAND], crow[ADJ_BAND];
+    static_assert(TAPS <= ADJ_TAPS_MAX, "adjoint taps");
+    __shared__ double wrow[TAPS][ADJ_BAND];
+    __shared__ int frow[ADJ_BAND], fofs[ADJ_BAND], crow[ADJ_BAND];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
@@ -990,9 +999,11 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
         for (int e = threadIdx.x; e < BR * Wf; e += blockDim.x) out[e] = T(0);
         return;
     }
-    const int NR = ahi - alo + 1;
+    // the staged rows are followed by TAPS - 1 rows of zeros, so the fast
+    // path reads rows f .. f + TAPS - 1 without clamping
+    const int NR = ahi - alo + 1, NRP = NR + TAPS - 1;
     T* Vs = reinterpret_cast<T*>(smem_raw);
-    Acc* Tb = reinterpret_cast<Acc*>(smem_raw + ((static_cast<size_t>(NR) * nn * sizeof(T) + 15) & ~size_t(15)));
+    Acc* Tb = reinterpret_cast<Acc*>(smem_raw + ((static_cast<size_t>(NRP) * nn * sizeof(T) + 15) & ~size_t(15)));
     const T* V = vptr<T>(J, in_vec, it.frame) + P.wfs[m].node_off + static_cast<int64_t>(alo) * nn;
     {
         // ADJ_PF loads in flight per thread: clamped addresses, predicated stores
@@ -1006,15 +1017,18 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
             for (int j = 0; j < ADJ_PF; ++j)
                 if (e0 + j * bd0 < tot) Vs[e0 + j * bd0] = v[j];
         }
+        for (int e = tot + threadIdx.x; e < NRP * nn; e += bd0) Vs[e] = T(0);
     }
     // row taps of the band: first staged row, count, weights
     if (threadIdx.x < BR) {
         const int r = r0 + threadIdx.x, f = rt[2 * r], cnt = rt[2 * r + 1];
-        frow[threadIdx.x] = cnt > 0 ? f - alo : 0;   // a row no node reaches reads row 0 with weight 0
+        const int fr = cnt > 0 ? f - alo : 0;   // a row no node reaches reads row 0 with weight 0
+        frow[threadIdx.x] = fr;
+        fofs[threadIdx.x] = fr * nn;
         crow[threadIdx.x] = cnt;
 #pragma unroll
         for (int q = 0; q < TAPS; ++q)
-            wrow[threadIdx.x][q] = q < cnt ? adj_weight(pa, pbx, f + q, N, x0 + r) : 0.0;
+            wrow[q][threadIdx.x] = q < cnt ? adj_weight(pa, pbx, f + q, N, x0 + r) : 0.0;
     }
     __syncthreads();
     const int bd = blockDim.x;
@@ -1025,17 +1039,16 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
         if (g1 < G1)
             for (int b = b0; b < nn; b += bstep)
                 for (int lr = g1; lr < BR; lr += G1) {
-                    const int f = frow[lr], cnt = crow[lr];
+                    const int cnt = crow[lr];
+                    const T* vc = Vs + fofs[lr] + b;
                     Acc acc = 0;
                     if (cnt <= TAPS) {
 #pragma unroll
-                        for (int q = 0; q < TAPS; ++q)
-                            acc += wrow[lr][q] * static_cast<Acc>(Vs[min(f + q, NR - 1) * nn + b]);
+                        for (int q = 0; q < TAPS; ++q) acc += wrow[q][lr] * static_cast<Acc>(vc[q * nn]);
                     } else {
-                        const int r = r0 + lr;
+                        const int r = r0 + lr, f = frow[lr];
                         for (int q = 0; q < cnt; ++q)
-                            acc += adj_weight(pa, pbx, alo + f + q, N, x0 + r) *
-                                   static_cast<Acc>(Vs[(f + q) * nn + b]);
+                            acc += adj_weight(pa, pbx, alo + f + q, N, x0 + r) * static_cast<Acc>(vc[q * nn]);
                     }
                     Tb[lr * nn + b] = acc;
                 }

@@ -968,6 +968,9 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             p->n_fpimg += static_cast<int64_t>(len[0]) * len[1];
             if (p->n_fpimg > (int64_t(1) << 30))
                 return fail(WMCAO_ERR_UNSUPPORTED, "adjoint footprint images too large");
+            // the level-1 analysis addresses one image with 32-bit byte offsets
+            if (static_cast<int64_t>(len[0]) * len[1] * p->esz >= (int64_t(1) << 31))
+                return fail(WMCAO_ERR_UNSUPPORTED, "adjoint footprint image too large");
             int br = ADJ_BAND, need = 0;
             for (; br >= 1; br /= 2) {
                 need = 0;
@@ -981,8 +984,10 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
                         }
                     }
                     const int rows = std::min(len[0], r0 + br) - r0;
+                    // staged node rows and the kernel's zero rows after them
                     const int vbytes =
-                        ahi < alo ? 0 : ((ahi - alo + 1) * nn * static_cast<int>(p->esz) + 15) & ~15;
+                        ahi < alo ? 0
+                                  : ((ahi - alo + ADJ_TAPS_MAX) * nn * static_cast<int>(p->esz) + 15) & ~15;
                     need = std::max(need, vbytes + rows * nn * 8);
                 }
                 if (need <= ADJ_LDS) break;
