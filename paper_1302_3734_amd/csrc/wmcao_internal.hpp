@@ -163,7 +163,7 @@ void launch_sensor(const JobArgs& a, const Item* items, int n, int mode, int in_
 template <class T>
 void launch_init(const JobArgs& a, const Item* items, int n, int warm, hipStream_t s);
 template <class T>
-void launch_update_r(const JobArgs& a, const Item* items, int n, int iter, hipStream_t s);
+void launch_update_r(const JobArgs& a, const Item* items, int n, int iter, int fresh, hipStream_t s);
 template <class T>
 void launch_update_p(const JobArgs& a, const Item* items, int n, int iter, hipStream_t s);
 template <class T>

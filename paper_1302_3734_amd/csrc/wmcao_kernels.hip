@@ -60,6 +60,32 @@ __device__ double block_sum(double v, double* red) {
     return red[16];
 }
 
+// Two deterministic block sums in the order of block_sum, for a result only
+// thread 0 needs (it is valid there only, and no barrier broadcasts it); red
+// holds 32 doubles.
+__device__ void block_sum2_first(double& a, double& b, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o, 64);
+        b += __shfl_down(b, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[wid] = a;
+        red[16 + wid] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0, t = 0.0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) s += red[i];
+        for (int i = 0; i < nw; ++i) t += red[16 + i];
+        a = s;
+        b = t;
+    }
+}
+
 // Four deterministic block sums at once (same tree as block_sum); red holds
 // 4 * 16 + 4 doubles.
 __device__ void block_sum4(double* v, double* red) {
@@ -107,6 +133,23 @@ __device__ void sum_slots3(const double* a, int na, const double* b, int nb, con
     out[1] = v[1];
     out[2] = v[2];
 }
+
+// Sum of n <= 64 values with the shuffle tree of one wave of block_sum4 (so
+// the same value as sum_slots for n <= 64), broadcast to every lane; no LDS
+// and no barrier.
+__device__ double wave_sum_small(const double* p, int n) {
+    const int lane = threadIdx.x & 63;
+    double v = p[min(lane, n - 1)];
+    v = lane < n ? v : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return __shfl(v, 0, 64);
+}
+
+// Per-frame scalars of a solve: [0] the step size a of the current
+// iteration, [1] the residual norm, [2 + parity] rho = <r, z> of the residual
+// of that parity (written by k_update_p, read by the next k_update_r).
+__device__ __forceinline__ double* frame_scal(const JobPlan& J, int f) { return J.alpha + 4 * f; }
 
 // Scale index k (1 = finest details, levels = coarsest details and low-pass)
 // of the Mallat coefficient (x, y) of an N x N layer.
@@ -620,7 +663,7 @@ template <class T>
 __global__ void __launch_bounds__(1024)
 k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int in_vec,
               int out_vec, int epi, int aux_vec) {
-    __shared__ double red[17];
+    __shared__ double red[32];
     const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -669,8 +712,8 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
         double* pq = part_ptr(J, it.frame, PT_PQ);
         double t = 0.0;
         for (int i = threadIdx.x; i < it.pad1; i += blockDim.x) t += pq[it.pad0 + i];
-        const double tiles = block_sum(t, red);
-        const double own = block_sum(acc, red);
+        double tiles = t, own = acc;
+        block_sum2_first(tiles, own, red);
         if (threadIdx.x == 0) pq[it.slot] = tiles + own;
     }
 }
@@ -1384,7 +1427,7 @@ __device__ __forceinline__ void st4(T* p, int64_t i, int64_t n, const T* v) {
 template <class T>
 __global__ void __launch_bounds__(256)
 k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
-    __shared__ double red[17];
+    __shared__ double red[32];
     const Item it = items[vec_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -1427,8 +1470,7 @@ k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
         sweep(std::true_type{});
     else
         sweep(std::false_type{});
-    rz = block_sum(rz, red);
-    rr = block_sum(rr, red);
+    block_sum2_first(rz, rr, red);
     if (threadIdx.x == 0) {
         part_ptr(J, it.frame, PT_RZ0)[it.slot] = rz;
         part_ptr(J, it.frame, PT_RR0)[it.slot] = rr;
@@ -1439,17 +1481,26 @@ k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
 // a = rho_i / <p, q>; r -= a q; partials of <r, J^-1 r>, <r, r> (next parity).
 template <class T>
 __global__ void __launch_bounds__(256)
-k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
+k_update_r(const JobArgs args, const Item* __restrict__ items, int iter, int fresh) {
     __shared__ double red[68];
     const Item it = items[vec_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
-    // <p, Ap>, rho_i and (first iteration) <r0, r0>, reduced together
-    double sums[3];
-    sum_slots3(part_ptr(J, it.frame, PT_PQ) + P.pq_base, P.L,
-               part_ptr(J, it.frame, PT_RZ0 + (iter & 1)), P.n_vec_slots,
-               part_ptr(J, it.frame, PT_RR0), iter == 0 ? P.n_vec_slots : 1, sums, red);
-    const double pq = sums[0], rho = sums[1];
+    // <p, Ap> (one total per layer) and rho_i.  rho_i is the sum k_update_p
+    // formed one iteration earlier, except on the first iteration and after a
+    // residual replacement (fresh), where the residual's partials are reduced
+    // here, together with <r0, r0> on the first iteration.
+    double pq, rho, sums[3] = {0.0, 0.0, 0.0};
+    if (fresh || iter == 0) {
+        sum_slots3(part_ptr(J, it.frame, PT_PQ) + P.pq_base, P.L,
+                   part_ptr(J, it.frame, PT_RZ0 + (iter & 1)), P.n_vec_slots,
+                   part_ptr(J, it.frame, PT_RR0), iter == 0 ? P.n_vec_slots : 1, sums, red);
+        pq = sums[0];
+        rho = sums[1];
+    } else {
+        pq = wave_sum_small(part_ptr(J, it.frame, PT_PQ) + P.pq_base, P.L);
+        rho = frame_scal(J, it.frame)[2 + (iter & 1)];
+    }
     int st = J.status[it.frame];
     double a = 0.0;
     if (st == WMCAO_FRAME_OK) {
@@ -1463,12 +1514,12 @@ k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
     if (iter == 0) {
         const double rr0 = sums[2];
         if (it.b == 0 && threadIdx.x == 0) {
-            J.alpha[2 * it.frame + 1] = sqrt(rr0);
+            frame_scal(J, it.frame)[1] = sqrt(rr0);
             if (J.resid) J.resid[static_cast<int64_t>(it.frame) * J.resid_ld] = sqrt(rr0);
         }
     }
     if (it.b == 0 && threadIdx.x == 0) {
-        J.alpha[2 * it.frame] = a;
+        frame_scal(J, it.frame)[0] = a;
         J.status[it.frame] = st;
     }
     if (st != WMCAO_FRAME_OK) return;
@@ -1505,8 +1556,7 @@ k_update_r(const JobArgs args, const Item* __restrict__ items, int iter) {
         sweep(std::true_type{});
     else
         sweep(std::false_type{});
-    rz = block_sum(rz, red);
-    rr = block_sum(rr, red);
+    block_sum2_first(rz, rr, red);
     if (threadIdx.x == 0) {
         part_ptr(J, it.frame, PT_RZ0 + ((iter + 1) & 1))[it.slot] = rz;
         part_ptr(J, it.frame, PT_RR0 + ((iter + 1) & 1))[it.slot] = rr;
@@ -1524,10 +1574,10 @@ k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
     const int st = J.status[it.frame];
     if (st != WMCAO_FRAME_OK) {
         if (it.b == 0 && threadIdx.x == 0 && J.resid)
-            J.resid[static_cast<int64_t>(it.frame) * J.resid_ld + iter + 1] = J.alpha[2 * it.frame + 1];
+            J.resid[static_cast<int64_t>(it.frame) * J.resid_ld + iter + 1] = frame_scal(J, it.frame)[1];
         return;
     }
-    const double a = J.alpha[2 * it.frame];
+    const double a = frame_scal(J, it.frame)[0];
     // rho_i, rho_{i+1} and <r, r>, reduced together
     double sums[3];
     sum_slots3(part_ptr(J, it.frame, PT_RZ0 + (iter & 1)), P.n_vec_slots,
@@ -1538,7 +1588,8 @@ k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
     if (it.b == 0) {
         const double rr = sums[2];
         if (threadIdx.x == 0) {
-            J.alpha[2 * it.frame + 1] = sqrt(rr);
+            frame_scal(J, it.frame)[1] = sqrt(rr);
+            frame_scal(J, it.frame)[2 + ((iter + 1) & 1)] = rho1;   // rho of the next iteration
             if (J.resid) J.resid[static_cast<int64_t>(it.frame) * J.resid_ld + iter + 1] = sqrt(rr);
         }
     }
@@ -1581,7 +1632,7 @@ k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
 template <class T>
 __global__ void __launch_bounds__(256)
 k_replace_r(const JobArgs args, const Item* __restrict__ items, int iter) {
-    __shared__ double red[17];
+    __shared__ double red[32];
     const Item it = items[vec_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -1620,8 +1671,7 @@ k_replace_r(const JobArgs args, const Item* __restrict__ items, int iter) {
         sweep(std::true_type{});
     else
         sweep(std::false_type{});
-    rz = block_sum(rz, red);
-    rr = block_sum(rr, red);
+    block_sum2_first(rz, rr, red);
     if (threadIdx.x == 0) {
         part_ptr(J, it.frame, PT_RZ0 + (iter & 1))[it.slot] = rz;
         part_ptr(J, it.frame, PT_RR0 + (iter & 1))[it.slot] = rr;
@@ -1865,9 +1915,9 @@ void launch_init(const JobArgs& a, const Item* items, int n, int warm, hipStream
 }
 
 template <class T>
-void launch_update_r(const JobArgs& a, const Item* items, int n, int iter, hipStream_t s) {
+void launch_update_r(const JobArgs& a, const Item* items, int n, int iter, int fresh, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_update_r<T>, dim3(n), dim3(256), 0, s, a, items, iter);
+    hipLaunchKernelGGL(k_update_r<T>, dim3(n), dim3(256), 0, s, a, items, iter, fresh);
 }
 
 template <class T>
@@ -1942,7 +1992,7 @@ void configure_kernels() {
     template void launch_weights<T>(const JobArgs&, const Item*, int, int, int, hipStream_t);       \
     template void launch_adjoint<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
     template void launch_init<T>(const JobArgs&, const Item*, int, int, hipStream_t);          \
-    template void launch_update_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \
+    template void launch_update_r<T>(const JobArgs&, const Item*, int, int, int, hipStream_t); \
     template void launch_update_p<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \
     template void launch_replace_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);     \
     template void launch_cast_from_double<T>(const double*, T*, int64_t, hipStream_t);         \

@@ -510,12 +510,17 @@ void run_solve(const JobArgs& a, const Sched& S, int n_iter, int warm, int resid
     if (warm) run_apply<T>(a, S, V_X, V_Q, s);
     timed(WMCAO_K_INIT, S.b_init, s, [&] { launch_init<T>(a, S.vec, S.n_vec, warm, s); });
     for (int it = 0; it < n_iter; ++it) {
-        if (resid_replace > 0 && it > 0 && it % resid_replace == 0) {
+        // rho of this iteration comes from the residual's partials on the
+        // first iteration and after a replacement, else from k_update_p
+        const bool replaced = resid_replace > 0 && it > 0 && it % resid_replace == 0;
+        if (replaced) {
             run_apply<T>(a, S, V_X, V_Q, s);
             timed(WMCAO_K_REPLACE_R, S.b_replace, s, [&] { launch_replace_r<T>(a, S.vec, S.n_vec, it, s); });
         }
         run_apply<T>(a, S, V_P, V_Q, s);
-        timed(WMCAO_K_UPDATE_R, S.b_update_r, s, [&] { launch_update_r<T>(a, S.vec, S.n_vec, it, s); });
+        const int fresh = it == 0 || replaced;
+        timed(WMCAO_K_UPDATE_R, S.b_update_r, s,
+              [&] { launch_update_r<T>(a, S.vec, S.n_vec, it, fresh, s); });
         timed(WMCAO_K_UPDATE_P, S.b_update_p, s, [&] { launch_update_p<T>(a, S.vec, S.n_vec, it, s); });
     }
 }
@@ -1097,10 +1102,10 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         return rc;
     if (!(p->vu = static_cast<double*>(p->alloc(static_cast<size_t>(p->n_nodes) * B * 8, &rc)))) return rc;
     if (!(p->part = static_cast<double*>(p->alloc(sizeof(double) * NPT * H.slots * B, &rc)))) return rc;
-    if (!(p->scal = static_cast<double*>(p->alloc(sizeof(double) * 2 * B, &rc)))) return rc;
+    if (!(p->scal = static_cast<double*>(p->alloc(sizeof(double) * 4 * B, &rc)))) return rc;
     if (!(p->status = static_cast<int*>(p->alloc(sizeof(int) * B, &rc)))) return rc;
     WM_HIP(hipMemset(p->part, 0, sizeof(double) * NPT * H.slots * B));
-    WM_HIP(hipMemset(p->scal, 0, sizeof(double) * 2 * B));
+    WM_HIP(hipMemset(p->scal, 0, sizeof(double) * 4 * B));
     WM_HIP(hipMemset(p->status, 0, sizeof(int) * B));
 
     // ---- Jacobi diagonal (Sec. 5.1), on the device ----------------------
