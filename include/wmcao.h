@@ -132,7 +132,15 @@ typedef struct {
  *   tile                  tile edge of the tiled wavelet kernels: 16, 32 or 64;
  *                         0 = library default
  *   lds_budget            bytes of LDS a whole-band wavelet kernel may use
- *                         (0 = library default) */
+ *                         (0 = library default)
+ *   streams               1: a solve runs on the caller's stream only; 2: a
+ *                         wmcao_solve / wmcao_solve_graph whose half batch holds
+ *                         at least 2^21 coefficients (16 or more E-ELT frames)
+ *                         runs its two halves concurrently, the second on a
+ *                         stream the plan owns (forked from and joined back to
+ *                         the caller's stream with events, so stream order and
+ *                         graph capture are unchanged; results are the same
+ *                         bit for bit); 0 = library default (2) */
 typedef struct {
     double alpha;
     double r0_m;
@@ -143,6 +151,7 @@ typedef struct {
     int precond;
     int tile;
     int lds_budget;
+    int streams;
 } wmcao_options;
 
 /* Build a plan on the current HIP device: validates the geometry, builds the

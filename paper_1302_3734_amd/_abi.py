@@ -36,7 +36,8 @@ class Wavelet(C.Structure):
 class Options(C.Structure):
     _fields_ = [("alpha", C.c_double), ("r0_m", C.c_double), ("L0_m", C.c_double),
                 ("dtype", C.c_int), ("max_batch", C.c_int), ("resid_replace_every", C.c_int),
-                ("precond", C.c_int), ("tile", C.c_int), ("lds_budget", C.c_int)]
+                ("precond", C.c_int), ("tile", C.c_int), ("lds_budget", C.c_int),
+                ("streams", C.c_int)]
 
 
 class WmcaoError(RuntimeError):

@@ -317,3 +317,39 @@ def test_edge_batches_and_zero_iterations():
     torch.cuda.synchronize()
     assert torch.all(x == 0.0)
     plan.close()
+
+
+@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
+def test_two_stream_halves_equal_one_stream(graph):
+    """A solve of 17 frames runs as halves of 8 and 9 frames on two streams
+    (the default): coefficients, residual histories and statuses are bitwise
+    those of the same solve on one stream, for warm starts and a residual
+    replacement, and twice in a row on the same buffers."""
+    require_gpu()
+    import torch
+    from paper_1302_3734_amd import Plan
+    cfg = WL.config_c1()
+    B, n_it = 17, 7
+    S0, sig, _, _ = setup(cfg)
+    slopes = np.stack([slopes_for(S0, cfg, sig, f) for f in range(B)])
+    s32 = to_dev(slopes, torch.float32)
+    x0 = torch.randn(B, S0.n, dtype=torch.float32, device="cuda", generator=torch.Generator(
+        device="cuda").manual_seed(5)) * 0.01
+    outs = {}
+    for streams in (1, 2):
+        plan = Plan(cfg, sig, dtype="f32", max_batch=B, streams=streams, resid_replace_every=4)
+        stream = torch.cuda.Stream()
+        x = x0.clone()
+        resid = torch.zeros(B, n_it + 1, dtype=torch.float64, device="cuda")
+        status = torch.zeros(B, dtype=torch.int32, device="cuda")
+        say(f"[streams] {streams} stream(s), graph={graph}")
+        with torch.cuda.stream(stream):
+            for _ in range(2):
+                plan.solve(s32, x, n_iter=n_it, warm_start=True, resid=resid, status=status,
+                           graph=graph, stream=stream)
+        stream.synchronize()
+        outs[streams] = (x.clone(), resid.clone(), status.clone())
+        plan.close()
+    for a, b in zip(outs[1], outs[2]):
+        assert torch.equal(a, b)
+    assert int(outs[2][2].min()) >= 0
