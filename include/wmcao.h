@@ -134,9 +134,10 @@ typedef struct {
  *   lds_budget            bytes of LDS a whole-band wavelet kernel may use
  *                         (0 = library default)
  *   streams               1: a solve runs on the caller's stream only; 2: a
- *                         wmcao_solve / wmcao_solve_graph whose half batch holds
- *                         at least 2^21 coefficients (16 or more E-ELT frames)
- *                         runs its two halves concurrently, the second on a
+ *                         solve (single-plan, or packed when every plan allows
+ *                         it) whose half batch holds at least 2^21 coefficients
+ *                         (16 or more E-ELT frames) runs its two halves
+ *                         concurrently, the second on a
  *                         stream the plan owns (forked from and joined back to
  *                         the caller's stream with events, so stream order and
  *                         graph capture are unchanged; results are the same

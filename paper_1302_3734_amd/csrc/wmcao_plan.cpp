@@ -398,7 +398,8 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
 }
 
 std::mutex g_multi_mu;
-std::map<std::vector<std::pair<const void*, int>>, std::unique_ptr<Sched>> g_multi_cache;
+// packed schedules by job shape: (plan, frames, first frame) per job
+std::map<std::vector<std::tuple<const void*, int, int>>, std::unique_ptr<Sched>> g_multi_cache;
 
 // Captured multi-plan solves, keyed by every argument that the graph bakes in.
 struct MultiGraphKey {
@@ -648,40 +649,86 @@ int enqueue_multi(const wmcao_plan_t* plans, const void* const* slopes, void* co
         jobs.push_back(JobSpec{plans[i], counts[i]});
     }
     // one schedule per distinct job shape, dropped when one of its plans is destroyed
-    std::vector<std::pair<const void*, int>> key;
-    for (auto& j : jobs) key.emplace_back(j.plan, j.count);
-    auto& cache = g_multi_cache;
     std::vector<std::unique_lock<std::mutex>> locks;
     for (auto& j : jobs) locks.emplace_back(j.plan->mu);
     DevGuard g(plans[0]->device);
     const int tile = plans[0]->tile;
     for (auto& j : jobs)
         if (j.plan->tile != tile) return fail(WMCAO_ERR_INVALID_ARG, "plans must share the tile size");
-    auto it = cache.find(key);
-    Sched* S = nullptr;
-    if (it == cache.end()) {
+    auto packed = [&](const std::vector<JobSpec>& js, Sched** out) -> int {
+        std::vector<std::tuple<const void*, int, int>> key;
+        for (auto& j : js) key.emplace_back(j.plan, j.count, j.first);
+        auto it = g_multi_cache.find(key);
+        if (it != g_multi_cache.end()) {
+            *out = it->second.get();
+            return WMCAO_OK;
+        }
         auto sp = std::make_unique<Sched>();
-        int rc = build_sched(jobs, tile, sp.get());
+        int rc = build_sched(js, tile, sp.get());
         if (rc) return rc;
-        S = sp.get();
-        cache[key] = std::move(sp);
-    } else {
-        S = it->second.get();
+        *out = sp.get();
+        g_multi_cache[key] = std::move(sp);
+        return WMCAO_OK;
+    };
+    // two concurrent halves (each plan's frames split in two) under the rule of
+    // a single-plan solve: every plan allows two streams and a half holds at
+    // least SPLIT_MIN_UNKNOWNS coefficients
+    int64_t total = 0;
+    bool two = true;
+    for (auto& j : jobs) {
+        total += static_cast<int64_t>(j.count) * j.plan->n;
+        two = two && j.plan->streams > 1;
     }
-    if (prepare_only) return WMCAO_OK;
-    JobArgs a{};
-    a.njp = n_plans;
-    int rr = 0;
+    std::vector<JobSpec> half[2];
+    std::vector<int> idx[2];
     for (int i = 0; i < n_plans; ++i) {
-        a.jp[i] = make_jobplan(plans[i], counts[i]);
-        a.jp[i].vec[V_X] = coeffs[i];
-        a.jp[i].vec[V_SLOPES] = const_cast<void*>(slopes[i]);
-        rr = std::max(rr, plans[i]->resid_replace);
+        const int c1 = counts[i] / 2, c0 = counts[i] - c1;
+        half[0].push_back(JobSpec{plans[i], c0, 0});
+        idx[0].push_back(i);
+        if (c1 > 0) {
+            half[1].push_back(JobSpec{plans[i], c1, c0});
+            idx[1].push_back(i);
+        }
     }
-    if (dt == WMCAO_F32)
-        run_solve<float>(a, *S, n_iter, warm_start, rr, s);
-    else
-        run_solve<double>(a, *S, n_iter, warm_start, rr, s);
+    const bool split = two && total / 2 >= SPLIT_MIN_UNKNOWNS && !half[1].empty();
+    Sched* S[2] = {nullptr, nullptr};
+    int rc = split ? packed(half[0], &S[0]) : packed(jobs, &S[0]);
+    if (!rc && split) rc = packed(half[1], &S[1]);
+    if (!rc && split) rc = ensure_side(plans[0]);
+    if (rc) return rc;
+    if (prepare_only) return WMCAO_OK;
+    int rr = 0;
+    for (int i = 0; i < n_plans; ++i) rr = std::max(rr, plans[i]->resid_replace);
+    auto args_for = [&](const std::vector<int>& ids) {
+        JobArgs a{};
+        a.njp = static_cast<int>(ids.size());
+        for (int k = 0; k < a.njp; ++k) {
+            const int i = ids[k];
+            a.jp[k] = make_jobplan(plans[i], counts[i]);
+            a.jp[k].vec[V_X] = coeffs[i];
+            a.jp[k].vec[V_SLOPES] = const_cast<void*>(slopes[i]);
+        }
+        return a;
+    };
+    auto run = [&](const JobArgs& a, const Sched& Sx, hipStream_t st) {
+        if (dt == WMCAO_F32)
+            run_solve<float>(a, Sx, n_iter, warm_start, rr, st);
+        else
+            run_solve<double>(a, Sx, n_iter, warm_start, rr, st);
+    };
+    if (!split) {
+        std::vector<int> all(n_plans);
+        for (int i = 0; i < n_plans; ++i) all[i] = i;
+        run(args_for(all), *S[0], s);
+        return check_launch();
+    }
+    wmcao_plan_s* p0 = plans[0];
+    WM_HIP(hipEventRecord(p0->ev_fork, s));
+    WM_HIP(hipStreamWaitEvent(p0->side, p0->ev_fork, 0));
+    run(args_for(idx[0]), *S[0], s);
+    run(args_for(idx[1]), *S[1], p0->side);
+    WM_HIP(hipEventRecord(p0->ev_join, p0->side));
+    WM_HIP(hipStreamWaitEvent(s, p0->ev_join, 0));
     return check_launch();
 }
 
@@ -1475,7 +1522,7 @@ void wmcao_plan_destroy(wmcao_plan_t plan) {
         std::lock_guard<std::mutex> lk(g_multi_mu);
         for (auto it = g_multi_cache.begin(); it != g_multi_cache.end();) {
             bool uses = false;
-            for (auto& kv : it->first) uses = uses || kv.first == plan;
+            for (auto& kv : it->first) uses = uses || std::get<0>(kv) == plan;
             if (uses) it = g_multi_cache.erase(it); else ++it;
         }
         for (auto it = g_multi_graphs.begin(); it != g_multi_graphs.end();) {
