@@ -5,13 +5,16 @@ Workload: the 42 m E-ELT configuration (6 sodium LGS with 84x84 Fried sensors
 and cone effect, 3 tip/tilt NGS, 9 layers of 128..256 pixels, db3 with 5
 levels, modified Jacobi PCG, 10 iterations, warm restart).  One step solves a
 batch of B frames (B independent telescope streams, each warm-started from its
-previous reconstruction) in FP32 with FP64 inner products and scalars.  Inputs
+previous reconstruction) in FP32 with FP64 inner products and scalars; the
+plan runs the batch as two concurrent halves on two HIP streams (its default
+for batches this large; --streams 1 keeps one stream).  Inputs
 are synthetic: seeded von Karman screens with frozen flow, slopes from the
 library's forward model plus Gaussian noise at SNR 20.
 
 Prints one JSON line: frames/s, p99 frame latency, the dominant kernel's
-achieved HBM bandwidth against the MI355X peak, the per-frame FP64 solve as a
-comparison, and the CPU oracle on a bounded sample.
+achieved HBM bandwidth against the MI355X peak (per-kernel times measured on
+one stream, where a launch's event time is its own), the per-frame FP64 solve
+as a comparison, and the CPU oracle on a bounded sample.
 """
 import argparse
 import json
