@@ -32,11 +32,11 @@ def test_strerror_and_last_error():
     assert isinstance(L.wmcao_last_error(), bytes)
 
 
-def _args(n=64, levels=4, order=3, n_sub=16, agg=0, dtype=0, tile=0, sigma=0.1):
+def _args(n=64, levels=4, order=3, n_sub=16, agg=0, dtype=0, tile=0, sigma=0.1, streams=0):
     Ls = (_abi.Layer * 1)(_abi.Layer(0.0, 1.0, 0.5, n))
     Ws = (_abi.Wfs * 1)(_abi.Wfs(0, 0.0, 0.0, 90e3, n_sub, agg, -1, -1, sigma, None, 0))
     pupil = _abi.Pupil(8.0, 0.0)
-    opts = _abi.Options(1.0, 0.15, 25.0, dtype, 1, 0, 1, tile, 0)
+    opts = _abi.Options(1.0, 0.15, 25.0, dtype, 1, 0, 1, tile, 0, streams)
     return pupil, Ls, Ws, _abi.Wavelet(0, order), levels, opts
 
 
@@ -49,6 +49,8 @@ def _args(n=64, levels=4, order=3, n_sub=16, agg=0, dtype=0, tile=0, sigma=0.1):
     ({"dtype": 7}, -1),
     ({"tile": 48}, -1),
     ({"sigma": 0.0}, -1),
+    ({"streams": 3}, -1),            # one stream or two concurrent halves
+    ({"streams": -1}, -1),
 ])
 def test_invalid_plans_rejected_on_host(kw, code):
     L = _abi.lib()
