@@ -135,8 +135,8 @@ typedef struct {
  *                         (0 = library default)
  *   streams               1: a solve runs on the caller's stream only; 2: a
  *                         solve (single-plan, or packed when every plan allows
- *                         it) whose half batch holds at least 2^21 coefficients
- *                         (16 or more E-ELT frames) runs its two halves
+ *                         it) whose half batch holds at least 2^20 coefficients
+ *                         (6 or more E-ELT frames) runs its two halves
  *                         concurrently, the second on a
  *                         stream the plan owns (forked from and joined back to
  *                         the caller's stream with events, so stream order and

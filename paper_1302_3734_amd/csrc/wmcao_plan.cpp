@@ -431,10 +431,11 @@ int get_sched(wmcao_plan_s* p, int batch, Sched** out, int first = 0) {
 
 // A solve runs as two concurrent halves when the plan allows two streams and
 // each half holds at least SPLIT_MIN_UNKNOWNS coefficients: the kernels of one
-// half fill the gaps the other half's leave (E-ELT frames: 9 % faster at 16
-// frames, 8 % at 32, 5 % at 64).  Smaller halves are launch-bound and lose
-// (128 frames of the 8 m system: 18 % slower), so they stay on one stream.
-constexpr int64_t SPLIT_MIN_UNKNOWNS = 2 * 1024 * 1024;
+// half fill the gaps the other half's leave (E-ELT frames: 7 % faster at 6
+// frames, 9 % at 8 to 16, 8 % at 32, 5 % at 64; 4 frames, 0.75 M per half,
+// gain nothing).  Smaller halves are launch-bound and can lose (128 frames of
+// the 8 m system, 0.79 M per half: 18 % slower), so they stay on one stream.
+constexpr int64_t SPLIT_MIN_UNKNOWNS = 1024 * 1024;
 
 bool splits(const wmcao_plan_s* p, int batch) {
     return p->streams > 1 && batch >= 2 && (batch / 2) * p->n >= SPLIT_MIN_UNKNOWNS;

@@ -321,33 +321,39 @@ def test_edge_batches_and_zero_iterations():
 
 @pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
 def test_two_stream_halves_equal_one_stream(graph):
-    """A solve of 17 frames runs as halves of 8 and 9 frames on two streams
-    (the default): coefficients, residual histories and statuses are bitwise
-    those of the same solve on one stream, for warm starts and a residual
+    """Seven E-ELT frames (1.1 M coefficients per half) run as halves of 3
+    and 4 frames on two streams (the default; the launch counts show the
+    split): coefficients, residual histories and statuses are bitwise those
+    of the same solve on one stream, for warm starts and a residual
     replacement, and twice in a row on the same buffers."""
     require_gpu()
     import torch
     from paper_1302_3734_amd import Plan
-    cfg = WL.config_c1()
-    B, n_it = 17, 7
-    S0, sig, _, _ = setup(cfg)
-    slopes = np.stack([slopes_for(S0, cfg, sig, f) for f in range(B)])
-    s32 = to_dev(slopes, torch.float32)
-    x0 = torch.randn(B, S0.n, dtype=torch.float32, device="cuda", generator=torch.Generator(
-        device="cuda").manual_seed(5)) * 0.01
+    cfg = WL.config_c2()
+    B, n_it = 7, 5
+    sig = [0.2] * 6 + [0.02, 0.006, 0.004]
+    gen = torch.Generator(device="cuda").manual_seed(5)
     outs = {}
     for streams in (1, 2):
-        plan = Plan(cfg, sig, dtype="f32", max_batch=B, streams=streams, resid_replace_every=4)
+        plan = Plan(cfg, sig, dtype="f32", max_batch=B, streams=streams, resid_replace_every=3)
+        if streams == 1:
+            s32 = torch.randn(B, plan.n_slopes, dtype=torch.float32, device="cuda", generator=gen) * 0.1
+            x0 = torch.randn(B, plan.n, dtype=torch.float32, device="cuda", generator=gen) * 0.01
         stream = torch.cuda.Stream()
         x = x0.clone()
         resid = torch.zeros(B, n_it + 1, dtype=torch.float64, device="cuda")
         status = torch.zeros(B, dtype=torch.int32, device="cuda")
         say(f"[streams] {streams} stream(s), graph={graph}")
+        if not graph:   # launch timing is not for graph capture
+            plan.profile(True)
         with torch.cuda.stream(stream):
             for _ in range(2):
                 plan.solve(s32, x, n_iter=n_it, warm_start=True, resid=resid, status=status,
                            graph=graph, stream=stream)
         stream.synchronize()
+        if not graph:   # one update_r launch per iteration and half
+            assert plan.profile_read()["update_r"][1] == 2 * n_it * streams
+            plan.profile(False)
         outs[streams] = (x.clone(), resid.clone(), status.clone())
         plan.close()
     for a, b in zip(outs[1], outs[2]):
