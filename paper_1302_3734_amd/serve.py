@@ -94,9 +94,12 @@ class Server:
         self.lane_of = {c: i % n_lanes for i, c in enumerate(names)}
         self.lane_cfgs = [[c for c in names if self.lane_of[c] == i] for i in range(n_lanes)]
         # one plan per configuration (its launches are ordered on its lane),
-        # batch = the telescope streams of that configuration
+        # batch = the telescope streams of that configuration.  The lanes are
+        # the concurrency: plans that also split large batches onto a second
+        # stream of their own made served frames slower (p50 1.2 to 3.0 ms at
+        # 2000 frames/s), so the plans here use one stream each.
         self.plans = {c: Plan(configs[c][0], configs[c][1], dtype=dtype, max_batch=count[c],
-                              tile=tile) for c in names}
+                              tile=tile, streams=1) for c in names}
         self.n = {c: p.n for c, p in self.plans.items()}
         self.n_slopes = {c: p.n_slopes for c, p in self.plans.items()}
         tdt = self.plans[names[0]].torch_dtype
