@@ -141,7 +141,10 @@ typedef struct {
  *                         stream the plan owns (forked from and joined back to
  *                         the caller's stream with events, so stream order and
  *                         graph capture are unchanged; results are the same
- *                         bit for bit); 0 = library default (2) */
+ *                         bit for bit); 0 = library default (2).  A caller that
+ *                         already overlaps several plans on streams of its own
+ *                         should pass 1: streams beyond the device's hardware
+ *                         queues can queue unrelated work behind each other */
 typedef struct {
     double alpha;
     double r0_m;
