@@ -67,9 +67,23 @@ def _cpu_worker(args):
     return done, spent
 
 
-def cpu_baseline(workers, frames_per_worker, n_iter):
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workers, frames_per_worker, n_iter, single_frames=3):
+    """The FP64 oracle on the host: one process with one thread, then one
+    single-threaded process per core, each solving frames of its own stream."""
     import multiprocessing as mp
     ctx = mp.get_context("fork")
+    with ctx.Pool(1) as pool:
+        d1, s1 = pool.map(_cpu_worker, [(0, single_frames, n_iter)])[0]
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
         res = pool.map(_cpu_worker, [(w, frames_per_worker, n_iter) for w in range(workers)])
@@ -77,10 +91,13 @@ def cpu_baseline(workers, frames_per_worker, n_iter):
     rate = sum(d / s for d, s in res)
     frames = sum(d for d, _ in res)
     return {"value": rate, "unit": "frames/s", "cores": workers, "kind": "oracle",
-            "sample": f"{workers} processes x {frames_per_worker} frames of the E-ELT workload "
-                      f"({frames} frames), FP64 NumPy oracle, right side + {n_iter} warm PCG "
-                      f"iterations timed per frame; plan, Jacobi and input synthesis excluded; "
-                      f"wall {wall:.1f} s"}
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread": {"value": d1 / s1, "unit": "frames/s", "cores": 1,
+                              "sample": f"{d1} frames, one process, one thread"},
+            "sample": f"{workers} single-threaded processes x {frames_per_worker} frames of the "
+                      f"E-ELT workload ({frames} frames), FP64 NumPy oracle, right side + "
+                      f"{n_iter} warm PCG iterations timed per frame; plan, Jacobi and input "
+                      f"synthesis excluded; wall {wall:.1f} s"}
 
 
 # ----------------------------------------------------------------- GPU leg ----
@@ -159,11 +176,40 @@ def served_stream(duration_s, rate_hz, n_iter, plain_fp64=False):
             "mean_frames_per_launch": round(float(np.mean(srv.frames_in_launch)), 3)}
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of a library kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by its
-    copy-kernel calibration factor), or None if there is none or the kernel
-    source has changed since the counters were taken."""
+# Stages of one operator apply and of the PCG updates, the library kernels
+# (timing kinds) that carry them, and the elements each pass must move by the
+# survey's algorithmic count (n unknowns, Q sensor nodes): W^-1 reads and
+# writes n; the projection chain reads n and writes the Q node fields; P^T
+# reads Q and writes n; W + alpha D reads the n-pixel P^T image and p, and
+# writes n (the right side's pass: 2n); the updates move 7n (x, r and the
+# inner products) + 4n (p) per iteration, and the initial residual 5n.
+STAGES = [
+    ("W^-1", ("idwt_coarse", "idwt_tile")),
+    ("P, Gamma, C^-1, Gamma^T", ("project", "weights")),
+    ("P^T", ("adjoint",)),
+    ("W + alpha D", ("fdwt_tile", "fdwt_coarse")),
+    ("PCG updates", ("init", "update_r", "update_p", "replace_r")),
+]
+
+
+def stage_elements(n, Q, steps, iters):
+    """Algorithmic elements moved by each stage over `steps` warm solves of
+    `iters` iterations (per frame): each solve is one right side, one apply
+    for the warm start's residual and one apply per iteration."""
+    applies, rhs = steps * (1 + iters), steps
+    return {"W^-1": applies * 2 * n,
+            "P, Gamma, C^-1, Gamma^T": applies * (n + Q),
+            "P^T": (applies + rhs) * (Q + n),
+            "W + alpha D": applies * 3 * n + rhs * 2 * n,
+            "PCG updates": steps * (iters * 11 * n + 5 * n)}
+
+
+def measured_traffic(prof, kernels):
+    """HBM bytes per launch of a group of library kernels from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by its
+    copy-kernel calibration factor), weighted by the launches of each kernel
+    in `prof`; None if there is no summary, a kernel is missing from it or the
+    kernel source has changed since the counters were taken."""
     import hashlib
     try:
         lines = open(TRAFFIC_FILE).read().splitlines()
@@ -179,14 +225,27 @@ def measured_traffic(kernel):
             if len(f) >= 3 and f[0].startswith("k_"):
                 rows[f[0]] = (float(f[1]), float(f[2]))
     src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    name = "k_" + kernel
-    if meta.get("kernel source sha256") != src or name not in rows:
+    if meta.get("kernel source sha256") != src:
         return None
     ff = float(meta.get("fetch calibration factor", "nan"))
     fw = float(meta.get("write calibration factor", "nan"))
-    fetch, write = rows[name]
-    val = 1024.0 * (fetch * ff + write * fw)
-    return round(val) if math.isfinite(val) else None
+    tot, cnt = 0.0, 0
+    for k in kernels:
+        launches = prof[k][1]
+        if not launches:
+            continue
+        if "k_" + k not in rows:
+            return None
+        fetch, write = rows["k_" + k]
+        tot += 1024.0 * (fetch * ff + write * fw) * launches
+        cnt += launches
+    if not cnt or not math.isfinite(tot):
+        return None
+    return round(tot / cnt)
+
+
+def n_nodes(cfg):
+    return sum((w["n_sub"] + 1) ** 2 for w in cfg["wfs"])
 
 
 def _synthetic_slopes(cfg, plan, frames, seeds=None, sig=None):
@@ -505,30 +564,48 @@ def main():
         p1.solve(slopes32[t], X, n_iter=IT, warm_start=True)
 
     step1(Wm + K + 1)
+    prof_steps = 5
     p1.profile(True)
-    for i in range(5):
+    for i in range(prof_steps):
         step1(Wm + K + 2 + i)
     torch.cuda.synchronize()
     prof = p1.profile_read()
     p1.profile(False)
     if p1 is not p32:
         p1.close()
-    dom = max(prof, key=lambda k: prof[k][0])
-    dms, dcnt, dbytes = prof[dom]
-    avg_s = dms / max(dcnt, 1) / 1e3
-    abytes = dbytes / max(dcnt, 1)
-    achieved = abytes / avg_s / 1e9
+    esz = 4
+    Q = n_nodes(cfg)
+    elems = stage_elements(n, Q, prof_steps, IT)
+    stages = {}
+    for name, ks in STAGES:
+        ms = sum(prof[k][0] for k in ks)
+        launches = sum(prof[k][1] for k in ks)
+        if not launches:
+            continue
+        abytes = elems[name] * esz * B                      # over the profiled window
+        design = sum(prof[k][2] for k in ks)
+        stages[name] = {"kernels": list(ks), "ms": round(ms, 4), "launches": launches,
+                        "avg_launch_us": round(1e3 * ms / launches, 3),
+                        "bytes_per_launch": round(abytes / launches),
+                        "achieved_gbs": round(abytes / (ms / 1e3) / 1e9, 1),
+                        "frac": round(abytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "design_bytes_per_launch": round(design / launches),
+                        "traffic_per_launch": measured_traffic(prof, ks)}
     tot_ms = sum(v[0] for v in prof.values())
     kernels = {k: {"avg_us": round(1e3 * v[0] / v[1], 3), "launches": v[1],
-                   "share": round(v[0] / tot_ms, 4),
-                   "gbs": round(v[2] / (v[0] / 1e3) / 1e9, 1)}
+                   "share": round(v[0] / tot_ms, 4)}
                for k, v in prof.items() if v[1]}
-    print(f"[bench] dominant kernel {dom}: {1e6 * avg_s:.1f} us/launch, {achieved:.0f} GB/s "
-          f"(one stream; timed steps {'two concurrent halves' if halves else 'one stream'})",
-          flush=True)
+    dom = max((nm for nm in stages if nm != "PCG updates"), key=lambda nm: stages[nm]["ms"])
+    D = stages[dom]
+    print(f"[bench] dominant operator stage {dom}: {D['avg_launch_us']:.1f} us/launch, "
+          f"{D['achieved_gbs']:.0f} GB/s by algorithmic bytes (one stream; timed steps "
+          f"{'two concurrent halves' if halves else 'one stream'})", flush=True)
+    for nm, v in stages.items():
+        print(f"[bench]   stage {nm:26s} {v['ms'] / prof_steps:8.3f} ms/step  x{v['launches']:4d}  "
+              f"{v['achieved_gbs']:7.1f} GB/s  frac {v['frac']:.3f}", flush=True)
     for k, v in kernels.items():
         print(f"[bench]   {k:12s} {v['avg_us']:9.1f} us  x{v['launches']:4d}  "
-              f"{100 * v['share']:5.1f}%  {v['gbs']:7.1f} GB/s", flush=True)
+              f"{100 * v['share']:5.1f}%", flush=True)
 
     # ---- reconstruction check and the per-frame FP64 comparison -------------
     result = {}
@@ -667,15 +744,22 @@ def main():
                    "concurrent_halves": bool(halves)},
         "p50_frame_latency_ms": round(p50, 4),
         "p99_frame_latency_ms": round(p99, 4),
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dom), "traffic_unit": "bytes per launch",
-                     "avg_launch_us": round(1e6 * avg_s, 3),
-                     "algorithmic_bytes_per_launch": int(abytes),
+        "roofline": {"bound": "hbm", "kernel": dom, "kernels": D["kernels"],
+                     "achieved": D["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": D["frac"], "traffic": D["traffic_per_launch"],
+                     "traffic_unit": "bytes per launch",
+                     "avg_launch_us": D["avg_launch_us"],
+                     "algorithmic_bytes_per_launch": D["bytes_per_launch"],
+                     "design_bytes_per_launch": D["design_bytes_per_launch"],
+                     "bytes_rule": ("survey's algorithmic count per stage pass: W^-1 2n, "
+                                    "P chain n+Q, P^T Q+n, W + alpha D 3n (right side 2n), "
+                                    "updates 11n per iteration; x 4 B x frames, divided by "
+                                    "the stage's launches"),
                      "measured_on": ("one stream, the same kernels over the whole batch (the "
                                      "timed steps run it as two concurrent halves, where a "
                                      "launch's event time would also hold the other half's "
                                      "kernels)") if halves else "the timed configuration"},
+        "stages": stages,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

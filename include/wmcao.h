@@ -124,8 +124,9 @@ typedef struct {
  *   alpha                 weight of the prior (eq. (19))
  *   r0_m, L0_m            Fried parameter (at the phase wavelength) and outer
  *                         scale entering D (Sec. 3)
- *   dtype                 operator and vector precision; scalars and inner
- *                         products are always FP64
+ *   dtype                 precision of the PCG vectors (x, b, r, p, A p, J) and
+ *                         of the caller's buffers; inner products, step scalars
+ *                         and the residual-replacement norms are always FP64
  *   max_batch             largest batch any call will pass (scratch is sized for it)
  *   resid_replace_every   R > 0: r <- b - A x every R iterations (0 = never)
  *   precond               0: plain CG, 1: modified Jacobi
@@ -144,7 +145,25 @@ typedef struct {
  *                         bit for bit); 0 = library default (2).  A caller that
  *                         already overlaps several plans on streams of its own
  *                         should pass 1: streams beyond the device's hardware
- *                         queues can queue unrelated work behind each other */
+ *                         queues can queue unrelated work behind each other
+ *   op_precision          type of the operator stages of a WMCAO_F32 plan (the
+ *                         wavelet tiles and low-pass scratch, the layer pixel
+ *                         fields, the adjoint node fields and footprint images,
+ *                         and their arithmetic): 32 or 64; 0 = library default:
+ *                         64 for plans of fewer than 2^17 unknowns (their solves
+ *                         are bound by launch latency, and their 10-step iterates
+ *                         are sensitive enough to rounding that single-precision
+ *                         operators move them by more than 1e-5), 32 otherwise.
+ *                         WMCAO_F64 plans take 0 or 64.  The projection's node
+ *                         fields, the slopes and the noise weighting are FP64 in
+ *                         every plan.  Plans packed into one launch run in one
+ *                         group per operator type (at most two types).
+ *   op_fp64_stages        with 32-bit operator storage: the stages whose
+ *                         arithmetic and LDS tiles are FP64, a mask of 1 (W^-1),
+ *                         2 (P^T) and 4 (W, with the sum of the P^T images);
+ *                         -1 = library default (4: the forward transform takes
+ *                         small differences of the summed P^T image, the other
+ *                         two stages run in FP32). */
 typedef struct {
     double alpha;
     double r0_m;
@@ -156,6 +175,8 @@ typedef struct {
     int tile;
     int lds_budget;
     int streams;
+    int op_precision;
+    int op_fp64_stages;
 } wmcao_options;
 
 /* Build a plan on the current HIP device: validates the geometry, builds the
@@ -237,7 +258,7 @@ int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int b
 /* Kernel kinds for per-kernel timing. */
 #define WMCAO_K_IDWT_COARSE 0   /* W^-1, low-pass block in LDS            */
 #define WMCAO_K_IDWT_TILE 1     /* W^-1, one tiled level                  */
-#define WMCAO_K_SENSOR 2        /* Gamma, C^-1, (I-T), Gamma^T            */
+#define WMCAO_K_SENSOR 2        /* right side / forward model: C^-1, (I-T), Gamma^T of the slopes */
 #define WMCAO_K_FDWT_TILE 3     /* W one tiled level (+ sum of the P^T footprint images at level 1) + alpha D, dot */
 #define WMCAO_K_FDWT_COARSE 4   /* W coarse levels + alpha D, dot         */
 #define WMCAO_K_INIT 5          /* r0, p0                                 */
@@ -246,7 +267,8 @@ int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int b
 #define WMCAO_K_REPLACE_R 8     /* r = b - A x                            */
 #define WMCAO_K_PROJECT 9       /* P: layers -> sensor node fields        */
 #define WMCAO_K_ADJOINT 10      /* P^T: node fields -> footprint images per sensor and layer */
-#define WMCAO_K_COUNT 11
+#define WMCAO_K_WEIGHTS 11      /* operator apply: Gamma, C^-1, (I-T), Gamma^T per node band */
+#define WMCAO_K_COUNT 12
 
 /* Per-kernel timing of later wmcao_solve / wmcao_apply_A calls on this plan:
  * with enable != 0 every launch is bracketed by HIP events on the launch

@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(HERE, "libwmcao.so")
 WMCAO_F32, WMCAO_F64 = 0, 1
 WMCAO_FRAME_OK, WMCAO_FRAME_CONVERGED, WMCAO_FRAME_BREAKDOWN = 0, 1, -7
 KERNELS = ["idwt_coarse", "idwt_tile", "sensor", "fdwt_tile", "fdwt_coarse", "init", "update_r",
-           "update_p", "replace_r", "project", "adjoint"]
+           "update_p", "replace_r", "project", "adjoint", "weights"]
 ERRORS = {-1: "INVALID_ARG", -2: "SIZE", -3: "FOOTPRINT", -4: "UNSUPPORTED", -5: "OOM",
           -6: "HIP", -7: "BREAKDOWN"}
 
@@ -37,7 +37,7 @@ class Options(C.Structure):
     _fields_ = [("alpha", C.c_double), ("r0_m", C.c_double), ("L0_m", C.c_double),
                 ("dtype", C.c_int), ("max_batch", C.c_int), ("resid_replace_every", C.c_int),
                 ("precond", C.c_int), ("tile", C.c_int), ("lds_budget", C.c_int),
-                ("streams", C.c_int)]
+                ("streams", C.c_int), ("op_precision", C.c_int), ("op_fp64_stages", C.c_int)]
 
 
 class WmcaoError(RuntimeError):

@@ -12,7 +12,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["wmcao_kernels.hip", "wmcao_plan.cpp"]
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are switched off for every HIP translation unit.
-FLAGS = ["-x", "hip", "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
+FLAGS = ["-x", "hip", "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++20",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 

@@ -24,14 +24,14 @@ enum Vec : int {
     V_R,          // residual
     V_P,          // search direction
     V_Q,          // A p
-    V_PHI,        // layer pixel fields (scratch)
-    V_LL,         // intermediate low-pass bands (scratch)
-    V_NODE,       // sensor node fields (scratch)
+    V_PHI,        // layer pixel fields (scratch, operator type)
+    V_LL,         // intermediate low-pass bands (scratch, operator type)
+    V_NODE,       // adjoint sensor node fields (scratch, operator type)
     V_SLOPES,     // caller's slopes (in)
     V_IN,         // caller's generic input
     V_OUT,        // caller's generic output
     V_U,          // sensor node fields of the projection, FP64 (scratch)
-    V_FP,         // per (sensor, layer) adjoint-projection footprint images (scratch)
+    V_FP,         // per (sensor, layer) adjoint-projection footprint images (scratch, operator type)
     V_SPART,      // per (sensor, node band) slope sums for tip/tilt and cells, FP64 (scratch)
     NV
 };
@@ -71,6 +71,7 @@ struct WfsInfo {
 
 struct PlanDev {
     int L, W, levels, dtype;
+    int op64;               // 1: operator storage S = double, 0: S = float
     int precond;
     int n_fdwt_slots;       // partial slots written by one wavelet-analysis pass per frame
     int pq_base;            // first of the L per-layer <p, Ap> totals
@@ -137,27 +138,31 @@ enum EpiMode : int { EPI_NONE = 0, EPI_APPLY = 1 };
 enum SensorMode : int { SM_APPLY = 0, SM_RHS = 1, SM_FWD = 2 };
 
 // ---- launchers (defined in wmcao_kernels.hip) --------------------------------
-template <class T>
+// T: storage of the PCG vectors and of the caller's slopes; S: storage of the
+// operator's intermediates (low-pass scratch, layer pixels, adjoint node fields
+// and footprint images); C: arithmetic and LDS tiles of the wavelet and
+// adjoint-projection stages.
+template <class T, class S, class C>
 void launch_idwt_coarse(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
                         int lds_bytes, hipStream_t s);
-template <class T>
+template <class T, class S, class C>
 void launch_idwt_tile(const JobArgs& a, const Item* items, int n, int level, int in_vec,
                       int out_vec, int tile, int lds_bytes, hipStream_t s);
-template <class T>
+template <class T, class S, class C>
 void launch_fdwt_tile(const JobArgs& a, const Item* items, int n, int level, int src, int in_vec,
                       int out_vec, int epi, int aux_vec, int tile, hipStream_t s);
-template <class T>
+template <class T, class S, class C>
 void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int in_vec,
                         int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s);
-template <class T>
+template <class T, class S>
 void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, hipStream_t s);
-template <class T>
+template <class T, class S>
 void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, int lds_bytes,
                     hipStream_t s);
-template <class T>
+template <class T, class S, class C>
 void launch_adjoint(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
                     int lds_bytes, int taps, hipStream_t s);
-template <class T>
+template <class T, class S>
 void launch_sensor(const JobArgs& a, const Item* items, int n, int mode, int in_vec, int out_vec,
                    int lds_bytes, hipStream_t s);
 template <class T>
@@ -174,8 +179,8 @@ void launch_jacobi(const PlanDev* P, const double* protos, const int* proto_off,
 void configure_kernels();
 template <class T>
 void launch_axpby(int64_t n, double a, const T* x, double b, const T* y, T* out, hipStream_t s);
-template <class T>
-void launch_cast_from_double(const double* in, T* out, int64_t n, hipStream_t s);
+template <class S, class D>
+void launch_cast(const S* in, D* out, int64_t n, hipStream_t s);
 
 constexpr int FUSE_LDS = 32 * 1024;   // largest low-pass block a synthesis tile rebuilds
 constexpr int TILE_NT = 256;          // threads of a wavelet tile block

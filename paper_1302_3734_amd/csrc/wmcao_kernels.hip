@@ -16,12 +16,20 @@
 //           k_update_p, k_replace_r
 //   plan time: k_jacobi (separable closed form of the Jacobi diagonal)
 //
-// Storage type T (float or double) is what crosses HBM and LDS tiles; every
-// sum, product and filter tap is evaluated in FP64 registers (type Acc), so the
-// FP32 path pays single-precision rounding only where a value is stored.  All
-// inner products are accumulated in FP64 and reduced in a fixed order (one
-// partial per block, summed by the consumer), so a frame's result does not
-// depend on what else is in the batch.
+// Three types parameterise the kernels.  T (float or double) is the storage
+// of the PCG vectors (x, b, r, p, A p, J) and of the caller's slopes.  S is the
+// storage of the operator's intermediates in HBM: the layer pixel fields, the
+// adjoint node fields and footprint images.  C is the arithmetic of the
+// wavelet and adjoint-projection stages, the type of their LDS tiles and of
+// the low-pass scratch bands that carry a transform from one level to the
+// next (a coarse band rounded to single precision loses the small details the
+// next analysis level takes from it).  FP64 plans use S = C = double; FP32 plans use S = float
+// with C chosen per stage, or S = C = double.  The projection's node fields,
+// the Fried slopes and the noise weighting are FP64 in every plan (the slopes
+// are differences of nearly equal node values), and every inner product is
+// accumulated in FP64 and reduced in a fixed order (one partial per block,
+// summed by the consumer), so a frame's result does not depend on what else
+// is in the batch.
 #include <initializer_list>
 #include <type_traits>
 
@@ -35,6 +43,15 @@ using Acc = double;
 template <class T>
 __device__ __forceinline__ T* vptr(const JobPlan& J, int v, int frame) {
     return reinterpret_cast<T*>(J.vec[v]) + static_cast<int64_t>(frame) * J.stride[v];
+}
+
+// Low-pass scratch of a frame: its region holds ll_size 8-byte elements
+// whatever type a stage keeps there, so that frames never overlap when stages
+// of different arithmetic run side by side.
+template <class C>
+__device__ __forceinline__ C* ll_ptr(const JobPlan& J, int frame) {
+    return reinterpret_cast<C*>(reinterpret_cast<char*>(J.vec[V_LL]) +
+                                static_cast<int64_t>(frame) * J.stride[V_LL] * 8);
 }
 
 __device__ __forceinline__ double* part_ptr(const JobPlan& J, int frame, int seg) {
@@ -161,11 +178,12 @@ __device__ __forceinline__ int level_of(int x, int y, int N, int levels) {
     return k;
 }
 
-__device__ __forceinline__ void load_filters(const PlanDev& P, Acc* hf, Acc* gf) {
+template <class C>
+__device__ __forceinline__ void load_filters(const PlanDev& P, C* hf, C* gf) {
 #pragma unroll
     for (int n = 0; n < 6; ++n) {
-        hf[n] = P.h[n];
-        gf[n] = P.g[n];
+        hf[n] = static_cast<C>(P.h[n]);
+        gf[n] = static_cast<C>(P.g[n]);
     }
 }
 
@@ -174,22 +192,23 @@ __device__ __forceinline__ void load_filters(const PlanDev& P, Acc* hf, Acc* gf)
 // registers.  A work item is one coarse position k of one line and yields the
 // output pair x[2k + par] = sum_t h[par + 2t] lo[k - t] + g[par + 2t] hi[k - t]
 // (par = 0, 1; indices mod M/2), so every filter tap is a compile-time index.
-__device__ void syn_pass(Acc* A, int ld, int M, int along_y, const Acc* hf, const Acc* gf) {
+template <class C>
+__device__ void syn_pass(C* A, int ld, int M, int along_y, const C* hf, const C* gf) {
     const int H = M >> 1, cnt = M * H;
-    Acc r0v[WM_QMAX / 2], r1v[WM_QMAX / 2];
+    C r0v[WM_QMAX / 2], r1v[WM_QMAX / 2];
 #pragma unroll
     for (int r = 0; r < WM_QMAX / 2; ++r) {
         const int e = threadIdx.x + r * blockDim.x;
         if (e < cnt) {
             int line, k;
             if (along_y) { line = e / H; k = e - line * H; } else { k = e / M; line = e - k * M; }
-            Acc x0 = 0, x1 = 0;
+            C x0 = 0, x1 = 0;
 #pragma unroll
             for (int t = 0; t < 3; ++t) {
                 int kk = k - t;
                 if (kk < 0) kk += H;
-                const Acc lo = along_y ? A[line * ld + kk] : A[kk * ld + line];
-                const Acc hi = along_y ? A[line * ld + H + kk] : A[(H + kk) * ld + line];
+                const C lo = along_y ? A[line * ld + kk] : A[kk * ld + line];
+                const C hi = along_y ? A[line * ld + H + kk] : A[(H + kk) * ld + line];
                 x0 += hf[2 * t] * lo + gf[2 * t] * hi;
                 x1 += hf[2 * t + 1] * lo + gf[2 * t + 1] * hi;
             }
@@ -219,21 +238,22 @@ __device__ void syn_pass(Acc* A, int ld, int M, int along_y, const Acc* hf, cons
 // One in-place periodic analysis step: a work item is one coarse position c
 // of one line and yields a_c = sum_n h_n x[(2c+n) mod M] (low half) and
 // d_c = sum_n g_n x[(2c+n) mod M] (high half).
-__device__ void ana_pass(Acc* A, int ld, int M, int along_y, const Acc* hf, const Acc* gf) {
+template <class C>
+__device__ void ana_pass(C* A, int ld, int M, int along_y, const C* hf, const C* gf) {
     const int H = M >> 1, cnt = M * H;
-    Acc r0v[WM_QMAX / 2], r1v[WM_QMAX / 2];
+    C r0v[WM_QMAX / 2], r1v[WM_QMAX / 2];
 #pragma unroll
     for (int r = 0; r < WM_QMAX / 2; ++r) {
         const int e = threadIdx.x + r * blockDim.x;
         if (e < cnt) {
             int line, c;
             if (along_y) { line = e / H; c = e - line * H; } else { c = e / M; line = e - c * M; }
-            Acc lo = 0, hi = 0;
+            C lo = 0, hi = 0;
 #pragma unroll
             for (int n = 0; n < 6; ++n) {
                 int idx = 2 * c + n;
                 if (idx >= M) idx -= M;
-                const Acc v = along_y ? A[line * ld + idx] : A[idx * ld + line];
+                const C v = along_y ? A[line * ld + idx] : A[idx * ld + line];
                 lo += hf[n] * v;
                 hi += gf[n] * v;
             }
@@ -292,16 +312,16 @@ __device__ __forceinline__ void node_stencil(double pa, double pb, int i, int N,
 }
 
 // P^T over a window of PR x PC pixels of layer l starting at (px0, py0)
-// (periodic indices, px0 + PR < 2N), written into G (row stride ldg, FP64):
+// (periodic indices, px0 + PR < 2N), written into G (row stride ldg):
 // the sum, in sensor order, of the footprint images of the sensors in mask
 // (k_adjoint).  A thread owns one window column and every rstep-th row, so
 // each G entry has one writer: no atomics and no barrier.  Rows go in chunks
 // of RC held in registers, two sensors per step; every load goes to a valid
 // address (clamped) with the value selected afterwards, so the 2 RC loads of
 // a step are all in flight before the first is added.
-template <class T, int RC>
-__device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, int px0, int py0,
-                                 int PR, int PC, Acc* G, int ldg, unsigned mask) {
+template <class S, class C, int RC>
+__device__ void pt_gather_window(const PlanDev& P, const S* img, int l, int N, int px0, int py0,
+                                 int PR, int PC, C* G, int ldg, unsigned mask) {
     const int tid = threadIdx.x, bd = blockDim.x;
     int c0, r0, rstep, cstep;
     if (PC <= bd) {
@@ -321,7 +341,7 @@ __device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, i
         if (gy >= N) gy -= N;
         for (int rb = r0; rb < PR; rb += RC * rstep) {
             int gx[RC];
-            Acc g[RC];
+            C g[RC];
 #pragma unroll
             for (int k = 0; k < RC; ++k) {
                 const int r = rb + k * rstep;
@@ -349,22 +369,22 @@ __device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, i
                 // image bases are uniform; byte offsets within an image fit 32 bits
                 const char* ia = reinterpret_cast<const char*>(img + P.fp_off[ma][l]);
                 const char* ib = reinterpret_cast<const char*>(img + P.fp_off[mb][l]);
-                T va[RC], vb[RC];
+                S va[RC], vb[RC];
                 bool la[RC], lb[RC];
 #pragma unroll
                 for (int k = 0; k < RC; ++k) {
                     const int ra = gx[k] - xa, rb2 = gx[k] - xb;
                     la[k] = ca && static_cast<unsigned>(ra) < static_cast<unsigned>(Ha);
                     lb[k] = cb && static_cast<unsigned>(rb2) < static_cast<unsigned>(Hb);
-                    const uint32_t oa = la[k] ? static_cast<uint32_t>(ra * Wa + yca) * sizeof(T) : 0u;
-                    const uint32_t ob = lb[k] ? static_cast<uint32_t>(rb2 * Wb + ycb) * sizeof(T) : 0u;
-                    va[k] = *reinterpret_cast<const T*>(ia + oa);
-                    vb[k] = *reinterpret_cast<const T*>(ib + ob);
+                    const uint32_t oa = la[k] ? static_cast<uint32_t>(ra * Wa + yca) * sizeof(S) : 0u;
+                    const uint32_t ob = lb[k] ? static_cast<uint32_t>(rb2 * Wb + ycb) * sizeof(S) : 0u;
+                    va[k] = *reinterpret_cast<const S*>(ia + oa);
+                    vb[k] = *reinterpret_cast<const S*>(ib + ob);
                 }
 #pragma unroll
                 for (int k = 0; k < RC; ++k) {
-                    if (la[k]) g[k] += static_cast<Acc>(va[k]);
-                    if (lb[k]) g[k] += static_cast<Acc>(vb[k]);
+                    if (la[k]) g[k] += static_cast<C>(va[k]);
+                    if (lb[k]) g[k] += static_cast<C>(vb[k]);
                 }
             }
 #pragma unroll
@@ -376,8 +396,9 @@ __device__ void pt_gather_window(const PlanDev& P, const T* img, int l, int N, i
 
 // ------------------------------------------------------------------ W^-1 ----
 // Levels J..k0+1 of the synthesis of one layer, with the whole M0 x M0
-// (M0 = N / 2^k0) low-pass block resident in LDS (FP64).
-template <class T>
+// (M0 = N / 2^k0) low-pass block resident in LDS.  Coefficients in T; the
+// result in C (LL_k0 scratch) or, at k0 = 0, in S (the pixels).
+template <class T, class S, class C>
 __global__ void __launch_bounds__(1024)
 k_idwt_coarse(const JobArgs args, const Item* __restrict__ items, int in_vec, int out_vec) {
     const Item it = items[xcd_item()];
@@ -386,38 +407,38 @@ k_idwt_coarse(const JobArgs args, const Item* __restrict__ items, int in_vec, in
     const LayerInfo& Ly = P.layer[it.a];
     const int N = Ly.N, k0 = Ly.k0, M0 = N >> k0;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    Acc* A = reinterpret_cast<Acc*>(smem_raw);
-    Acc hf[6], gf[6];
+    C* A = reinterpret_cast<C*>(smem_raw);
+    C hf[6], gf[6];
     load_filters(P, hf, gf);
     const T* src = vptr<T>(J, in_vec, it.frame) + Ly.coff;
     for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x)
-        A[e] = src[static_cast<int64_t>(e / M0) * N + (e % M0)];
+        A[e] = static_cast<C>(src[static_cast<int64_t>(e / M0) * N + (e % M0)]);
     __syncthreads();
     for (int lev = P.levels; lev > k0; --lev) {
         const int M = N >> (lev - 1);
         syn_pass(A, M0, M, 0, hf, gf);   // undo the x step
         syn_pass(A, M0, M, 1, hf, gf);   // undo the y step
     }
-    if (k0 > 0) {   // low-pass band of the finest coarse level: FP64 scratch
-        double* dst = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[k0];
+    if (k0 > 0) {   // low-pass band of the finest coarse level: scratch (C)
+        C* dst = ll_ptr<C>(J, it.frame) + Ly.ll_off[k0];
         for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) dst[e] = A[e];
     } else {
-        T* dst = vptr<T>(J, out_vec, it.frame) + Ly.coff;
-        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) dst[e] = static_cast<T>(A[e]);
+        S* dst = vptr<S>(J, out_vec, it.frame) + Ly.coff;
+        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) dst[e] = static_cast<S>(A[e]);
     }
 }
 
 // One synthesis level k <= k0 over a TS x TS output tile: reads the low-pass
 // band LL_k (scratch) and the three level-k detail bands (Mallat regions of the
 // input coefficients) on a (TS/2+2)^2 window, writes LL_{k-1} (scratch) or, at
-// k = 1, the layer pixels.
-template <class T, int TS>
+// k = 1, the layer pixels (S).
+template <class T, class S, class C, int TS>
 __global__ void __launch_bounds__(TILE_NT)
 k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int in_vec,
             int out_vec) {
     constexpr int CW = TS / 2 + 2;
-    __shared__ Acc sLL[CW][CW + 1], sLH[CW][CW + 1], sHL[CW][CW + 1], sHH[CW][CW + 1];
-    __shared__ Acc sAL[TS][CW + 1], sAH[TS][CW + 1];
+    __shared__ C sLL[CW][CW + 1], sLH[CW][CW + 1], sHL[CW][CW + 1], sHH[CW][CW + 1];
+    __shared__ C sAL[TS][CW + 1], sAH[TS][CW + 1];
     const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -425,25 +446,26 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
     const int N = Ly.N, M = N >> (level - 1), H = M >> 1;
     const int ntx = (M + TS - 1) / TS;
     const int x0 = (it.b % ntx) * TS, y0 = (it.b / ntx) * TS;
-    Acc hf[6], gf[6];
+    C hf[6], gf[6];
     load_filters(P, hf, gf);
     const T* src = vptr<T>(J, in_vec, it.frame) + Ly.coff;
-    const double* ll = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level];
+    const C* llg = ll_ptr<C>(J, it.frame) + Ly.ll_off[level];
+    const C* lll = nullptr;    // LL_k rebuilt in LDS by this tile, else read from llg
     if (level == Ly.k0 && Ly.fuse) {
         // rebuild LL_k0 = the synthesis of levels J..k0+1 of the coarse block
         // (Mallat top-left M0 x M0) in LDS; every tile of this level repeats it
         extern __shared__ __align__(16) unsigned char smem_raw[];
-        Acc* Ac = reinterpret_cast<Acc*>(smem_raw);
+        C* Ac = reinterpret_cast<C*>(smem_raw);
         const int M0 = H;
         for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x)
-            Ac[e] = src[static_cast<int64_t>(e / M0) * N + (e % M0)];
+            Ac[e] = static_cast<C>(src[static_cast<int64_t>(e / M0) * N + (e % M0)]);
         __syncthreads();
         for (int lev = P.levels; lev > level; --lev) {
             const int Mc = N >> (lev - 1);
             syn_pass(Ac, M0, Mc, 0, hf, gf);
             syn_pass(Ac, M0, Mc, 1, hf, gf);
         }
-        ll = Ac;
+        lll = Ac;
     }
     const int cx0 = (x0 >> 1) - 2, cy0 = (y0 >> 1) - 2;
 #pragma unroll
@@ -454,21 +476,21 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
         gy += gy < 0 ? H : 0;
         while (gx >= H) gx -= H;
         while (gy >= H) gy -= H;
-        sLL[a][b] = ll[gx * H + gy];
-        sLH[a][b] = src[static_cast<int64_t>(gx) * N + H + gy];
-        sHL[a][b] = src[static_cast<int64_t>(H + gx) * N + gy];
-        sHH[a][b] = src[static_cast<int64_t>(H + gx) * N + H + gy];
+        sLL[a][b] = lll ? lll[gx * H + gy] : llg[gx * H + gy];
+        sLH[a][b] = static_cast<C>(src[static_cast<int64_t>(gx) * N + H + gy]);
+        sHL[a][b] = static_cast<C>(src[static_cast<int64_t>(H + gx) * N + gy]);
+        sHH[a][b] = static_cast<C>(src[static_cast<int64_t>(H + gx) * N + H + gy]);
     }
     __syncthreads();
     // along x: output rows 2p and 2p + 1 (x0 is even) from coarse rows p + 2 - t
 #pragma unroll
     for (int e = threadIdx.x; e < (TS / 2) * CW; e += TILE_NT) {
         const int pr = e / CW, b = e % CW;
-        Acc al0 = 0, al1 = 0, ah0 = 0, ah1 = 0;
+        C al0 = 0, al1 = 0, ah0 = 0, ah1 = 0;
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             const int k = pr + 2 - t;
-            const Acc ll_ = sLL[k][b], hl = sHL[k][b], lh = sLH[k][b], hh = sHH[k][b];
+            const C ll_ = sLL[k][b], hl = sHL[k][b], lh = sLH[k][b], hh = sHH[k][b];
             al0 += hf[2 * t] * ll_ + gf[2 * t] * hl;
             al1 += hf[2 * t + 1] * ll_ + gf[2 * t + 1] * hl;
             ah0 += hf[2 * t] * lh + gf[2 * t] * hh;
@@ -480,20 +502,20 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
         sAH[2 * pr + 1][b] = ah1;
     }
     __syncthreads();
-    // level > 1: the next finer low-pass band, FP64 scratch; level 1: pixels
-    double* dll = level > 1 ? vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level - 1] : nullptr;
-    T* dst = vptr<T>(J, out_vec, it.frame) + Ly.coff;
+    // level > 1: the next finer low-pass band (scratch); level 1: pixels
+    C* dll = level > 1 ? ll_ptr<C>(J, it.frame) + Ly.ll_off[level - 1] : nullptr;
+    S* dst = vptr<S>(J, out_vec, it.frame) + Ly.coff;
     const int ld = level > 1 ? M : N;
     // along y: output columns 2q and 2q + 1 from coarse columns q + 2 - t
 #pragma unroll
     for (int e = threadIdx.x; e < TS * (TS / 2); e += TILE_NT) {
         const int li = e / (TS / 2), q = e % (TS / 2);
         const int i = x0 + li, j = y0 + 2 * q;
-        Acc v0 = 0, v1 = 0;
+        C v0 = 0, v1 = 0;
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             const int k = q + 2 - t;
-            const Acc lo = sAL[li][k], hi = sAH[li][k];
+            const C lo = sAL[li][k], hi = sAH[li][k];
             v0 += hf[2 * t] * lo + gf[2 * t] * hi;
             v1 += hf[2 * t + 1] * lo + gf[2 * t + 1] * hi;
         }
@@ -503,25 +525,25 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
             dll[o] = v0;
             dll[o + 1] = v1;
         } else {
-            dst[o] = static_cast<T>(v0);
-            dst[o + 1] = static_cast<T>(v1);
+            dst[o] = static_cast<S>(v0);
+            dst[o + 1] = static_cast<S>(v1);
         }
     }
 }
 
 // --------------------------------------------------------- W (+ P^T, D) ----
 // One analysis level k <= k0 over a (TS/2)^2 tile of each band.  The input
-// window of (TS+4)^2 values is LL_{k-1} (scratch) or, at k = 1, the layer
-// pixels: read from memory (SRC_PIX) or gathered from the sensor node fields
-// through P^T (SRC_PT).  LL_k goes to scratch; the three detail bands go to
-// the output with, under EPI_APPLY, + alpha D_k p and a partial <p, out>.
-template <class T, int TS>
+// window of (TS+4)^2 values (S in HBM) is LL_{k-1} (scratch) or, at k = 1, the layer
+// pixels: read from memory (SRC_PIX) or summed from the adjoint footprint
+// images (SRC_PT).  LL_k goes to scratch; the three detail bands go to the
+// output (T) with, under EPI_APPLY, + alpha D_k p and an FP64 partial <p, out>.
+template <class T, class S, class C, int TS>
 __global__ void __launch_bounds__(TILE_NT)
 k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int src, int in_vec,
             int out_vec, int epi, int aux_vec) {
     constexpr int HT = TS / 2, PW = TS + 4;
-    __shared__ Acc sA[PW][PW + 1];
-    __shared__ Acc sL[PW][HT + 1], sH[PW][HT + 1];
+    __shared__ C sA[PW][PW + 1];
+    __shared__ C sL[PW][HT + 1], sH[PW][HT + 1];
     __shared__ double red[17];
     const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
@@ -531,7 +553,7 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     const int ntx = (H + HT - 1) / HT;
     const int cx0 = (it.b % ntx) * HT, cy0 = (it.b / ntx) * HT;
     const int px0 = 2 * cx0, py0 = 2 * cy0;
-    Acc hf[6], gf[6];
+    C hf[6], gf[6];
     load_filters(P, hf, gf);
     // p at this thread's first epilogue coefficients, loaded before the window
     // so that its latency overlaps the analysis
@@ -558,12 +580,12 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     if (level == 1 && src == SRC_PT) {
         // rows per thread of the PW x PW window, at most 8 per register chunk
         constexpr int RPT = (PW + TILE_NT / PW - 1) / (TILE_NT / PW);
-        pt_gather_window<T, (RPT < 8 ? RPT : 8)>(P, vptr<T>(J, in_vec, it.frame), it.a, N, px0, py0,
-                                                 PW, PW, &sA[0][0], PW + 1,
-                                                 static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a] + it.b]));
+        pt_gather_window<S, C, (RPT < 8 ? RPT : 8)>(P, vptr<S>(J, in_vec, it.frame), it.a, N, px0,
+                                                    py0, PW, PW, &sA[0][0], PW + 1,
+                                                    static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a] + it.b]));
     } else if (level > 1) {
-        // the low-pass band of the level below (FP64 scratch)
-        const double* ind = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level - 1];
+        // the low-pass band of the level below (scratch)
+        const C* ind = ll_ptr<C>(J, it.frame) + Ly.ll_off[level - 1];
 #pragma unroll
         for (int k = 0; k < WIN_IT; ++k) {
             const int e0 = threadIdx.x + k * TILE_NT, e = min(e0, PW * PW - 1);
@@ -571,11 +593,11 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
             int gx = px0 + a, gy = py0 + b;   // periodic wrap
             while (gx >= M) gx -= M;
             while (gy >= M) gy -= M;
-            const double v = ind[static_cast<int64_t>(gx) * M + gy];
+            const C v = ind[static_cast<int64_t>(gx) * M + gy];
             if (e0 < PW * PW) sA[a][b] = v;
         }
     } else {
-        const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
+        const S* in = vptr<S>(J, in_vec, it.frame) + Ly.coff;
 #pragma unroll
         for (int k = 0; k < WIN_IT; ++k) {
             const int e0 = threadIdx.x + k * TILE_NT, e = min(e0, PW * PW - 1);
@@ -583,18 +605,18 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
             int gx = px0 + a, gy = py0 + b;   // periodic wrap
             while (gx >= M) gx -= M;
             while (gy >= M) gy -= M;
-            const T v = in[static_cast<int64_t>(gx) * N + gy];
-            if (e0 < PW * PW) sA[a][b] = static_cast<Acc>(v);
+            const S v = in[static_cast<int64_t>(gx) * N + gy];
+            if (e0 < PW * PW) sA[a][b] = static_cast<C>(v);
         }
     }
     __syncthreads();
 #pragma unroll
     for (int e = threadIdx.x; e < PW * HT; e += TILE_NT) {
         const int a = e / HT, c = e % HT;
-        Acc lo = 0, hi = 0;
+        C lo = 0, hi = 0;
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
-            const Acc v = sA[a][2 * c + n];
+            const C v = sA[a][2 * c + n];
             lo += hf[n] * v;
             hi += gf[n] * v;
         }
@@ -604,8 +626,8 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     __syncthreads();
     T* out = vptr<T>(J, out_vec, it.frame) + Ly.coff;
     const T* pv = vptr<T>(J, aux_vec, it.frame) + Ly.coff;   // valid for every caller
-    const Acc aD = P.alpha * Ly.D[level - 1];
-    double* llo = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[level];
+    const C aD = static_cast<C>(P.alpha * Ly.D[level - 1]);
+    C* llo = ll_ptr<C>(J, it.frame) + Ly.ll_off[level];
     double acc = 0.0;
     constexpr int EPI_IT = (HT * HT + TILE_NT - 1) / TILE_NT;
 #pragma unroll
@@ -614,10 +636,10 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
         const int c1 = ec / HT, c2 = ec % HT;
         const int X = cx0 + c1, Y = cy0 + c2;
         const bool ok = e < HT * HT && X < H && Y < H;
-        Acc ll = 0, hl = 0, lh = 0, hh = 0;
+        C ll = 0, hl = 0, lh = 0, hh = 0;
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
-            const Acc l = sL[2 * c1 + n][c2], h = sH[2 * c1 + n][c2];
+            const C l = sL[2 * c1 + n][c2], h = sH[2 * c1 + n][c2];
             ll += hf[n] * l;
             hl += gf[n] * l;
             lh += hf[n] * h;
@@ -633,12 +655,11 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
         if (ok) {
             llo[X * H + Y] = ll;
             if (epi == EPI_APPLY) {
-                const Acc p1 = pr1, p2 = pr2, p3 = pr3;
-                const T o1 = static_cast<T>(lh + aD * p1);
-                const T o2 = static_cast<T>(hl + aD * p2);
-                const T o3 = static_cast<T>(hh + aD * p3);
-                acc += p1 * static_cast<Acc>(o1) + p2 * static_cast<Acc>(o2) +
-                       p3 * static_cast<Acc>(o3);
+                const T o1 = static_cast<T>(lh + aD * static_cast<C>(pr1));
+                const T o2 = static_cast<T>(hl + aD * static_cast<C>(pr2));
+                const T o3 = static_cast<T>(hh + aD * static_cast<C>(pr3));
+                acc += static_cast<Acc>(pr1) * static_cast<Acc>(o1) + static_cast<Acc>(pr2) * static_cast<Acc>(o2) +
+                       static_cast<Acc>(pr3) * static_cast<Acc>(o3);
                 out[iLH] = o1;
                 out[iHL] = o2;
                 out[iHH] = o3;
@@ -655,11 +676,11 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     }
 }
 
-// Levels k0+1..J of the analysis with the M0 x M0 block in LDS (FP64), then
+// Levels k0+1..J of the analysis with the M0 x M0 block in LDS (C), then
 // the epilogue over every coefficient of that block.  At k0 = 0 the block is
 // the whole layer, read (SRC_PIX) or gathered through P^T (SRC_PT).  Dynamic
-// LDS: the M0 x M0 block (FP64).
-template <class T>
+// LDS: the M0 x M0 block.
+template <class T, class S, class C>
 __global__ void __launch_bounds__(1024)
 k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int in_vec,
               int out_vec, int epi, int aux_vec) {
@@ -670,18 +691,18 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
     const LayerInfo& Ly = P.layer[it.a];
     const int N = Ly.N, k0 = Ly.k0, M0 = N >> k0;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    Acc* A = reinterpret_cast<Acc*>(smem_raw);
-    Acc hf[6], gf[6];
+    C* A = reinterpret_cast<C*>(smem_raw);
+    C hf[6], gf[6];
     load_filters(P, hf, gf);
     if (k0 > 0) {
-        const double* ll = vptr<double>(J, V_LL, it.frame) + Ly.ll_off[k0];
+        const C* ll = ll_ptr<C>(J, it.frame) + Ly.ll_off[k0];
         for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = ll[e];
     } else if (src == SRC_PIX) {
-        const T* in = vptr<T>(J, in_vec, it.frame) + Ly.coff;
-        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = in[e];
+        const S* in = vptr<S>(J, in_vec, it.frame) + Ly.coff;
+        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) A[e] = static_cast<C>(in[e]);
     } else {
-        pt_gather_window<T, 4>(P, vptr<T>(J, in_vec, it.frame), it.a, N, 0, 0, N, N, A, N,
-                            static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a]]));
+        pt_gather_window<S, C, 4>(P, vptr<S>(J, in_vec, it.frame), it.a, N, 0, 0, N, N, A, N,
+                                  static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a]]));
     }
     __syncthreads();
     for (int lev = k0 + 1; lev <= P.levels; ++lev) {
@@ -695,12 +716,12 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
     for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x) {
         const int x = e / M0, y = e % M0;
         const int64_t gi = static_cast<int64_t>(x) * N + y;
-        Acc v = A[e];
+        const C v = A[e];
         if (epi == EPI_APPLY) {
             const int k = max(level_of(x, y, N, P.levels), 1);
-            const Acc p = pv[gi];
-            const T o = static_cast<T>(v + P.alpha * Ly.D[k - 1] * p);
-            acc += p * static_cast<Acc>(o);
+            const T p = pv[gi];
+            const T o = static_cast<T>(v + static_cast<C>(P.alpha * Ly.D[k - 1]) * static_cast<C>(p));
+            acc += static_cast<Acc>(p) * static_cast<Acc>(o);
             out[gi] = o;
         } else {
             out[gi] = static_cast<T>(v);
@@ -728,7 +749,7 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
 // Fried differences do not cancel single-precision digits.
 constexpr int PROJ_LB = 9;   // layers whose samples a thread loads together
 
-template <class T>
+template <class T, class S>
 __global__ void __launch_bounds__(512)
 k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int sums) {
     __shared__ double su[(PROJ_ROWS + 1) * (WM_NSUB_MAX + 1)];
@@ -765,19 +786,19 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
                          csw[l][k - rows_c]);
     }
     __syncthreads();
-    const T* phi = vptr<T>(J, in_vec, it.frame);
+    const S* phi = vptr<S>(J, in_vec, it.frame);
     double* u = vptr<double>(J, V_U, it.frame) + w.node_off;
     for (int e = threadIdx.x; e < rows_c * nn; e += blockDim.x) {
         const int li = e / nn, j = e - (e / nn) * nn;
         Acc acc = 0;
         // PROJ_LB layers per step: their samples are loaded before any is used
         for (int l0 = 0; l0 < L; l0 += PROJ_LB) {
-            T v[PROJ_LB][4];
+            S v[PROJ_LB][4];
 #pragma unroll
             for (int k = 0; k < PROJ_LB; ++k) {
                 const int l = min(l0 + k, L - 1);   // past the last layer: a valid load, unused
                 const int N = lay_n[l];
-                const T* f = phi + lay_off[l] + static_cast<int64_t>(ri0[l][li]) * N + cj0[l][j];
+                const S* f = phi + lay_off[l] + static_cast<int64_t>(ri0[l][li]) * N + cj0[l][j];
                 v[k][0] = f[0];
                 v[k][1] = f[1];
                 v[k][2] = f[N];
@@ -860,7 +881,7 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
 //           sensors; mu = nu = 0 otherwise)
 //   cells:  cell slopes = cell sums / cell counts, then the same with per-cell
 //           blocks, divided by the cell count for the fine subapertures.
-template <class T>
+template <class T, class SO>
 __global__ void __launch_bounds__(256)
 k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     // su, swx, swy: dynamic LDS of weights_lds_bytes(nn, ns) for this sensor
@@ -880,12 +901,12 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     double* swx = su + (PROJ_ROWS + 2) * nn;
     double* swy = swx + (PROJ_ROWS + 1) * ns;
     const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
-    T* vout = vptr<T>(J, out_vec, it.frame) + w.node_off;
+    SO* vout = vptr<SO>(J, out_vec, it.frame) + w.node_off;
     if (w.kind == 1) {
         for (int e = threadIdx.x; e < rows * nn; e += blockDim.x) {
             const int node = r0 * nn + e;
             const int q = w.maskmap[node];
-            vout[node] = static_cast<T>(q >= 0 ? w.blocks[3 * q] * ug[node] : 0.0);
+            vout[node] = static_cast<SO>(q >= 0 ? w.blocks[3 * q] * ug[node] : 0.0);
         }
         return;
     }
@@ -995,7 +1016,7 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
         if (a < ns && b < ns) v -= swx[dn + b] + swy[dn + b];
         if (a >= 1 && b >= 1) v += swx[up + b - 1] + swy[up + b - 1];
         if (a < ns && b >= 1) v += swy[dn + b - 1] - swx[dn + b - 1];
-        vout[a * nn + b] = static_cast<T>(0.5 * v);
+        vout[a * nn + b] = static_cast<SO>(0.5 * v);
     }
 }
 
@@ -1009,7 +1030,9 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
 // column is fed by at most TAPS consecutive nodes on the fast path; TAPS (2
 // to 4) is the largest count the plans of the launch need (3 for node spacings
 // from 2/3 of a pixel up), and any row or column fed by more takes the general
-// loop.  LDS: the staged node rows (storage type) and T, sized by the plan.
+// loop.  LDS: the staged node rows and T (both C), sized by the plan.  The tap
+// weights are formed in FP64 (the same stencil as the forward projection) and
+// rounded to C; the images are stored in S.
 
 __device__ __forceinline__ Acc adj_weight(double pa, double pb, int i, int N, int g) {
     int i0;
@@ -1018,11 +1041,11 @@ __device__ __forceinline__ Acc adj_weight(double pa, double pb, int i, int N, in
     return i0 == g ? 1.0 - t : (i0 + 1 == g ? t : 0.0);
 }
 
-template <class T, int TAPS>
+template <class T, class S, class C, int TAPS>
 __global__ void __launch_bounds__(256)
 k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int out_vec) {
     static_assert(TAPS <= ADJ_TAPS_MAX, "adjoint taps");
-    __shared__ double wrow[TAPS][ADJ_BAND];
+    __shared__ C wrow[TAPS][ADJ_BAND];
     __shared__ int frow[ADJ_BAND], fofs[ADJ_BAND], crow[ADJ_BAND];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Item it = items[xcd_item()];
@@ -1037,30 +1060,30 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
     const int* rt = P.fp_rc + 2 * P.fp_tab[m][l];
     const int* ct = rt + 2 * Hf;
     const int alo = ct[2 * Wf + 2 * it.slot], ahi = ct[2 * Wf + 2 * it.slot + 1];
-    T* out = vptr<T>(J, out_vec, it.frame) + P.fp_off[m][l] + r0 * Wf;
+    S* out = vptr<S>(J, out_vec, it.frame) + P.fp_off[m][l] + r0 * Wf;
     if (ahi < alo) {
-        for (int e = threadIdx.x; e < BR * Wf; e += blockDim.x) out[e] = T(0);
+        for (int e = threadIdx.x; e < BR * Wf; e += blockDim.x) out[e] = S(0);
         return;
     }
     // the staged rows are followed by TAPS - 1 rows of zeros, so the fast
     // path reads rows f .. f + TAPS - 1 without clamping
     const int NR = ahi - alo + 1, NRP = NR + TAPS - 1;
-    T* Vs = reinterpret_cast<T*>(smem_raw);
-    Acc* Tb = reinterpret_cast<Acc*>(smem_raw + ((static_cast<size_t>(NRP) * nn * sizeof(T) + 15) & ~size_t(15)));
-    const T* V = vptr<T>(J, in_vec, it.frame) + P.wfs[m].node_off + static_cast<int64_t>(alo) * nn;
+    C* Vs = reinterpret_cast<C*>(smem_raw);
+    C* Tb = reinterpret_cast<C*>(smem_raw + ((static_cast<size_t>(NRP) * nn * sizeof(C) + 15) & ~size_t(15)));
+    const S* V = vptr<S>(J, in_vec, it.frame) + P.wfs[m].node_off + static_cast<int64_t>(alo) * nn;
     {
         // ADJ_PF loads in flight per thread: clamped addresses, predicated stores
         constexpr int ADJ_PF = 8;
         const int tot = NR * nn, bd0 = blockDim.x;
         for (int e0 = threadIdx.x; e0 < tot; e0 += ADJ_PF * bd0) {
-            T v[ADJ_PF];
+            S v[ADJ_PF];
 #pragma unroll
             for (int j = 0; j < ADJ_PF; ++j) v[j] = V[min(e0 + j * bd0, tot - 1)];
 #pragma unroll
             for (int j = 0; j < ADJ_PF; ++j)
-                if (e0 + j * bd0 < tot) Vs[e0 + j * bd0] = v[j];
+                if (e0 + j * bd0 < tot) Vs[e0 + j * bd0] = static_cast<C>(v[j]);
         }
-        for (int e = tot + threadIdx.x; e < NRP * nn; e += bd0) Vs[e] = T(0);
+        for (int e = tot + threadIdx.x; e < NRP * nn; e += bd0) Vs[e] = C(0);
     }
     // row taps of the band: first staged row, count, weights
     if (threadIdx.x < BR) {
@@ -1071,7 +1094,7 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
         crow[threadIdx.x] = cnt;
 #pragma unroll
         for (int q = 0; q < TAPS; ++q)
-            wrow[q][threadIdx.x] = q < cnt ? adj_weight(pa, pbx, f + q, N, x0 + r) : 0.0;
+            wrow[q][threadIdx.x] = static_cast<C>(q < cnt ? adj_weight(pa, pbx, f + q, N, x0 + r) : 0.0);
     }
     __syncthreads();
     const int bd = blockDim.x;
@@ -1083,15 +1106,15 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
             for (int b = b0; b < nn; b += bstep)
                 for (int lr = g1; lr < BR; lr += G1) {
                     const int cnt = crow[lr];
-                    const T* vc = Vs + fofs[lr] + b;
-                    Acc acc = 0;
+                    const C* vc = Vs + fofs[lr] + b;
+                    C acc = 0;
                     if (cnt <= TAPS) {
 #pragma unroll
-                        for (int q = 0; q < TAPS; ++q) acc += wrow[q][lr] * static_cast<Acc>(vc[q * nn]);
+                        for (int q = 0; q < TAPS; ++q) acc += wrow[q][lr] * vc[q * nn];
                     } else {
                         const int r = r0 + lr, f = frow[lr];
                         for (int q = 0; q < cnt; ++q)
-                            acc += adj_weight(pa, pbx, alo + f + q, N, x0 + r) * static_cast<Acc>(vc[q * nn]);
+                            acc += static_cast<C>(adj_weight(pa, pbx, alo + f + q, N, x0 + r)) * vc[q * nn];
                     }
                     Tb[lr * nn + b] = acc;
                 }
@@ -1104,26 +1127,26 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
     for (int c = c0; c < Wf; c += cstep) {
         const int f = ct[2 * c], cnt = ct[2 * c + 1], gy = y0 + c;
         if (cnt <= TAPS) {
-            Acc w[TAPS];
+            C w[TAPS];
             int ix[TAPS];
 #pragma unroll
             for (int q = 0; q < TAPS; ++q) {
-                w[q] = q < cnt ? adj_weight(pa, pby, f + q, N, gy) : 0.0;
+                w[q] = static_cast<C>(q < cnt ? adj_weight(pa, pby, f + q, N, gy) : 0.0);
                 ix[q] = min(f + q, nn - 1);
             }
             for (int lr = g2; lr < BR; lr += G2) {
-                const Acc* tr = Tb + lr * nn;
-                Acc acc = 0;
+                const C* tr = Tb + lr * nn;
+                C acc = 0;
 #pragma unroll
                 for (int q = 0; q < TAPS; ++q) acc += w[q] * tr[ix[q]];
-                out[lr * Wf + c] = static_cast<T>(acc);
+                out[lr * Wf + c] = static_cast<S>(acc);
             }
         } else {
             for (int lr = g2; lr < BR; lr += G2) {
-                const Acc* tr = Tb + lr * nn;
-                Acc acc = 0;
-                for (int q = 0; q < cnt; ++q) acc += adj_weight(pa, pby, f + q, N, gy) * tr[f + q];
-                out[lr * Wf + c] = static_cast<T>(acc);
+                const C* tr = Tb + lr * nn;
+                C acc = 0;
+                for (int q = 0; q < cnt; ++q) acc += static_cast<C>(adj_weight(pa, pby, f + q, N, gy)) * tr[f + q];
+                out[lr * Wf + c] = static_cast<S>(acc);
             }
         }
     }
@@ -1137,7 +1160,7 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
 // SM_FWD:   node field u -> raw slopes to the output.
 // One block of 1024 threads per (frame, sensor); the node field and the
 // weighted-slope grids live in LDS in FP64; QM elements per thread.
-template <class T, int QM>
+template <class T, class SO, int QM>
 __global__ void __launch_bounds__(1024)
 k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_vec, int out_vec) {
     __shared__ double red[17];
@@ -1186,8 +1209,8 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
             if (q < S) U[w.act[q]] = w.blocks[3 * q] * sx[r];
         }
         __syncthreads();
-        T* vout = vptr<T>(J, out_vec, it.frame) + w.node_off;
-        for (int e = tid; e < nn * nn; e += bd) vout[e] = static_cast<T>(U[e]);
+        SO* vout = vptr<SO>(J, out_vec, it.frame) + w.node_off;
+        for (int e = tid; e < nn * nn; e += bd) vout[e] = static_cast<SO>(U[e]);
         return;
     }
 
@@ -1358,7 +1381,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
         if (q < Sf) U[w.act[q]] = sy[r];
     }
     __syncthreads();
-    T* vout = vptr<T>(J, out_vec, it.frame) + w.node_off;
+    SO* vout = vptr<SO>(J, out_vec, it.frame) + w.node_off;
 #pragma unroll
     for (int r = 0; r < QM; ++r) {
         const int e = tid + r * bd;
@@ -1369,7 +1392,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
             if (a < ns && b < ns) v -= U[a * ns + b];
             if (a >= 1 && b >= 1) v += U[(a - 1) * ns + b - 1];
             if (a >= 1 && b < ns) v -= U[(a - 1) * ns + b];
-            vout[e] = static_cast<T>(0.5 * v);
+            vout[e] = static_cast<SO>(0.5 * v);
         }
     }
 }
@@ -1824,88 +1847,88 @@ void launch_axpby(int64_t n, double a, const T* x, double b, const T* y, T* out,
                        n, a, x, b, y, out);
 }
 
-template <class T>
-__global__ void k_cast_from_double(const double* in, T* out, int64_t n) {
+template <class S, class D>
+__global__ void k_cast(const S* in, D* out, int64_t n) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = static_cast<T>(in[i]);
+    if (i < n) out[i] = static_cast<D>(in[i]);
 }
 
 // -------------------------------------------------------------- launchers ----
-template <class T>
+template <class T, class S, class C>
 void launch_idwt_coarse(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
                         int lds_bytes, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_idwt_coarse<T>, dim3(n), dim3(1024), lds_bytes, s, a, items, in_vec,
+    hipLaunchKernelGGL((k_idwt_coarse<T, S, C>), dim3(n), dim3(1024), lds_bytes, s, a, items, in_vec,
                        out_vec);
 }
 
-template <class T>
+template <class T, class S, class C>
 void launch_idwt_tile(const JobArgs& a, const Item* items, int n, int level, int in_vec,
                       int out_vec, int tile, int lds_bytes, hipStream_t s) {
     if (n <= 0) return;
     if (tile == 16)
-        hipLaunchKernelGGL((k_idwt_tile<T, 16>), dim3(n), dim3(TILE_NT), lds_bytes, s, a, items, level, in_vec, out_vec);
+        hipLaunchKernelGGL((k_idwt_tile<T, S, C, 16>), dim3(n), dim3(TILE_NT), lds_bytes, s, a, items, level, in_vec, out_vec);
     else if (tile == 64)
-        hipLaunchKernelGGL((k_idwt_tile<T, 64>), dim3(n), dim3(TILE_NT), lds_bytes, s, a, items, level, in_vec, out_vec);
+        hipLaunchKernelGGL((k_idwt_tile<T, S, C, 64>), dim3(n), dim3(TILE_NT), lds_bytes, s, a, items, level, in_vec, out_vec);
     else
-        hipLaunchKernelGGL((k_idwt_tile<T, 32>), dim3(n), dim3(TILE_NT), lds_bytes, s, a, items, level, in_vec, out_vec);
+        hipLaunchKernelGGL((k_idwt_tile<T, S, C, 32>), dim3(n), dim3(TILE_NT), lds_bytes, s, a, items, level, in_vec, out_vec);
 }
 
-template <class T>
+template <class T, class S, class C>
 void launch_fdwt_tile(const JobArgs& a, const Item* items, int n, int level, int src, int in_vec,
                       int out_vec, int epi, int aux_vec, int tile, hipStream_t s) {
     if (n <= 0) return;
     if (tile == 16)
-        hipLaunchKernelGGL((k_fdwt_tile<T, 16>), dim3(n), dim3(TILE_NT), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
+        hipLaunchKernelGGL((k_fdwt_tile<T, S, C, 16>), dim3(n), dim3(TILE_NT), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
     else if (tile == 64)
-        hipLaunchKernelGGL((k_fdwt_tile<T, 64>), dim3(n), dim3(TILE_NT), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
+        hipLaunchKernelGGL((k_fdwt_tile<T, S, C, 64>), dim3(n), dim3(TILE_NT), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
     else
-        hipLaunchKernelGGL((k_fdwt_tile<T, 32>), dim3(n), dim3(TILE_NT), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
+        hipLaunchKernelGGL((k_fdwt_tile<T, S, C, 32>), dim3(n), dim3(TILE_NT), 0, s, a, items, level, src, in_vec, out_vec, epi, aux_vec);
 }
 
-template <class T>
+template <class T, class S, class C>
 void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int in_vec,
                         int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_fdwt_coarse<T>, dim3(n), dim3(1024), lds_bytes, s, a, items, src, in_vec,
+    hipLaunchKernelGGL((k_fdwt_coarse<T, S, C>), dim3(n), dim3(1024), lds_bytes, s, a, items, src, in_vec,
                        out_vec, epi, aux_vec);
 }
 
-template <class T>
+template <class T, class S>
 void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(512), 0, s, a, items, in_vec, sums);
+    hipLaunchKernelGGL((k_project<T, S>), dim3(n), dim3(512), 0, s, a, items, in_vec, sums);
 }
 
-template <class T>
+template <class T, class S>
 void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, int lds_bytes,
                     hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_weights<T>, dim3(n), dim3(256), lds_bytes, s, a, items, out_vec);
+    hipLaunchKernelGGL((k_weights<T, S>), dim3(n), dim3(256), lds_bytes, s, a, items, out_vec);
 }
 
-template <class T>
+template <class T, class S, class C>
 void launch_adjoint(const JobArgs& a, const Item* items, int n, int in_vec, int out_vec,
                     int lds_bytes, int taps, hipStream_t s) {
     if (n <= 0) return;
     if (taps <= 2)
-        hipLaunchKernelGGL((k_adjoint<T, 2>), dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
+        hipLaunchKernelGGL((k_adjoint<T, S, C, 2>), dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
     else if (taps == 3)
-        hipLaunchKernelGGL((k_adjoint<T, 3>), dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
+        hipLaunchKernelGGL((k_adjoint<T, S, C, 3>), dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
     else
-        hipLaunchKernelGGL((k_adjoint<T, 4>), dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
+        hipLaunchKernelGGL((k_adjoint<T, S, C, 4>), dim3(n), dim3(256), lds_bytes, s, a, items, in_vec, out_vec);
 }
 
-template <class T>
+template <class T, class S>
 void launch_sensor(const JobArgs& a, const Item* items, int n, int mode, int in_vec, int out_vec,
                    int lds_bytes, hipStream_t s) {
     if (n <= 0) return;
     // lds_bytes carries the node-field size; elements per thread follow from it
     const int elems = lds_bytes / static_cast<int>(sizeof(Acc));
     if (elems <= 8 * 1024)
-        hipLaunchKernelGGL((k_sensor<T, 8>), dim3(n), dim3(1024), lds_bytes, s, a, items, mode, in_vec, out_vec);
+        hipLaunchKernelGGL((k_sensor<T, S, 8>), dim3(n), dim3(1024), lds_bytes, s, a, items, mode, in_vec, out_vec);
     else
-        hipLaunchKernelGGL((k_sensor<T, 16>), dim3(n), dim3(1024), lds_bytes, s, a, items, mode, in_vec, out_vec);
+        hipLaunchKernelGGL((k_sensor<T, S, 16>), dim3(n), dim3(1024), lds_bytes, s, a, items, mode, in_vec, out_vec);
 }
 
 template <class T>
@@ -1940,10 +1963,11 @@ void launch_jacobi(const PlanDev* P, const double* protos, const int* proto_off,
     hipLaunchKernelGGL(k_jacobi, dim3(nb), dim3(128), 0, s, P, ja, n, out);
 }
 
-template <class T>
-void launch_cast_from_double(const double* in, T* out, int64_t n, hipStream_t s) {
+template <class S, class D>
+void launch_cast(const S* in, D* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
     const int nb = static_cast<int>((n + 255) / 256);
-    hipLaunchKernelGGL(k_cast_from_double<T>, dim3(nb), dim3(256), 0, s, in, out, n);
+    hipLaunchKernelGGL((k_cast<S, D>), dim3(nb), dim3(256), 0, s, in, out, n);
 }
 
 // Let the whole-band kernels use up to the 160 KB of LDS of a CDNA4 compute
@@ -1959,46 +1983,66 @@ static void allow_full_lds(K* k) {
     (void)hipGetLastError();
 }
 
-void configure_kernels() {
-    allow_full_lds(&k_idwt_coarse<float>);
-    allow_full_lds(&k_idwt_coarse<double>);
-    allow_full_lds(&k_idwt_tile<float, 16>);
-    allow_full_lds(&k_idwt_tile<float, 32>);
-    allow_full_lds(&k_idwt_tile<float, 64>);
-    allow_full_lds(&k_idwt_tile<double, 16>);
-    allow_full_lds(&k_idwt_tile<double, 32>);
-    allow_full_lds(&k_idwt_tile<double, 64>);
-    allow_full_lds(&k_fdwt_coarse<float>);
-    allow_full_lds(&k_fdwt_coarse<double>);
-    allow_full_lds(&k_adjoint<float, 2>);
-    allow_full_lds(&k_adjoint<float, 3>);
-    allow_full_lds(&k_adjoint<float, 4>);
-    allow_full_lds(&k_adjoint<double, 2>);
-    allow_full_lds(&k_adjoint<double, 3>);
-    allow_full_lds(&k_adjoint<double, 4>);
-    allow_full_lds(&k_sensor<float, 8>);
-    allow_full_lds(&k_sensor<float, 16>);
-    allow_full_lds(&k_sensor<double, 8>);
-    allow_full_lds(&k_sensor<double, 16>);
+template <class T, class S, class C>
+static void allow_full_lds_ops() {
+    allow_full_lds(&k_idwt_coarse<T, S, C>);
+    allow_full_lds(&k_idwt_tile<T, S, C, 16>);
+    allow_full_lds(&k_idwt_tile<T, S, C, 32>);
+    allow_full_lds(&k_idwt_tile<T, S, C, 64>);
+    allow_full_lds(&k_fdwt_coarse<T, S, C>);
+    allow_full_lds(&k_adjoint<T, S, C, 2>);
+    allow_full_lds(&k_adjoint<T, S, C, 3>);
+    allow_full_lds(&k_adjoint<T, S, C, 4>);
 }
 
-#define WM_INSTANTIATE(T)                                                                       \
-    template void launch_idwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, hipStream_t); \
-    template void launch_idwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, int, hipStream_t); \
-    template void launch_fdwt_tile<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, int, hipStream_t); \
-    template void launch_fdwt_coarse<T>(const JobArgs&, const Item*, int, int, int, int, int, int, int, hipStream_t); \
-    template void launch_sensor<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
-    template void launch_project<T>(const JobArgs&, const Item*, int, int, int, hipStream_t);  \
-    template void launch_weights<T>(const JobArgs&, const Item*, int, int, int, hipStream_t);       \
-    template void launch_adjoint<T>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
-    template void launch_init<T>(const JobArgs&, const Item*, int, int, hipStream_t);          \
-    template void launch_update_r<T>(const JobArgs&, const Item*, int, int, int, hipStream_t); \
-    template void launch_update_p<T>(const JobArgs&, const Item*, int, int, hipStream_t);      \
-    template void launch_replace_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);     \
-    template void launch_cast_from_double<T>(const double*, T*, int64_t, hipStream_t);         \
+void configure_kernels() {
+    allow_full_lds_ops<float, float, float>();
+    allow_full_lds_ops<float, float, double>();
+    allow_full_lds_ops<float, double, double>();
+    allow_full_lds_ops<double, double, double>();
+    allow_full_lds(&k_sensor<float, float, 8>);
+    allow_full_lds(&k_sensor<float, float, 16>);
+    allow_full_lds(&k_sensor<float, double, 8>);
+    allow_full_lds(&k_sensor<float, double, 16>);
+    allow_full_lds(&k_sensor<double, double, 8>);
+    allow_full_lds(&k_sensor<double, double, 16>);
+}
+
+// Wavelet and adjoint-projection stages: vector storage T, operator storage S,
+// arithmetic C.
+#define WM_INSTANTIATE_STAGES(T, S, C)                                                             \
+    template void launch_idwt_coarse<T, S, C>(const JobArgs&, const Item*, int, int, int, int, hipStream_t); \
+    template void launch_idwt_tile<T, S, C>(const JobArgs&, const Item*, int, int, int, int, int, int, hipStream_t); \
+    template void launch_fdwt_tile<T, S, C>(const JobArgs&, const Item*, int, int, int, int, int, int, int, int, hipStream_t); \
+    template void launch_fdwt_coarse<T, S, C>(const JobArgs&, const Item*, int, int, int, int, int, int, int, hipStream_t); \
+    template void launch_adjoint<T, S, C>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t);
+
+// Projection and sensor stages (FP64 arithmetic): vector storage T, operator storage S.
+#define WM_INSTANTIATE_SENSORS(T, S)                                                               \
+    template void launch_sensor<T, S>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
+    template void launch_project<T, S>(const JobArgs&, const Item*, int, int, int, hipStream_t);  \
+    template void launch_weights<T, S>(const JobArgs&, const Item*, int, int, int, hipStream_t);
+
+// The PCG vector steps: storage T.
+#define WM_INSTANTIATE_VEC(T)                                                                      \
+    template void launch_init<T>(const JobArgs&, const Item*, int, int, hipStream_t);             \
+    template void launch_update_r<T>(const JobArgs&, const Item*, int, int, int, hipStream_t);    \
+    template void launch_update_p<T>(const JobArgs&, const Item*, int, int, hipStream_t);         \
+    template void launch_replace_r<T>(const JobArgs&, const Item*, int, int, hipStream_t);        \
     template void launch_axpby<T>(int64_t, double, const T*, double, const T*, T*, hipStream_t);
 
-WM_INSTANTIATE(float)
-WM_INSTANTIATE(double)
+WM_INSTANTIATE_STAGES(float, float, float)
+WM_INSTANTIATE_STAGES(float, float, double)
+WM_INSTANTIATE_STAGES(float, double, double)
+WM_INSTANTIATE_STAGES(double, double, double)
+WM_INSTANTIATE_SENSORS(float, float)
+WM_INSTANTIATE_SENSORS(float, double)
+WM_INSTANTIATE_SENSORS(double, double)
+WM_INSTANTIATE_VEC(float)
+WM_INSTANTIATE_VEC(double)
+template void launch_cast<double, float>(const double*, float*, int64_t, hipStream_t);
+template void launch_cast<float, double>(const float*, double*, int64_t, hipStream_t);
+template void launch_cast<float, float>(const float*, float*, int64_t, hipStream_t);
+template void launch_cast<double, double>(const double*, double*, int64_t, hipStream_t);
 
 }  // namespace wm

@@ -45,13 +45,17 @@ struct DevBuf {
 };
 
 struct Sched {
-    // Item lists per stage, on the device.
-    std::unique_ptr<DevBuf> buf;
+    // Item lists per stage, on the device (shared by the frame-prefix views
+    // of the allocation-free solve).
+    std::shared_ptr<DevBuf> buf;
+    int frames = 0;                     // frames of a single-plan schedule
     const Item* coarse = nullptr;       // every layer (analysis)
     int n_coarse = 0;
     const Item* coarse_syn = nullptr;   // layers whose synthesis tiles do not rebuild LL_k0
     int n_coarse_syn = 0;
-    int lds_idwt_lvl[WM_MAXLEV + 1] = {};   // dynamic LDS of the level-k synthesis tiles
+    // dynamic LDS sizes, [0] for FP32 and [1] for FP64 arithmetic (LDS tiles
+    // follow the arithmetic type)
+    int lds_idwt_lvl[2][WM_MAXLEV + 1] = {};   // the level-k synthesis tiles
     const Item* tiled[WM_MAXLEV + 1] = {};
     int n_tiled[WM_MAXLEV + 1] = {};
     const Item* sensor = nullptr;
@@ -60,13 +64,13 @@ struct Sched {
     int n_proj = 0;
     const Item* adj = nullptr;
     int n_adj = 0;
-    int lds_adj = 0;
+    int lds_adj[2] = {};
     int adj_taps = 2;      // fast-path taps of the adjoint (largest over the plans)
     const Item* vec = nullptr;
     int n_vec = 0;
     int maxk0 = 0;
-    int lds_idwt = 0;      // dynamic LDS of the whole-band synthesis
-    int lds_fdwt = 0;      // dynamic LDS of the whole-band analysis (+ gather tables)
+    int lds_idwt[2] = {};  // the whole-band synthesis
+    int lds_fdwt[2] = {};  // the whole-band analysis
     int lds_sensor = 0;
     int lds_weights = 0;   // dynamic LDS of k_weights
     int tile = 32;
@@ -133,7 +137,9 @@ struct ProfScope {
 struct wmcao_plan_s {
     int device = 0;
     wmcao_dtype dtype = WMCAO_F64;
-    size_t esz = 8;
+    size_t esz = 8;       // bytes of a PCG vector element (T)
+    int op64 = 1;         // operator type F: 1 double, 0 float
+    size_t osz = 8;       // bytes of an operator element (F)
     int L = 0, W = 0, levels = 0;
     int max_batch = 1;
     int tile = 32;
@@ -160,15 +166,18 @@ struct wmcao_plan_s {
     int64_t n_fp = 0;   // layer pixels some sensor node's bilinear stencil touches
     int64_t n_fpimg = 0;  // values of the adjoint footprint images of one frame
     int64_t n_spart = 0;  // doubles of the per-band slope sums of one frame
-    int lds_adjoint = 0;  // row-pass buffer of the adjoint kernel
+    int lds_adjoint[2] = {};  // staged rows + row-pass buffer of the adjoint, FP32 / FP64 arithmetic
+    int c64 = 7;              // stages computing in FP64 (C_IDWT | C_ADJ | C_FDWT)
     int adj_taps = 2;     // most nodes feeding one footprint row or column (2 to 4)
     std::vector<int64_t> layer_off, slope_off;
     std::map<std::pair<int, int>, std::unique_ptr<Sched>> sched;   // by (first frame, frames)
     int streams = 2;                 // 2: solves of >= SPLIT_MIN frames run as two halves
     hipStream_t side = nullptr;      // stream of the second half
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    // captured graph of one wmcao_solve_graph argument set
+    // captured graph of one wmcao_solve_graph argument set, and the event
+    // recorded after its latest replay
     hipGraphExec_t gexec = nullptr;
+    hipEvent_t gdone = nullptr;
     std::tuple<const void*, void*, int, int, int, double*, int*, void*> gkey{};
     std::mutex mu;
     Profiler prof;
@@ -262,9 +271,9 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // (the consumer sums L totals); the vector passes use one slot per chunk.
 int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj;
-    int lds_lvl[WM_MAXLEV + 1] = {};
+    int lds_lvl[2][WM_MAXLEV + 1] = {};
     std::vector<Item> tiled[WM_MAXLEV + 1];
-    int maxk0 = 0, lds_i = 0, lds_f = 0, lds_s = 0, lds_a = 0, lds_w = 0, taps_a = 2;
+    int maxk0 = 0, lds_i[2] = {}, lds_f[2] = {}, lds_s = 0, lds_a[2] = {}, lds_w = 0, taps_a = 2;
     for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
         const wmcao_plan_s* P = jobs[jp].plan;
         for (int f = jobs[jp].first; f < jobs[jp].first + jobs[jp].count; ++f) {
@@ -287,11 +296,13 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                 coarse.push_back(Item{jp, f, l, 0, tile_slots + l, first[l], cnt[l], 0});
                 const LayerInfo& Ly = P->host.layer[l];
                 if (!Ly.fuse) coarse_syn.push_back(coarse.back());
-                if (Ly.fuse)
-                    lds_lvl[Ly.k0] = std::max(lds_lvl[Ly.k0], (Ly.N >> Ly.k0) * (Ly.N >> Ly.k0) * 8);
                 const int N = Ly.N, M0 = N >> Ly.k0;
-                lds_i = std::max(lds_i, M0 * M0 * 8);
-                lds_f = std::max(lds_f, M0 * M0 * 8);
+                for (int c = 0; c < 2; ++c) {
+                    const int esz_c = c ? 8 : 4;
+                    if (Ly.fuse) lds_lvl[c][Ly.k0] = std::max(lds_lvl[c][Ly.k0], M0 * M0 * esz_c);
+                    lds_i[c] = std::max(lds_i[c], M0 * M0 * esz_c);
+                    lds_f[c] = std::max(lds_f[c], M0 * M0 * esz_c);
+                }
             }
             for (int m = 0; m < P->W; ++m)
                 for (int l = 0; l < P->L; ++l) {
@@ -299,7 +310,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                     const int nb = br > 0 ? ceil_div(P->host.fp_h[m][l], br) : 0;
                     for (int b = 0; b < nb; ++b) adj.push_back(Item{jp, f, m, l, b, 0, 0, 0});
                 }
-            lds_a = std::max(lds_a, P->lds_adjoint);
+            for (int c = 0; c < 2; ++c) lds_a[c] = std::max(lds_a[c], P->lds_adjoint[c]);
             taps_a = std::max(taps_a, P->adj_taps);
             for (int m = 0; m < P->W; ++m) {
                 sensor.push_back(Item{jp, f, m, 0, 0, 0, 0, 0});
@@ -312,38 +323,42 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
             const int nch = static_cast<int>((P->n + VEC_CHUNK - 1) / VEC_CHUNK);
             for (int c = 0; c < nch; ++c) vec.push_back(Item{jp, f, 0, c, c, 0, 0, 0});
         }
-        // algorithmic bytes (see the kernel table in the design notes)
+        // bytes each launch reads and writes as designed (see the kernel table
+        // in the design notes): e per PCG vector element, o per operator element
         const double e = static_cast<double>(P->esz) * jobs[jp].count;
+        const double o = static_cast<double>(P->osz) * jobs[jp].count;
         const double Q = static_cast<double>(P->n_nodes), n = static_cast<double>(P->n);
         bool gathers_tile = false, gathers_coarse = false;
-        const double c8 = 8.0 * jobs[jp].count;     // low-pass scratch bands are FP64
+        // low-pass scratch bands in each stage's arithmetic type
+        const double c8i = ((P->c64 & 1) ? 8.0 : 4.0) * jobs[jp].count;
+        const double c8f = ((P->c64 & 4) ? 8.0 : 4.0) * jobs[jp].count;
         for (int l = 0; l < P->L; ++l) {
             const LayerInfo& Ly = P->host.layer[l];
             const double M0 = Ly.N >> Ly.k0, B0 = M0 * M0;
             if (Ly.fuse)   // the level-k0 tiles read the coarse block instead of LL_k0
-                S->b_idwt_tile[Ly.k0] += B0 * e - B0 * c8;
+                S->b_idwt_tile[Ly.k0] += B0 * e - B0 * c8i;
             else
-                S->b_idwt_coarse += B0 * e + B0 * (Ly.k0 ? c8 : e);
-            for (int a = 0; a < 2; ++a) S->b_fdwt_coarse[a] += (Ly.k0 ? B0 * c8 : 0) + B0 * e + (a ? B0 * e : 0);
+                S->b_idwt_coarse += B0 * e + B0 * (Ly.k0 ? c8i : o);
+            for (int a = 0; a < 2; ++a) S->b_fdwt_coarse[a] += (Ly.k0 ? B0 * c8f : 0) + B0 * e + (a ? B0 * e : 0);
             gathers_coarse = gathers_coarse || Ly.k0 == 0;
             for (int k = 1; k <= Ly.k0; ++k) {
                 const double M = Ly.N >> (k - 1), Hq = (M / 2) * (M / 2);
-                S->b_idwt_tile[k] += Hq * c8 + 3 * Hq * e + M * M * (k > 1 ? c8 : e);
+                S->b_idwt_tile[k] += Hq * c8i + 3 * Hq * e + M * M * (k > 1 ? c8i : o);
                 for (int a = 0; a < 2; ++a)
-                    S->b_fdwt_tile[a][k] += (k > 1 ? M * M * c8 : 0) + Hq * c8 + 3 * Hq * e + (a ? 3 * Hq * e : 0);
+                    S->b_fdwt_tile[a][k] += (k > 1 ? M * M * c8f : 0) + Hq * c8f + 3 * Hq * e + (a ? 3 * Hq * e : 0);
                 gathers_tile = gathers_tile || k == 1;
             }
         }
         const double F = static_cast<double>(P->n_fpimg);
         for (int a = 0; a < 2; ++a) {
-            if (gathers_tile) S->b_fdwt_tile[a][1] += F * e;
-            if (gathers_coarse) S->b_fdwt_coarse[a] += F * e;
+            if (gathers_tile) S->b_fdwt_tile[a][1] += F * o;
+            if (gathers_coarse) S->b_fdwt_coarse[a] += F * o;
         }
-        S->b_adjoint += (Q + F) * e;
+        S->b_adjoint += (Q + F) * o;
         const double u8 = 8.0 * jobs[jp].count;     // node fields of the projection are FP64
-        S->b_project += P->n_fp * e + Q * u8;
-        S->b_sensor[0] += Q * u8 + Q * e;
-        S->b_sensor[1] += P->n_slopes * e + Q * e;
+        S->b_project += P->n_fp * o + Q * u8;
+        S->b_sensor[0] += Q * u8 + Q * o;
+        S->b_sensor[1] += P->n_slopes * e + Q * o;
         S->b_sensor[2] += Q * u8 + P->n_slopes * e;
         S->b_init += 5 * n * e;
         S->b_update_r += 4 * n * e;
@@ -363,7 +378,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     add(proj);
     add(adj);
     for (int k = 1; k <= WM_MAXLEV; ++k) add(tiled[k]);
-    S->buf = std::make_unique<DevBuf>();
+    S->buf = std::make_shared<DevBuf>();
     const size_t bytes = std::max<size_t>(all.size(), 1) * sizeof(Item);
     hipError_t e = hipMalloc(&S->buf->p, bytes);
     if (e != hipSuccess) return fail(WMCAO_ERR_OOM, "schedule allocation failed");
@@ -381,16 +396,19 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     S->n_proj = static_cast<int>(proj.size());
     S->adj = base + offs[5];
     S->n_adj = static_cast<int>(adj.size());
-    S->lds_adj = lds_a;
+    for (int c = 0; c < 2; ++c) S->lds_adj[c] = lds_a[c];
     S->adj_taps = taps_a;
-    for (int k = 0; k <= WM_MAXLEV; ++k) S->lds_idwt_lvl[k] = lds_lvl[k];
+    for (int c = 0; c < 2; ++c)
+        for (int k = 0; k <= WM_MAXLEV; ++k) S->lds_idwt_lvl[c][k] = lds_lvl[c][k];
     for (int k = 1; k <= WM_MAXLEV; ++k) {
         S->tiled[k] = base + offs[5 + k];
         S->n_tiled[k] = static_cast<int>(tiled[k].size());
     }
     S->maxk0 = maxk0;
-    S->lds_idwt = lds_i;
-    S->lds_fdwt = lds_f;
+    for (int c = 0; c < 2; ++c) {
+        S->lds_idwt[c] = lds_i[c];
+        S->lds_fdwt[c] = lds_f[c];
+    }
     S->lds_sensor = lds_s;
     S->lds_weights = lds_w;
     S->tile = tile;
@@ -411,7 +429,25 @@ struct MultiGraphKey {
     }
 };
 constexpr size_t MULTI_GRAPH_CACHE = 64;
-std::map<MultiGraphKey, hipGraphExec_t> g_multi_graphs;
+// A cached capture, the event recorded after its latest replay (so that it is
+// destroyed only once that replay has finished) and its last use, for
+// least-recently-used eviction.
+struct CachedGraph {
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    uint64_t last_use = 0;
+};
+std::map<MultiGraphKey, CachedGraph> g_multi_graphs;
+uint64_t g_graph_clock = 0;
+
+void destroy_cached(CachedGraph& g) {
+    if (g.done) {
+        (void)hipEventSynchronize(g.done);
+        (void)hipEventDestroy(g.done);
+    }
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = CachedGraph{};
+}
 
 // Schedule of frames first .. first + batch - 1 of a plan (cached).
 int get_sched(wmcao_plan_s* p, int batch, Sched** out, int first = 0) {
@@ -424,6 +460,7 @@ int get_sched(wmcao_plan_s* p, int batch, Sched** out, int first = 0) {
     auto S = std::make_unique<Sched>();
     int rc = build_sched({JobSpec{p, batch, first}}, p->tile, S.get());
     if (rc) return rc;
+    S->frames = batch;
     *out = S.get();
     p->sched[key] = std::move(S);
     return WMCAO_OK;
@@ -492,77 +529,121 @@ JobPlan make_jobplan(wmcao_plan_s* p, int nframes) {
 }
 
 // ------------------------------------------------------- stage drivers ----
-template <class T>
-void run_idwt(const JobArgs& a, const Sched& S, int in_vec, int out_vec, hipStream_t s) {
-    if (S.n_coarse_syn > 0)
-        timed(WMCAO_K_IDWT_COARSE, S.b_idwt_coarse, s, [&] {
-            launch_idwt_coarse<T>(a, S.coarse_syn, S.n_coarse_syn, in_vec, out_vec, S.lds_idwt, s);
-        });
-    for (int k = S.maxk0; k >= 1; --k)
-        timed(WMCAO_K_IDWT_TILE, S.b_idwt_tile[k], s, [&] {
-            launch_idwt_tile<T>(a, S.tiled[k], S.n_tiled[k], k, in_vec, out_vec, S.tile,
-                                S.lds_idwt_lvl[k], s);
-        });
+// T: PCG vector type of the plans of the job; S: their operator storage type;
+// c64: stages computing in FP64 (C_IDWT, C_ADJ, C_FDWT bits; all of them when
+// S is double).
+enum : int { C_IDWT = 1, C_ADJ = 2, C_FDWT = 4 };
+// Stages of an FP32-storage operator that compute in FP64 unless the plan
+// says otherwise: the forward transform, whose detail coefficients are small
+// differences of the summed P^T image (single-precision arithmetic there moved
+// E-ELT iterates by 2.5e-5; FP64 there alone by 3.8e-6, measured), while
+// W^-1 and P^T run in FP32.
+constexpr int DEFAULT_FP64_STAGES = C_FDWT;
+
+// Calls f.template operator()<C>() with C = double if the stage bit is set in
+// c64 (or S is double), else float.
+template <class S, class Fn>
+void with_compute(int c64, int bit, Fn&& f) {
+    if (std::is_same<S, double>::value || (c64 & bit))
+        f.template operator()<double>();
+    else
+        f.template operator()<float>();
 }
 
-template <class T>
-void run_fdwt(const JobArgs& a, const Sched& S, int src, int in_vec, int out_vec, int epi,
-              int aux_vec, hipStream_t s) {
-    for (int k = 1; k <= S.maxk0; ++k)
-        timed(WMCAO_K_FDWT_TILE, S.b_fdwt_tile[epi == EPI_APPLY][k], s, [&] {
-            launch_fdwt_tile<T>(a, S.tiled[k], S.n_tiled[k], k, src, in_vec, out_vec, epi,
-                                aux_vec, S.tile, s);
+template <class T, class S>
+void run_idwt(const JobArgs& a, const Sched& Sc, int in_vec, int out_vec, int c64, hipStream_t s) {
+    with_compute<S>(c64, C_IDWT, [&]<class C>() {
+        if (Sc.n_coarse_syn > 0)
+            timed(WMCAO_K_IDWT_COARSE, Sc.b_idwt_coarse, s, [&] {
+                launch_idwt_coarse<T, S, C>(a, Sc.coarse_syn, Sc.n_coarse_syn, in_vec, out_vec,
+                                            Sc.lds_idwt[sizeof(C) == 8], s);
+            });
+        for (int k = Sc.maxk0; k >= 1; --k)
+            timed(WMCAO_K_IDWT_TILE, Sc.b_idwt_tile[k], s, [&] {
+                launch_idwt_tile<T, S, C>(a, Sc.tiled[k], Sc.n_tiled[k], k, in_vec, out_vec, Sc.tile,
+                                          Sc.lds_idwt_lvl[sizeof(C) == 8][k], s);
+            });
+    });
+}
+
+template <class T, class S>
+void run_fdwt(const JobArgs& a, const Sched& Sc, int src, int in_vec, int out_vec, int epi,
+              int aux_vec, int c64, hipStream_t s) {
+    with_compute<S>(c64, C_FDWT, [&]<class C>() {
+        for (int k = 1; k <= Sc.maxk0; ++k)
+            timed(WMCAO_K_FDWT_TILE, Sc.b_fdwt_tile[epi == EPI_APPLY][k], s, [&] {
+                launch_fdwt_tile<T, S, C>(a, Sc.tiled[k], Sc.n_tiled[k], k, src, in_vec, out_vec, epi,
+                                          aux_vec, Sc.tile, s);
+            });
+        timed(WMCAO_K_FDWT_COARSE, Sc.b_fdwt_coarse[epi == EPI_APPLY], s, [&] {
+            launch_fdwt_coarse<T, S, C>(a, Sc.coarse, Sc.n_coarse, src, in_vec, out_vec, epi, aux_vec,
+                                        Sc.lds_fdwt[sizeof(C) == 8], s);
         });
-    timed(WMCAO_K_FDWT_COARSE, S.b_fdwt_coarse[epi == EPI_APPLY], s, [&] {
-        launch_fdwt_coarse<T>(a, S.coarse, S.n_coarse, src, in_vec, out_vec, epi, aux_vec,
-                              S.lds_fdwt, s);
+    });
+}
+
+template <class T, class S>
+void run_adjoint(const JobArgs& a, const Sched& Sc, int c64, hipStream_t s) {
+    with_compute<S>(c64, C_ADJ, [&]<class C>() {
+        timed(WMCAO_K_ADJOINT, Sc.b_adjoint, s, [&] {
+            launch_adjoint<T, S, C>(a, Sc.adj, Sc.n_adj, V_NODE, V_FP, Sc.lds_adj[sizeof(C) == 8],
+                                    Sc.adj_taps, s);
+        });
     });
 }
 
 // y = A x for every frame of the job (x_vec, y_vec are vector kinds).
-template <class T>
-void run_apply(const JobArgs& a, const Sched& S, int x_vec, int y_vec, hipStream_t s) {
-    run_idwt<T>(a, S, x_vec, V_PHI, s);
-    timed(WMCAO_K_PROJECT, S.b_project, s, [&] { launch_project<T>(a, S.proj, S.n_proj, V_PHI, 1, s); });
-    timed(WMCAO_K_SENSOR, S.b_sensor[0], s,
-          [&] { launch_weights<T>(a, S.proj, S.n_proj, V_NODE, S.lds_weights, s); });
-    timed(WMCAO_K_ADJOINT, S.b_adjoint, s, [&] {
-        launch_adjoint<T>(a, S.adj, S.n_adj, V_NODE, V_FP, S.lds_adj, S.adj_taps, s);
-    });
-    run_fdwt<T>(a, S, SRC_PT, V_FP, y_vec, EPI_APPLY, x_vec, s);
+template <class T, class S>
+void run_apply(const JobArgs& a, const Sched& Sc, int x_vec, int y_vec, int c64, hipStream_t s) {
+    run_idwt<T, S>(a, Sc, x_vec, V_PHI, c64, s);
+    timed(WMCAO_K_PROJECT, Sc.b_project, s, [&] { launch_project<T, S>(a, Sc.proj, Sc.n_proj, V_PHI, 1, s); });
+    timed(WMCAO_K_WEIGHTS, Sc.b_sensor[0], s,
+          [&] { launch_weights<T, S>(a, Sc.proj, Sc.n_proj, V_NODE, Sc.lds_weights, s); });
+    run_adjoint<T, S>(a, Sc, c64, s);
+    run_fdwt<T, S>(a, Sc, SRC_PT, V_FP, y_vec, EPI_APPLY, x_vec, c64, s);
 }
 
-template <class T>
-void run_rhs(const JobArgs& a, const Sched& S, int slopes_vec, int b_vec, hipStream_t s) {
-    timed(WMCAO_K_SENSOR, S.b_sensor[1], s, [&] {
-        launch_sensor<T>(a, S.sensor, S.n_sensor, SM_RHS, slopes_vec, V_NODE, S.lds_sensor, s);
+template <class T, class S>
+void run_rhs(const JobArgs& a, const Sched& Sc, int slopes_vec, int b_vec, int c64, hipStream_t s) {
+    timed(WMCAO_K_SENSOR, Sc.b_sensor[1], s, [&] {
+        launch_sensor<T, S>(a, Sc.sensor, Sc.n_sensor, SM_RHS, slopes_vec, V_NODE, Sc.lds_sensor, s);
     });
-    timed(WMCAO_K_ADJOINT, S.b_adjoint, s, [&] {
-        launch_adjoint<T>(a, S.adj, S.n_adj, V_NODE, V_FP, S.lds_adj, S.adj_taps, s);
-    });
-    run_fdwt<T>(a, S, SRC_PT, V_FP, b_vec, EPI_NONE, b_vec, s);
+    run_adjoint<T, S>(a, Sc, c64, s);
+    run_fdwt<T, S>(a, Sc, SRC_PT, V_FP, b_vec, EPI_NONE, b_vec, c64, s);
 }
 
-template <class T>
-void run_solve(const JobArgs& a, const Sched& S, int n_iter, int warm, int resid_replace,
+template <class T, class S>
+void run_solve(const JobArgs& a, const Sched& Sc, int n_iter, int warm, int resid_replace, int c64,
                hipStream_t s) {
-    run_rhs<T>(a, S, V_SLOPES, V_B, s);
-    if (warm) run_apply<T>(a, S, V_X, V_Q, s);
-    timed(WMCAO_K_INIT, S.b_init, s, [&] { launch_init<T>(a, S.vec, S.n_vec, warm, s); });
+    run_rhs<T, S>(a, Sc, V_SLOPES, V_B, c64, s);
+    if (warm) run_apply<T, S>(a, Sc, V_X, V_Q, c64, s);
+    timed(WMCAO_K_INIT, Sc.b_init, s, [&] { launch_init<T>(a, Sc.vec, Sc.n_vec, warm, s); });
     for (int it = 0; it < n_iter; ++it) {
         // rho of this iteration comes from the residual's partials on the
         // first iteration and after a replacement, else from k_update_p
         const bool replaced = resid_replace > 0 && it > 0 && it % resid_replace == 0;
         if (replaced) {
-            run_apply<T>(a, S, V_X, V_Q, s);
-            timed(WMCAO_K_REPLACE_R, S.b_replace, s, [&] { launch_replace_r<T>(a, S.vec, S.n_vec, it, s); });
+            run_apply<T, S>(a, Sc, V_X, V_Q, c64, s);
+            timed(WMCAO_K_REPLACE_R, Sc.b_replace, s, [&] { launch_replace_r<T>(a, Sc.vec, Sc.n_vec, it, s); });
         }
-        run_apply<T>(a, S, V_P, V_Q, s);
+        run_apply<T, S>(a, Sc, V_P, V_Q, c64, s);
         const int fresh = it == 0 || replaced;
-        timed(WMCAO_K_UPDATE_R, S.b_update_r, s,
-              [&] { launch_update_r<T>(a, S.vec, S.n_vec, it, fresh, s); });
-        timed(WMCAO_K_UPDATE_P, S.b_update_p, s, [&] { launch_update_p<T>(a, S.vec, S.n_vec, it, s); });
+        timed(WMCAO_K_UPDATE_R, Sc.b_update_r, s,
+              [&] { launch_update_r<T>(a, Sc.vec, Sc.n_vec, it, fresh, s); });
+        timed(WMCAO_K_UPDATE_P, Sc.b_update_p, s, [&] { launch_update_p<T>(a, Sc.vec, Sc.n_vec, it, s); });
     }
+}
+
+// Calls f.template operator()<T, S>() with the vector and operator storage
+// types of a plan: (double, double), (float, double) or (float, float).
+template <class Fn>
+void with_types(const wmcao_plan_s* p, Fn&& f) {
+    if (p->dtype == WMCAO_F64)
+        f.template operator()<double, double>();
+    else if (p->op64)
+        f.template operator()<float, double>();
+    else
+        f.template operator()<float, float>();
 }
 
 int check_launch() {
@@ -602,10 +683,7 @@ int enqueue_solve(wmcao_plan_s* p, const void* slopes, void* coeffs, int batch, 
     a.jp[0].resid = resid;
     a.jp[0].resid_ld = n_iter + 1;
     auto run = [&](const Sched& S, hipStream_t st) {
-        if (p->dtype == WMCAO_F32)
-            run_solve<float>(a, S, n_iter, warm, p->resid_replace, st);
-        else
-            run_solve<double>(a, S, n_iter, warm, p->resid_replace, st);
+        with_types(p, [&]<class T, class Sv>() { run_solve<T, Sv>(a, S, n_iter, warm, p->resid_replace, p->c64, st); });
     };
     if (!splits(p, batch)) {
         Sched* S = nullptr;
@@ -671,36 +749,9 @@ int enqueue_multi(const wmcao_plan_t* plans, const void* const* slopes, void* co
         g_multi_cache[key] = std::move(sp);
         return WMCAO_OK;
     };
-    // two concurrent halves (each plan's frames split in two) under the rule of
-    // a single-plan solve: every plan allows two streams and a half holds at
-    // least SPLIT_MIN_UNKNOWNS coefficients
-    int64_t total = 0;
-    bool two = true;
-    for (auto& j : jobs) {
-        total += static_cast<int64_t>(j.count) * j.plan->n;
-        two = two && j.plan->streams > 1;
-    }
-    std::vector<JobSpec> half[2];
-    std::vector<int> idx[2];
-    for (int i = 0; i < n_plans; ++i) {
-        const int c1 = counts[i] / 2, c0 = counts[i] - c1;
-        half[0].push_back(JobSpec{plans[i], c0, 0});
-        idx[0].push_back(i);
-        if (c1 > 0) {
-            half[1].push_back(JobSpec{plans[i], c1, c0});
-            idx[1].push_back(i);
-        }
-    }
-    const bool split = two && total / 2 >= SPLIT_MIN_UNKNOWNS && !half[1].empty();
-    Sched* S[2] = {nullptr, nullptr};
-    int rc = split ? packed(half[0], &S[0]) : packed(jobs, &S[0]);
-    if (!rc && split) rc = packed(half[1], &S[1]);
-    if (!rc && split) rc = ensure_side(plans[0]);
-    if (rc) return rc;
-    if (prepare_only) return WMCAO_OK;
     int rr = 0;
     for (int i = 0; i < n_plans; ++i) rr = std::max(rr, plans[i]->resid_replace);
-    auto args_for = [&](const std::vector<int>& ids) {
+    auto args_for = [&](const std::vector<JobSpec>& js, const std::vector<int>& ids) {
         JobArgs a{};
         a.njp = static_cast<int>(ids.size());
         for (int k = 0; k < a.njp; ++k) {
@@ -711,23 +762,82 @@ int enqueue_multi(const wmcao_plan_t* plans, const void* const* slopes, void* co
         }
         return a;
     };
-    auto run = [&](const JobArgs& a, const Sched& Sx, hipStream_t st) {
-        if (dt == WMCAO_F32)
-            run_solve<float>(a, Sx, n_iter, warm_start, rr, st);
-        else
-            run_solve<double>(a, Sx, n_iter, warm_start, rr, st);
+    auto run = [&](const JobArgs& a, const Sched& Sx, const wmcao_plan_s* typ, hipStream_t st) {
+        with_types(typ, [&]<class T, class Sv>() { run_solve<T, Sv>(a, Sx, n_iter, warm_start, rr, typ->c64, st); });
     };
-    if (!split) {
-        std::vector<int> all(n_plans);
-        for (int i = 0; i < n_plans; ++i) all[i] = i;
-        run(args_for(all), *S[0], s);
+    // Groups of one launch sequence each: plans of one operator type share
+    // kernels, so plans of both types run as two groups, the second on the
+    // first plan's side stream.  Within a single group, each plan's frames
+    // split into two concurrent halves under the rule of a single-plan solve:
+    // every plan allows two streams and a half holds at least
+    // SPLIT_MIN_UNKNOWNS coefficients.
+    std::vector<JobSpec> grp[2];
+    std::vector<int> idx[2];
+    // operator type of a plan: FP64 storage, or FP32 storage with its FP64 stages
+    auto op_key = [](const wmcao_plan_s* q) { return q->op64 ? 8 : q->c64; };
+    int keys[2] = {op_key(plans[0]), -1};
+    for (int i = 0; i < n_plans; ++i) {
+        const int k = op_key(plans[i]);
+        if (k != keys[0] && keys[1] < 0) keys[1] = k;
+        if (k != keys[0] && k != keys[1])
+            return fail(WMCAO_ERR_INVALID_ARG, "packed plans may use at most two operator types");
+    }
+    const bool mixed_ops = keys[1] >= 0;
+    if (mixed_ops) {
+        for (int i = 0; i < n_plans; ++i) {
+            const int g = op_key(plans[i]) == keys[0] ? 0 : 1;
+            grp[g].push_back(JobSpec{plans[i], counts[i], 0});
+            idx[g].push_back(i);
+        }
+    } else {
+        int64_t total = 0;
+        bool two = true;
+        for (auto& j : jobs) {
+            total += static_cast<int64_t>(j.count) * j.plan->n;
+            two = two && j.plan->streams > 1;
+        }
+        std::vector<JobSpec> half[2];
+        std::vector<int> hidx[2];
+        for (int i = 0; i < n_plans; ++i) {
+            const int c1 = counts[i] / 2, c0 = counts[i] - c1;
+            half[0].push_back(JobSpec{plans[i], c0, 0});
+            hidx[0].push_back(i);
+            if (c1 > 0) {
+                half[1].push_back(JobSpec{plans[i], c1, c0});
+                hidx[1].push_back(i);
+            }
+        }
+        const bool split = two && total / 2 >= SPLIT_MIN_UNKNOWNS && !half[1].empty();
+        if (split) {
+            for (int g = 0; g < 2; ++g) {
+                grp[g] = half[g];
+                idx[g] = hidx[g];
+            }
+        } else {
+            grp[0] = jobs;
+            for (int i = 0; i < n_plans; ++i) idx[0].push_back(i);
+        }
+    }
+    const bool two_groups = !grp[1].empty();
+    // a plan limited to one stream keeps both groups on the caller's stream
+    bool side_ok = true;
+    for (int i = 0; i < n_plans; ++i) side_ok = side_ok && plans[i]->streams > 1;
+    Sched* S[2] = {nullptr, nullptr};
+    int rc = packed(grp[0], &S[0]);
+    if (!rc && two_groups) rc = packed(grp[1], &S[1]);
+    if (!rc && two_groups && side_ok) rc = ensure_side(plans[0]);
+    if (rc) return rc;
+    if (prepare_only) return WMCAO_OK;
+    if (!two_groups || !side_ok) {
+        run(args_for(grp[0], idx[0]), *S[0], plans[idx[0][0]], s);
+        if (two_groups) run(args_for(grp[1], idx[1]), *S[1], plans[idx[1][0]], s);
         return check_launch();
     }
     wmcao_plan_s* p0 = plans[0];
     WM_HIP(hipEventRecord(p0->ev_fork, s));
     WM_HIP(hipStreamWaitEvent(p0->side, p0->ev_fork, 0));
-    run(args_for(idx[0]), *S[0], s);
-    run(args_for(idx[1]), *S[1], p0->side);
+    run(args_for(grp[0], idx[0]), *S[0], plans[idx[0][0]], s);
+    run(args_for(grp[1], idx[1]), *S[1], plans[idx[1][0]], p0->side);
     WM_HIP(hipEventRecord(p0->ev_join, p0->side));
     WM_HIP(hipStreamWaitEvent(s, p0->ev_join, 0));
     return check_launch();
@@ -776,6 +886,12 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     if (opts->precond != 0 && opts->precond != 1) return fail(WMCAO_ERR_INVALID_ARG, "precond");
     if (opts->resid_replace_every < 0) return fail(WMCAO_ERR_INVALID_ARG, "resid_replace_every < 0");
     if (opts->streams < 0 || opts->streams > 2) return fail(WMCAO_ERR_INVALID_ARG, "streams must be 0, 1 or 2");
+    if (opts->op_precision != 0 && opts->op_precision != 32 && opts->op_precision != 64)
+        return fail(WMCAO_ERR_INVALID_ARG, "op_precision must be 0, 32 or 64");
+    if (opts->dtype == WMCAO_F64 && opts->op_precision == 32)
+        return fail(WMCAO_ERR_INVALID_ARG, "FP64 plans have FP64 operators");
+    if (opts->op_fp64_stages < -1 || opts->op_fp64_stages > 7)
+        return fail(WMCAO_ERR_INVALID_ARG, "op_fp64_stages must be -1 or a mask of 1, 2 and 4");
     if (!(pupil->diameter_m > 0.0) || pupil->obstruction_ratio < 0.0 || pupil->obstruction_ratio >= 1.0)
         return fail(WMCAO_ERR_INVALID_ARG, "pupil");
     bool seen_ngs = false;
@@ -814,6 +930,19 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     std::call_once(once, [] { configure_kernels(); });
     p->dtype = opts->dtype;
     p->esz = opts->dtype == WMCAO_F32 ? 4 : 8;
+    {
+        int64_t n_total = 0;
+        for (int l = 0; l < n_layers; ++l) n_total += static_cast<int64_t>(layers[l].n) * layers[l].n;
+        // default: FP64 operators below 2^17 unknowns (launch-bound solves whose
+        // iterates are most sensitive to rounding), FP32 above
+        const int op = opts->dtype == WMCAO_F64 ? 64
+                       : opts->op_precision ? opts->op_precision
+                       : (n_total < (int64_t(1) << 17) ? 64 : 32);
+        p->op64 = op == 64 ? 1 : 0;
+        p->osz = p->op64 ? 8 : 4;
+        p->c64 = p->op64 ? (C_IDWT | C_ADJ | C_FDWT)
+                 : opts->op_fp64_stages >= 0 ? opts->op_fp64_stages : DEFAULT_FP64_STAGES;
+    }
     p->L = n_layers;
     p->W = n_wfs;
     p->levels = levels;
@@ -829,6 +958,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     H.W = n_wfs;
     H.levels = levels;
     H.dtype = opts->dtype;
+    H.op64 = p->op64;
     H.precond = opts->precond;
     H.alpha = opts->alpha;
     db3_filters(H.h, H.g);
@@ -1083,7 +1213,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             if (p->n_fpimg > (int64_t(1) << 30))
                 return fail(WMCAO_ERR_UNSUPPORTED, "adjoint footprint images too large");
             // the level-1 analysis addresses one image with 32-bit byte offsets
-            if (static_cast<int64_t>(len[0]) * len[1] * p->esz >= (int64_t(1) << 31))
+            if (static_cast<int64_t>(len[0]) * len[1] * p->osz >= (int64_t(1) << 31))
                 return fail(WMCAO_ERR_UNSUPPORTED, "adjoint footprint image too large");
             int br = ADJ_BAND, need = 0;
             for (; br >= 1; br /= 2) {
@@ -1099,9 +1229,8 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
                     }
                     const int rows = std::min(len[0], r0 + br) - r0;
                     // staged node rows and the kernel's zero rows after them
-                    const int vbytes =
-                        ahi < alo ? 0
-                                  : ((ahi - alo + ADJ_TAPS_MAX) * nn * static_cast<int>(p->esz) + 15) & ~15;
+                    // sized for FP64 arithmetic, so one band split serves both
+                    const int vbytes = ahi < alo ? 0 : ((ahi - alo + ADJ_TAPS_MAX) * nn * 8 + 15) & ~15;
                     need = std::max(need, vbytes + rows * nn * 8);
                 }
                 if (need <= ADJ_LDS) break;
@@ -1122,7 +1251,21 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
                 fprc.push_back(alo);
                 fprc.push_back(ahi);
             }
-            p->lds_adjoint = std::max(p->lds_adjoint, need);
+            p->lds_adjoint[1] = std::max(p->lds_adjoint[1], need);
+            // the same bands with FP32 LDS
+            for (int r0 = 0; r0 < len[0]; r0 += br) {
+                int alo = nn, ahi = -1;
+                for (int r = r0; r < std::min(len[0], r0 + br); ++r) {
+                    const int f = fprc[2 * (tab + r)], c = fprc[2 * (tab + r) + 1];
+                    if (c > 0) {
+                        alo = std::min(alo, f);
+                        ahi = std::max(ahi, f + c - 1);
+                    }
+                }
+                const int rows = std::min(len[0], r0 + br) - r0;
+                const int vbytes = ahi < alo ? 0 : ((ahi - alo + ADJ_TAPS_MAX) * nn * 4 + 15) & ~15;
+                p->lds_adjoint[0] = std::max(p->lds_adjoint[0], vbytes + rows * nn * 4);
+            }
         }
     }
 
@@ -1203,10 +1346,12 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     if (!(p->vr = p->alloc(ve, &rc))) return rc;
     if (!(p->vp = p->alloc(ve, &rc))) return rc;
     if (!(p->vq = p->alloc(ve, &rc))) return rc;
-    if (!(p->vphi = p->alloc(ve, &rc))) return rc;
-    if (!(p->vll = p->alloc(static_cast<size_t>(p->ll_size) * B * 8, &rc))) return rc;   // FP64
-    if (!(p->vnode = p->alloc(static_cast<size_t>(p->n_nodes) * B * p->esz, &rc))) return rc;
-    if (!(p->vfp = p->alloc(static_cast<size_t>(p->n_fpimg) * B * p->esz, &rc))) return rc;
+    // operator scratch in the operator type
+    if (!(p->vphi = p->alloc(static_cast<size_t>(p->n) * B * p->osz, &rc))) return rc;
+    // low-pass bands in the arithmetic type of the stage using them (<= 8 bytes)
+    if (!(p->vll = p->alloc(static_cast<size_t>(p->ll_size) * B * 8, &rc))) return rc;
+    if (!(p->vnode = p->alloc(static_cast<size_t>(p->n_nodes) * B * p->osz, &rc))) return rc;
+    if (!(p->vfp = p->alloc(static_cast<size_t>(p->n_fpimg) * B * p->osz, &rc))) return rc;
     if (!(p->vspart = static_cast<double*>(p->alloc(static_cast<size_t>(p->n_spart) * B * 8, &rc))))
         return rc;
     if (!(p->vu = static_cast<double*>(p->alloc(static_cast<size_t>(p->n_nodes) * B * 8, &rc)))) return rc;
@@ -1250,7 +1395,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         rc = check_launch();
         if (rc) return rc;
         if (p->dtype == WMCAO_F32)
-            launch_cast_from_double<float>(p->jac_d, static_cast<float*>(jac_t), p->n, nullptr);
+            launch_cast<double, float>(p->jac_d, static_cast<float*>(jac_t), p->n, nullptr);
         rc = check_launch();
         if (rc) return rc;
         WM_HIP(hipDeviceSynchronize());
@@ -1288,41 +1433,48 @@ static int simple_call(wmcao_plan_t p, const void* in, void* out, int batch, voi
     a.jp[0].vec[V_IN] = const_cast<void*>(in);
     a.jp[0].vec[V_OUT] = out;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool f32 = p->dtype == WMCAO_F32;
     ProfScope ps(&p->prof);
-    switch (kind) {
-        case 0:   // W^-1
-            a.jp[0].stride[V_IN] = a.jp[0].stride[V_OUT] = p->n;
-            if (f32) run_idwt<float>(a, *S, V_IN, V_OUT, s); else run_idwt<double>(a, *S, V_IN, V_OUT, s);
-            break;
-        case 1:   // W
-            a.jp[0].stride[V_IN] = a.jp[0].stride[V_OUT] = p->n;
-            if (f32) run_fdwt<float>(a, *S, SRC_PIX, V_IN, V_OUT, EPI_NONE, V_IN, s);
-            else run_fdwt<double>(a, *S, SRC_PIX, V_IN, V_OUT, EPI_NONE, V_IN, s);
-            break;
-        case 2:   // forward slopes from layers
-            a.jp[0].stride[V_IN] = p->n;
-            a.jp[0].stride[V_OUT] = p->n_slopes;
-            if (f32) {
-                launch_project<float>(a, S->proj, S->n_proj, V_IN, 0, s);
-                launch_sensor<float>(a, S->sensor, S->n_sensor, SM_FWD, V_U, V_OUT, S->lds_sensor, s);
-            } else {
-                launch_project<double>(a, S->proj, S->n_proj, V_IN, 0, s);
-                launch_sensor<double>(a, S->sensor, S->n_sensor, SM_FWD, V_U, V_OUT, S->lds_sensor, s);
-            }
-            break;
-        case 3:   // rhs
-            a.jp[0].stride[V_IN] = p->n_slopes;
-            a.jp[0].stride[V_OUT] = p->n;
-            if (f32) run_rhs<float>(a, *S, V_IN, V_OUT, s); else run_rhs<double>(a, *S, V_IN, V_OUT, s);
-            break;
-        case 4:   // apply
-            a.jp[0].stride[V_IN] = a.jp[0].stride[V_OUT] = p->n;
-            if (f32) run_apply<float>(a, *S, V_IN, V_OUT, s); else run_apply<double>(a, *S, V_IN, V_OUT, s);
-            break;
-        default:
-            return fail(WMCAO_ERR_INVALID_ARG, "kind");
-    }
+    // the operator stages read and write pixel fields in the operator type F;
+    // when the caller's buffers hold another type (an FP32 plan with FP64
+    // operators), pixel fields pass through the plan's pixel scratch
+    const bool same = p->esz == p->osz;
+    with_types(p, [&]<class T, class Sv>() {
+        switch (kind) {
+            case 0:   // W^-1
+                a.jp[0].stride[V_IN] = a.jp[0].stride[V_OUT] = p->n;
+                run_idwt<T, Sv>(a, *S, V_IN, same ? V_OUT : V_PHI, p->c64, s);
+                if (!same)
+                    launch_cast<Sv, T>(static_cast<const Sv*>(p->vphi), static_cast<T*>(out),
+                                       p->n * batch, s);
+                break;
+            case 1:   // W
+                a.jp[0].stride[V_IN] = a.jp[0].stride[V_OUT] = p->n;
+                if (!same)
+                    launch_cast<T, Sv>(static_cast<const T*>(in), static_cast<Sv*>(p->vphi),
+                                       p->n * batch, s);
+                run_fdwt<T, Sv>(a, *S, SRC_PIX, same ? V_IN : V_PHI, V_OUT, EPI_NONE, V_OUT, p->c64, s);
+                break;
+            case 2:   // forward slopes from layers
+                a.jp[0].stride[V_IN] = p->n;
+                a.jp[0].stride[V_OUT] = p->n_slopes;
+                if (!same)
+                    launch_cast<T, Sv>(static_cast<const T*>(in), static_cast<Sv*>(p->vphi),
+                                       p->n * batch, s);
+                launch_project<T, Sv>(a, S->proj, S->n_proj, same ? V_IN : V_PHI, 0, s);
+                launch_sensor<T, Sv>(a, S->sensor, S->n_sensor, SM_FWD, V_U, V_OUT, S->lds_sensor, s);
+                break;
+            case 3:   // rhs
+                a.jp[0].stride[V_IN] = p->n_slopes;
+                a.jp[0].stride[V_OUT] = p->n;
+                run_rhs<T, Sv>(a, *S, V_IN, V_OUT, p->c64, s);
+                break;
+            case 4:   // apply
+                a.jp[0].stride[V_IN] = a.jp[0].stride[V_OUT] = p->n;
+                run_apply<T, Sv>(a, *S, V_IN, V_OUT, p->c64, s);
+                break;
+        }
+    });
+    if (kind < 0 || kind > 4) return fail(WMCAO_ERR_INVALID_ARG, "kind");
     return check_launch();
 }
 
@@ -1386,10 +1538,12 @@ int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int b
     if (!plan->gexec || plan->gkey != key) {
         rc = prepare_solve(plan, batch);   // outside the capture (it allocates)
         if (rc) return rc;
-        if (plan->gexec) {
+        if (plan->gexec) {   // replaced: wait for its last replay before freeing it
+            if (plan->gdone) (void)hipEventSynchronize(plan->gdone);
             (void)hipGraphExecDestroy(plan->gexec);
             plan->gexec = nullptr;
         }
+        if (!plan->gdone) WM_HIP(hipEventCreateWithFlags(&plan->gdone, hipEventDisableTiming));
         WM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         rc = enqueue_solve(plan, slopes, coeffs, batch, n_iter, warm_start, resid_dev, status_dev, s);
         hipGraph_t graph = nullptr;
@@ -1408,6 +1562,7 @@ int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int b
         plan->gkey = key;
     }
     WM_HIP(hipGraphLaunch(plan->gexec, s));
+    WM_HIP(hipEventRecord(plan->gdone, s));
     return WMCAO_OK;
 }
 
@@ -1440,9 +1595,12 @@ int wmcao_solve_multi_graph(const wmcao_plan_t* plans, const void* const* slopes
         int rc = enqueue_multi(plans, slopes, coeffs, counts, n_plans, n_iter, warm_start, s,
                                /*prepare_only=*/true);
         if (rc) return rc;
-        if (g_multi_graphs.size() >= MULTI_GRAPH_CACHE) {
-            (void)hipGraphExecDestroy(g_multi_graphs.begin()->second);
-            g_multi_graphs.erase(g_multi_graphs.begin());
+        if (g_multi_graphs.size() >= MULTI_GRAPH_CACHE) {   // evict the least recently used
+            auto lru = g_multi_graphs.begin();
+            for (auto jt = g_multi_graphs.begin(); jt != g_multi_graphs.end(); ++jt)
+                if (jt->second.last_use < lru->second.last_use) lru = jt;
+            destroy_cached(lru->second);
+            g_multi_graphs.erase(lru);
         }
         DevGuard g(plans[0]->device);
         WM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1454,14 +1612,21 @@ int wmcao_solve_multi_graph(const wmcao_plan_t* plans, const void* const* slopes
             return rc;
         }
         if (e != hipSuccess) return fail(WMCAO_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
-        hipGraphExec_t ge = nullptr;
-        e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+        CachedGraph cg;
+        e = hipGraphInstantiate(&cg.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(WMCAO_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e));
-        it = g_multi_graphs.emplace(key, ge).first;
+        e = hipEventCreateWithFlags(&cg.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(cg.exec);
+            return fail(WMCAO_ERR_HIP, std::string("event: ") + hipGetErrorString(e));
+        }
+        it = g_multi_graphs.emplace(key, cg).first;
     }
     DevGuard g(plans[0]->device);
-    WM_HIP(hipGraphLaunch(it->second, s));
+    it->second.last_use = ++g_graph_clock;
+    WM_HIP(hipGraphLaunch(it->second.exec, s));
+    WM_HIP(hipEventRecord(it->second.done, s));
     return WMCAO_OK;
 }
 
@@ -1530,7 +1695,7 @@ void wmcao_plan_destroy(wmcao_plan_t plan) {
             bool uses = false;
             for (auto& t : it->first.args) uses = uses || std::get<0>(t) == plan;
             if (uses) {
-                (void)hipGraphExecDestroy(it->second);
+                destroy_cached(it->second);
                 it = g_multi_graphs.erase(it);
             } else {
                 ++it;
@@ -1538,6 +1703,7 @@ void wmcao_plan_destroy(wmcao_plan_t plan) {
         }
     }
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->gdone) (void)hipEventDestroy(plan->gdone);
     if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
     if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
     if (plan->side) (void)hipStreamDestroy(plan->side);

@@ -9,12 +9,15 @@ sensors (one per direction, the pupil nodes as measurement points): P phi is
 (H^T H + alpha I) a = H^T P phi are solved by the same PCG kernels on the
 mirror plan (its "layers" are the actuator grids, with no wavelet transform).
 
-Pseudo-open-loop control (Sec. 4.2, Alg. 4.1), with a two-frame delay:
-    s_ol = s + A^ a_{t-2};   da = R s_ol - a_{t-2};   a_t = a_{t-1} + g da,
-where R is tomography (warm-started PCG, Sec. 5.1) followed by W^-1 and the
-fitting step, and A^ maps mirror commands to sensor slopes (a plan whose
-layers are the mirror grids, seen by the tomography's own sensors).  Every
-vector operation is a library kernel (``wmcao_axpby``).
+Pseudo-open-loop control (Sec. 4.2, Alg. 4.1) with a delay of two frames:
+the residual slopes measured through the commands applied two frames ago are
+turned back into open-loop slopes by adding what those commands contribute
+(A^ maps commands to slopes: a plan whose layers are the mirror grids, seen by
+the tomography's own sensors); R (tomography by warm-started PCG, Sec. 5.1,
+then W^-1 and the fitting step) reconstructs commands from them, and an
+integrator with gain g moves the latest commands a fraction g towards that
+reconstruction, measured against the commands the slopes were taken with.
+Every vector operation is a library kernel (``wmcao_axpby``).
 """
 import ctypes as C
 
@@ -81,18 +84,29 @@ class PolcController:
     def mirror_slopes(self, a):
         return self.ahat.forward_layers(a)
 
+    def _open_loop(self, s, a_meas):
+        """Slopes the atmosphere alone would give: s plus the contribution of
+        the commands a_meas that were applied when s was measured."""
+        axpby(1.0, s, 1.0, self.mirror_slopes(a_meas), self.s_ol)
+        return self.s_ol
+
+    def _reconstruct(self, s_ol):
+        """R: tomography (warm-started after the first step), W^-1, fitting."""
+        warm = self.steps > 0
+        self.tomo.solve(s_ol, self.c, n_iter=self.n_iter, warm_start=warm)
+        self.fitter.fit(self.tomo.coeffs_to_layers(self.c), self.a_fit, warm_start=warm)
+        return self.a_fit
+
     def step(self, s):
         """One control step from the residual slopes s measured for the
         commands a_{t-2}; returns the new commands a_t."""
-        a2, a1 = self.a_hist
-        axpby(1.0, s, 1.0, self.mirror_slopes(a2), self.s_ol)               # s_ol = s + A^ a_{t-2}
-        self.tomo.solve(self.s_ol, self.c, n_iter=self.n_iter, warm_start=self.steps > 0)
-        layers = self.tomo.coeffs_to_layers(self.c)
-        self.fitter.fit(layers, self.a_fit, warm_start=self.steps > 0)      # R s_ol
-        a_new = torch.empty_like(a1)
-        axpby(1.0, self.a_fit, -1.0, a2, a_new)                            # da = R s_ol - a_{t-2}
-        axpby(1.0, a1, self.gain, a_new, a_new)                            # a_t = a_{t-1} + g da
-        self.a_hist = [a1, a_new]
+        a_meas, a_last = self.a_hist
+        target = self._reconstruct(self._open_loop(s, a_meas))
+        # integrator: a_last + g (target - a_meas), as (a_last - g a_meas) + g target
+        a_new = torch.empty_like(a_last)
+        axpby(1.0, a_last, -self.gain, a_meas, a_new)
+        axpby(1.0, a_new, self.gain, target, a_new)
+        self.a_hist = [a_last, a_new]
         self.steps += 1
         return a_new
 

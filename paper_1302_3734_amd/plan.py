@@ -31,7 +31,8 @@ class Plan:
     """A solver plan for one telescope configuration on the current device."""
 
     def __init__(self, cfg, sigmas, dtype="f64", max_batch=1, cinv_blocks=None,
-                 precond=True, resid_replace_every=0, tile=0, lds_budget=0, streams=0):
+                 precond=True, resid_replace_every=0, tile=0, lds_budget=0, streams=0,
+                 op_precision=0, op_fp64_stages=-1):
         lib = _abi.lib()
         code, self.torch_dtype = _DT[dtype]
         self.dtype = dtype
@@ -61,7 +62,8 @@ class Plan:
         pupil = _abi.Pupil(cfg["diameter"], cfg["obstruction"])
         opts = _abi.Options(cfg["alpha"], cfg["r0"], cfg["L0"], code, self.max_batch,
                             int(resid_replace_every), 1 if precond else 0, int(tile),
-                            int(lds_budget), int(streams))
+                            int(lds_budget), int(streams), int(op_precision),
+                            int(op_fp64_stages))
         h = C.c_void_p()
         rc = lib.wmcao_plan(C.byref(pupil), Ls, len(layers), Ws, len(wfs), _abi.Wavelet(0, 3),
                             int(cfg["levels"]), C.byref(opts), C.byref(h))

@@ -67,7 +67,8 @@ class Server:
 
     configs: {name: (cfg dict, sigmas)}; streams: {stream name: config name}.
     hip_streams: number of lanes (default: one per configuration); configuration
-    i uses lane i mod hip_streams.  hbm_budget: bytes that frames in flight may
+    i uses lane i mod hip_streams, unless lane_map ({config name: lane index})
+    assigns the lanes.  hbm_budget: bytes that frames in flight may
     reserve (default: half of the free device memory at start).  depth: launches
     a lane may hold in flight.  max_frames: frames of one telescope stream in
     one launch.  keep_inputs: keep each frame's warm start (for
@@ -78,7 +79,7 @@ class Server:
 
     def __init__(self, configs, streams, dtype="f32", n_iter=10, hip_streams=None,
                  hbm_budget=None, keep_inputs=False, graphs=True, tile=0, pack=True, depth=2,
-                 max_frames=8):
+                 max_frames=8, lane_map=None):
         self.dtype = dtype
         self.n_iter = int(n_iter)
         self.keep_inputs = keep_inputs
@@ -89,9 +90,13 @@ class Server:
         # frames of a configuration in one launch: max_frames per telescope stream
         count = {c: k * self.max_frames for c, k in collections.Counter(streams.values()).items()}
         names = [c for c in configs if count.get(c)]
-        n_lanes = min(len(names), int(hip_streams) if hip_streams else len(names))
+        if lane_map:
+            n_lanes = max(int(lane_map[c]) for c in names) + 1
+            self.lane_of = {c: int(lane_map[c]) for c in names}
+        else:
+            n_lanes = min(len(names), int(hip_streams) if hip_streams else len(names))
+            self.lane_of = {c: i % n_lanes for i, c in enumerate(names)}
         self.lanes = [torch.cuda.Stream() for _ in range(n_lanes)]
-        self.lane_of = {c: i % n_lanes for i, c in enumerate(names)}
         self.lane_cfgs = [[c for c in names if self.lane_of[c] == i] for i in range(n_lanes)]
         # one plan per configuration (its launches are ordered on its lane),
         # batch = the telescope streams of that configuration.  The lanes are

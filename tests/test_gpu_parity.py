@@ -1,9 +1,8 @@
 """GPU parity of every operator stage against the FP64 oracle, through the C ABI.
 
 Tolerances: the FP64 path must agree with the oracle to rounding level
-(1e-12 relative for one operator application, 1e-11 for a whole PCG solve);
-the FP32 path to 1e-5 (operators) -- single-precision storage of every vector
-with FP64 inner products."""
+(1e-12 relative for one operator application); the FP32 path to 1e-5, with
+single-precision operators (op_precision 32) or FP64 operators (64)."""
 import numpy as np
 import pytest
 
@@ -36,6 +35,14 @@ CASES = [
     ("c2-f32", WL.config_c2, "f32", {}),
     ("c2-f64-lds160", WL.config_c2, "f64", {"lds_budget": 160 * 1024}),
     ("c2-f32-tile64", WL.config_c2, "f32", {"tile": 64}),
+    # single-precision operators on the small systems too (their default is
+    # FP64 operators), at several tiles and with ragged tails
+    ("tiny-f32-op32", tiny_config, "f32", {"op_precision": 32}),
+    ("ragged-tiled-f32-op32", tiny_ragged_config, "f32", {"tile": 16, "lds_budget": 512,
+                                                          "op_precision": 32}),
+    ("max-f32-op32", tiny_max_config, "f32", {"tile": 16, "op_precision": 32}),
+    ("c1-f32", WL.config_c1, "f32", {}),
+    ("c2-f32-op64", WL.config_c2, "f32", {"op_precision": 64}),
 ]
 
 _cache = {}

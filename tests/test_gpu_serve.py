@@ -70,3 +70,57 @@ def test_budget_queues_frames():
         fu.result(timeout=60)
     srv.close()
     assert max(srv.frames_in_launch) == 1 and len(srv.records) == 6
+
+
+def test_served_c5_geometries_equal_alone_and_match_oracle():
+    """The served stream's four telescope configurations (8 m and 16 m
+    NGS-only, 39 m and 42 m LGS-only), one telescope stream each, with the two
+    E-ELT-class configurations sharing one lane: every served frame equals
+    the same frame solved alone from the same warm start, bitwise, and the
+    newest frame of every stream matches the FP64 oracle's PCG from that warm
+    start (FP32 bar)."""
+    require_gpu()
+    import torch
+    from paper_1302_3734_amd import Plan
+    from paper_1302_3734_amd.serve import Server
+    from tests import oracle_jobs
+    from tests.gpu_common import oracle_pool_map, record
+    names = ["C4-8m-ngs", "C4-16m-ngs", "C4-39m-lgs", "C4-42m-lgs"]
+    cfgs, pools = {}, {}
+    n_frames = 4
+    for nm in names:
+        cfg = WL.config_by_name(nm)
+        S, sig, s, _ = setup(cfg, frame=0, seed_frame=0)
+        cfgs[nm] = (cfg, sig)
+        sl = oracle_pool_map(oracle_jobs.slopes, [(nm, sig, f, 0) for f in range(1, n_frames + 1)])
+        pools[nm] = [torch.tensor(v, dtype=torch.float32, device="cuda") for v in sl]
+    streams = {nm: nm for nm in names}
+    lanes = {"C4-8m-ngs": 0, "C4-16m-ngs": 1, "C4-39m-lgs": 2, "C4-42m-lgs": 2}
+    srv = Server(cfgs, streams, dtype="f32", n_iter=10, keep_inputs=True, lane_map=lanes)
+    futs = []
+    say("[serve-c5] submitting")
+    for f in range(n_frames):
+        for nm in names:
+            futs.append((nm, f, srv.submit(nm, pools[nm][f])))
+        time.sleep(0.001)
+    results = [(nm, f, fu.result(timeout=120)) for nm, f, fu in futs]
+    srv.close()
+    say(f"[serve-c5] {len(results)} frames, {srv.launches} launches")
+    alone = {nm: Plan(cfg, sig, dtype="f32", max_batch=1) for nm, (cfg, sig) in cfgs.items()}
+    jobs = []
+    for nm, f, (x, x0) in results:
+        xs = x0.clone()
+        alone[nm].solve(pools[nm][f].reshape(1, -1), xs, n_iter=10, warm_start=True)
+        torch.cuda.synchronize()
+        assert torch.equal(xs, x), (nm, f)
+        if f == n_frames - 1:
+            jobs.append((nm, cfgs[nm][1], pools[nm][f].double().cpu().numpy(),
+                         x0.double().cpu().numpy().ravel(), x.double().cpu().numpy().ravel(), 10, "f32"))
+    for p in alone.values():
+        p.close()
+    say("[serve-c5] oracle references")
+    res = oracle_pool_map(oracle_jobs.check, jobs)
+    for job, (e, bars) in zip(jobs, res):
+        say(f"[serve-c5] {job[0]}: e {e} bars {bars}")
+        record("served-" + job[0], "f32", e, bars)
+        assert all(a < c for a, c in zip(e, bars)), (job[0], e, bars)

@@ -1,14 +1,20 @@
 """GPU parity of whole PCG solves (Sec. 5.1) against the FP64 oracle through
-the C ABI: FP64 to 1e-11 and FP32 to 1e-5 in coefficient error, per-layer
-reconstruction error and residual difference; batch invariance; breakdown
-handling; graph replay."""
+the C ABI.
+
+Bars: FP64 1e-11 in coefficient error e_x, per-layer reconstruction error
+e_phi and residual difference e_res.  FP32 1e-5 in each, or twice the
+oracle's own deviation when it stores its CG vectors, b and J in FP32
+(gpu_common.fp32_spread) where that alone exceeds half the bar.  Also: batch
+invariance, breakdown handling, graph replay, mixed-size packing, two-stream
+halves."""
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as WL
-from tests.gpu_common import (fp32_tol, rel, require_gpu, say, setup, slopes_for, to_dev,
-                              to_np)
+from tests import oracle_jobs
+from tests.gpu_common import (fp32_tol, oracle_pool_map, record, rel, require_gpu, say, setup,
+                              slopes_for, solve_errors, to_dev, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -18,23 +24,29 @@ def _tdt(dt):
     return torch.float64 if dt == "f64" else torch.float32
 
 
-def _errors(S, x, x_ref, b):
-    e_x = rel(x, x_ref)
-    e_phi = max(rel(a, r) for a, r in zip(S.to_layers(x), S.to_layers(x_ref)))
-    e_res = float(np.linalg.norm(S.apply_A(x) - S.apply_A(x_ref)) / np.linalg.norm(b))
-    return e_x, e_phi, e_res
-
-
 def _f(S, b, x):
     """The quadratic functional 1/2 x^T A x - b^T x that CG minimises."""
     return 0.5 * x @ S.apply_A(x) - b @ x
 
 
+def _check_all(name, dt, results, frames):
+    worst = 0.0
+    for f, (e, bars) in zip(frames, results):
+        record(name, dt, e, bars)
+        ratio = max(a / c for a, c in zip(e, bars))
+        worst = max(worst, ratio)
+        if ratio >= 1.0:
+            say(f"[{name}-{dt}] frame {f}: e {e} bars {bars}")
+    say(f"[{name}-{dt}] {len(frames)} frames, largest error/bar {worst:.3f}")
+    for f, (e, bars) in zip(frames, results):
+        assert all(a < c for a, c in zip(e, bars)), (name, f, e, bars)
+
+
 def test_c1_fp64_cold_10_and_20_iterations():
-    """10 iterations: FP64 parity to 1e-11.  20 iterations: the C1 system is
-    so ill-conditioned that the iterate is not reproducible under rounding --
-    the oracle itself moves by ~1e-4 when its right side changes by one ulp --
-    so the GPU must stay within 10x of that spread, and the CG functional
+    """10 iterations: FP64 parity to 1e-11.  20 iterations: the oracle's own
+    iterate moves by ~1e-4 when its right side changes by one ulp (against
+    ~1e-13 at 10 iterations), so no implementation can meet 1e-11 there; the
+    GPU must stay within 10x of that one-ulp spread, and the CG functional
     within 10x of its spread."""
     require_gpu()
     import torch
@@ -52,11 +64,12 @@ def test_c1_fp64_cold_10_and_20_iterations():
         x = to_np(plan.solve(to_dev(s[None, :], torch.float64), n_iter=k, resid=resid,
                              status=status)).ravel()
         assert int(status.item()) == 0
-        e_x, e_phi, e_res = _errors(S, x, x_ref, b)
+        e = solve_errors(S, x, x_ref, b)
         e_f = abs(_f(S, b, x) - _f(S, b, x_ref)) / abs(_f(S, b, x_ref))
-        say(f"[c1-f64-{k}] e_x {e_x:.2e} e_phi {e_phi:.2e} e_res {e_res:.2e} e_f {e_f:.2e}")
+        say(f"[c1-f64-{k}] e_x {e[0]:.2e} e_phi {e[1]:.2e} e_res {e[2]:.2e} e_f {e_f:.2e}")
         if k == 10:
-            assert e_x < 1e-11 and e_phi < 1e-11 and e_res < 1e-11
+            record("C1", "f64", e, (1e-11,) * 3)
+            assert max(e) < 1e-11
             np.testing.assert_allclose(to_np(resid), info["rnorm"], rtol=1e-9)
         else:
             rng = np.random.default_rng(12)
@@ -66,8 +79,10 @@ def test_c1_fp64_cold_10_and_20_iterations():
                 xp, _ = O.pcg(S.apply_A, bp, k, jacobi=J)
                 sx = max(sx, rel(xp, x_ref))
                 sf = max(sf, abs(_f(S, b, xp) - _f(S, b, x_ref)) / abs(_f(S, b, x_ref)))
-            say(f"[c1-f64-{k}] oracle one-ulp spread: x {sx:.2e} f {sf:.2e}")
-            assert e_x < max(1e-11, 10 * sx) and e_f < max(1e-13, 10 * sf)
+            say(f"[c1-f64-{k}] oracle one-ulp spread: x {sx:.2e} f {sf:.2e}; "
+                f"GPU e_x {e[0]:.2e} e_f {e_f:.2e}")
+            record("C1-20its", "f64", (e[0], e_f, e[2]), (max(1e-11, 10 * sx), max(1e-13, 10 * sf), 1.0))
+            assert e[0] < max(1e-11, 10 * sx) and e_f < max(1e-13, 10 * sf)
     plan.close()
 
 
@@ -81,14 +96,20 @@ def test_c1_plain_cg_fp64():
     x_ref, _ = O.pcg(S.apply_A, b, 10)
     plan = Plan(cfg, sig, dtype="f64", max_batch=1, precond=False)
     x = to_np(plan.solve(to_dev(s[None, :], torch.float64), n_iter=10)).ravel()
-    assert rel(x, x_ref) < 1e-11
+    e = solve_errors(S, x, x_ref, b)
+    record("C1-cg", "f64", e, (1e-11,) * 3)
+    assert max(e) < 1e-11
     plan.close()
 
 
-@pytest.mark.parametrize("dt,kw", [("f64", {}), ("f32", {}), ("f32", {"resid_replace_every": 5}),
+@pytest.mark.parametrize("dt,kw", [("f64", {}), ("f32", {}), ("f32", {"op_precision": 64}),
+                                   ("f32", {"resid_replace_every": 5}),
                                    ("f64", {"lds_budget": 160 * 1024})],
-                         ids=["f64", "f32", "f32-rr5", "f64-lds160"])
+                         ids=["f64", "f32", "f32-op64", "f32-rr5", "f64-lds160"])
 def test_c2_warm_10_iterations(dt, kw):
+    """The E-ELT system, one frame warm-started from the previous frame's
+    30-iteration reconstruction: FP32 (single-precision operators by default)
+    within a fixed 1e-5, FP64 within 1e-11."""
     require_gpu()
     import torch
     from paper_1302_3734_amd import Plan
@@ -103,36 +124,34 @@ def test_c2_warm_10_iterations(dt, kw):
     s1_in = to_np(to_dev(s1, tdt)).ravel()
     b = S.rhs(s1_in)
     x_ref, info = O.pcg(S.apply_A, b, 10, x0=x0_in, jacobi=J)
-    say(f"[c2-{dt}] solve")
+    say(f"[c2-{dt}{kw}] solve")
     plan = Plan(cfg, sig, dtype=dt, max_batch=1, **kw)
     xt = to_dev(x0_in[None, :], tdt)
     resid = torch.zeros(11, dtype=torch.float64, device="cuda")
     plan.solve(to_dev(s1_in[None, :], tdt), xt, n_iter=10, warm_start=True, resid=resid)
     x = to_np(xt).ravel()
-    e_x, e_phi, e_res = _errors(S, x, x_ref, b)
-    say(f"[c2-{dt}{kw}] e_x {e_x:.2e} e_phi {e_phi:.2e} e_res {e_res:.2e}")
+    e = solve_errors(S, x, x_ref, b)
+    say(f"[c2-{dt}{kw}] e_x {e[0]:.2e} e_phi {e[1]:.2e} e_res {e[2]:.2e}")
     tol = 1e-11 if dt == "f64" else 1e-5
-    assert e_x < tol and e_phi < tol and e_res < tol
+    record("C2" + ("-op64" if kw.get("op_precision") == 64 else ""), dt, e, (tol,) * 3)
+    assert max(e) < tol
     if dt == "f64":
         np.testing.assert_allclose(to_np(resid), info["rnorm"], rtol=1e-9)
     plan.close()
 
 
-def test_c3_batched_fp32_per_frame_and_batch_invariance():
+def test_c3_batched_fp32_every_frame_and_batch_invariance():
     """128 independent C1 frames (own seeded screens and noise) in one batched
-    FP32 solve of 10 iterations captured as a HIP graph: sampled frames within
-    1e-5 of the FP64 oracle -- or, for frames so ill-conditioned that FP32
-    storage alone moves the iterate further, within twice the oracle's own FP32
-    rounding spread -- and bitwise equal to their solo solves."""
+    FP32 solve of 10 iterations captured as a HIP graph: every frame against
+    the FP64 oracle, and sampled frames bitwise equal to their solo solves."""
     require_gpu()
     import torch
     from paper_1302_3734_amd import Plan
     cfg = WL.config_c1()
     B = 128
     S0, sig, _, _ = setup(cfg)
-    S = O.System(cfg, sig)
-    J = S.jacobi_separable()
-    slopes = np.stack([slopes_for(S, cfg, sig, f) for f in range(B)])
+    say("[c3] slopes")
+    slopes = np.stack(oracle_pool_map(oracle_jobs.slopes, [("C1", sig, f, None) for f in range(B)]))
     s32 = to_dev(slopes, torch.float32)
     plan = Plan(cfg, sig, dtype="f32", max_batch=B)
     say("[c3] batched solve (graph)")
@@ -142,18 +161,11 @@ def test_c3_batched_fp32_per_frame_and_batch_invariance():
         plan.solve(s32, out, n_iter=10, graph=True, stream=stream)
     stream.synchronize()
     X = to_np(out).reshape(B, -1)
-    worst = 0.0
-    for f in range(0, B, 11):
-        s_in = to_np(s32[f]).ravel()
-        b = S.rhs(s_in)
-        x_ref, _ = O.pcg(S.apply_A, b, 10, jacobi=J)
-        e = _errors(S, X[f], x_ref, b)
-        tol = fp32_tol(S, b, 10, J)
-        say(f"[c3] frame {f}: e_x {e[0]:.2e} e_phi {e[1]:.2e} e_res {e[2]:.2e} "
-            f"tol {tol[0]:.1e} {tol[1]:.1e} {tol[2]:.1e}")
-        worst = max(worst, max(e))
-        assert all(ei < ti for ei, ti in zip(e, tol)), (f, e, tol)
-    say(f"[c3] worst error {worst:.2e}")
+    S_in = to_np(s32).reshape(B, -1)
+    say("[c3] oracle references")
+    res = oracle_pool_map(oracle_jobs.check, [("C1", sig, S_in[f], None, X[f], 10, "f32")
+                                              for f in range(B)])
+    _check_all("C3", "f32", res, list(range(B)))
     for f in (0, 77, B - 1):
         xs = to_np(plan.solve(s32[f:f + 1].contiguous(), n_iter=10)).ravel()
         assert np.array_equal(xs, X[f]), f
@@ -206,35 +218,44 @@ def test_graph_replay_matches_eager():
     plan.close()
 
 
-def test_c4_mixed_sizes_one_launch():
-    """Frames of four telescope classes packed into one solve: each result
-    bitwise equal to the same frame solved alone, and within 1e-5 (FP32) of
-    the oracle."""
+C4_COUNTS = {"C4-8m-lgs": 2, "C4-8m-ngs": 3, "C4-16m-lgs": 1, "C4-16m-ngs": 2,
+             "C4-39m-lgs": 1, "C4-39m-ngs": 1, "C4-42m-lgs": 2, "C4-42m-ngs": 1}
+
+
+def test_c4_mixed_sizes_one_launch_every_frame():
+    """Frames of all eight telescope classes (8, 16, 39 and 42 m; LGS-only and
+    NGS-only) packed into one solve: every frame bitwise equal to the same
+    frame solved alone, every frame within the FP32 bar of the oracle, and
+    every graph replay equal to the eager result."""
     require_gpu()
     import torch
     from paper_1302_3734_amd import Plan, solve_multi
-    classes = [c for c in WL.config_c4_classes()
-               if c["name"] in ("C4-8m-lgs", "C4-8m-ngs", "C4-16m-ngs", "C4-42m-lgs")]
-    plans, slopes, systems, counts = [], [], [], [1, 2, 1, 1]
-    for cfg, cnt in zip(classes, counts):
+    classes = WL.config_c4_classes()
+    plans, slopes, sigs = [], [], []
+    for cfg in classes:
+        cnt = C4_COUNTS[cfg["name"]]
         S, sig, s, _ = setup(cfg)
-        sl = np.stack([s] + [slopes_for(S, cfg, sig, f) for f in range(1, cnt)])
+        sl = np.stack([s] + oracle_pool_map(oracle_jobs.slopes,
+                                            [(cfg["name"], sig, f, None) for f in range(1, cnt)]))
         plans.append(Plan(cfg, sig, dtype="f32", max_batch=cnt))
         slopes.append(to_dev(sl, torch.float32))
-        systems.append(S)
-    coeffs = [torch.zeros(c, p.n, dtype=torch.float32, device="cuda") for c, p in zip(counts, plans)]
+        sigs.append(sig)
+    coeffs = [torch.zeros(p.max_batch, p.n, dtype=torch.float32, device="cuda") for p in plans]
     say("[c4] multi solve")
     solve_multi(plans, slopes, coeffs, n_iter=10)
-    for i, (p, S) in enumerate(zip(plans, systems)):
+    jobs, frames = [], []
+    for i, (p, cfg) in enumerate(zip(plans, classes)):
         solo = p.solve(slopes[i], n_iter=10)
-        assert torch.equal(solo, coeffs[i]), classes[i]["name"]
-        s_in = to_np(slopes[i][0]).ravel()
-        b = S.rhs(s_in)
-        x_ref, _ = O.pcg(S.apply_A, b, 10, jacobi=S.jacobi_separable())
-        e = _errors(S, to_np(coeffs[i][0]).ravel(), x_ref, b)
-        tol = fp32_tol(S, b, 10, S.jacobi_separable())
-        say(f"[c4] {classes[i]['name']} errors {e} tol {tol}")
-        assert all(ei < ti for ei, ti in zip(e, tol)), (classes[i]["name"], e, tol)
+        assert torch.equal(solo, coeffs[i]), cfg["name"]
+        X = to_np(coeffs[i]).reshape(p.max_batch, -1)
+        S_in = to_np(slopes[i]).reshape(p.max_batch, -1)
+        for f in range(p.max_batch):
+            jobs.append((cfg["name"], sigs[i], S_in[f], None, X[f], 10, "f32"))
+            frames.append((cfg["name"], f))
+    say(f"[c4] oracle references of {len(jobs)} frames")
+    res = oracle_pool_map(oracle_jobs.check, jobs)
+    for (name, f), r in zip(frames, res):
+        _check_all(name, "f32", [r], [f])
     # the same packed solve captured as a graph: every replay equals the eager
     # result, with eager library work and synchronisations between replays
     outs = [torch.empty_like(c) for c in coeffs]
@@ -254,12 +275,12 @@ def test_c4_mixed_sizes_one_launch():
         p.close()
 
 
-def test_c2_batch32_bench_configuration_sampled_frames():
+def test_c2_batch32_bench_configuration_every_frame():
     """The benchmark's launch: E-ELT (C2) FP32, 32 frames of their own seeded
-    noise in one eager solve with the default tiles, 10 warm iterations.
-    Sampled frames are checked against the FP64 oracle one by one (1e-5, or
-    twice the oracle's FP32 rounding spread) and are bitwise equal to their
-    solo solves."""
+    noise in one eager solve with the default plan (single-precision
+    operators, two concurrent halves), 10 warm iterations.  Every frame is
+    checked against the FP64 oracle at the fixed 1e-5 bar; one is bitwise
+    equal to its solo solve."""
     require_gpu()
     import torch
     from paper_1302_3734_amd import Plan
@@ -269,22 +290,19 @@ def test_c2_batch32_bench_configuration_sampled_frames():
     J = S.jacobi_separable()
     x0, _ = O.pcg(S.apply_A, S.rhs(s0), 10, jacobi=J)      # a shared warm start
     x0_in = to_np(to_dev(x0, torch.float32)).ravel()
-    slopes = np.stack([slopes_for(S, cfg, sig, 1 + f, seed_frame=0) for f in range(B)])
+    say("[c2-b32] slopes")
+    slopes = np.stack(oracle_pool_map(oracle_jobs.slopes, [("C2", sig, 1 + f, 0) for f in range(B)]))
     s32 = to_dev(slopes, torch.float32)
     plan = Plan(cfg, sig, dtype="f32", max_batch=B)
     X = to_dev(np.repeat(x0_in[None, :], B, axis=0), torch.float32)
     say("[c2-b32] batched solve")
     plan.solve(s32, X, n_iter=10, warm_start=True)
     Xn = to_np(X).reshape(B, -1)
-    for f in (0, 15, B - 1):
-        s_in = to_np(s32[f]).ravel()
-        b = S.rhs(s_in)
-        x_ref, _ = O.pcg(S.apply_A, b, 10, x0=x0_in, jacobi=J)
-        e = _errors(S, Xn[f], x_ref, b)
-        tol = fp32_tol(S, b, 10, J, x0_in)
-        say(f"[c2-b32] frame {f}: e_x {e[0]:.2e} e_phi {e[1]:.2e} e_res {e[2]:.2e} "
-            f"tol {tol[0]:.1e} {tol[1]:.1e} {tol[2]:.1e}")
-        assert all(ei < ti for ei, ti in zip(e, tol)), (f, e, tol)
+    S_in = to_np(s32).reshape(B, -1)
+    say("[c2-b32] oracle references")
+    res = oracle_pool_map(oracle_jobs.check, [("C2", sig, S_in[f], x0_in, Xn[f], 10, "f32-fixed")
+                                              for f in range(B)])
+    _check_all("C2-b32", "f32", res, list(range(B)))
     xs = to_dev(x0_in[None, :], torch.float32)
     plan.solve(s32[15:16].contiguous(), xs, n_iter=10, warm_start=True)
     assert np.array_equal(to_np(xs).ravel(), Xn[15])
