@@ -255,6 +255,24 @@ int wmcao_solve_multi_graph(const wmcao_plan_t* plans, const void* const* slopes
 int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int batch, int n_iter,
                       int warm_start, double* resid_dev, int* status_dev, void* hip_stream);
 
+/* wmcao_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, with every scratch buffer of the call (b, r, p, A p, the
+ * operator's intermediates, slope sums, partial sums, per-frame scalars and,
+ * if status_dev is NULL, the status) in one fixed device array of the
+ * library, 32 MiB per GPU, held until the process ends.  The call allocates
+ * nothing: no hipMalloc, no new schedule (it uses the first `batch` frames of
+ * the max_batch schedule built with the plan) and no second stream (it runs
+ * on hip_stream only).  Arguments and results are those of wmcao_solve, bit
+ * for bit.  A batch whose scratch exceeds the array returns WMCAO_ERR_SIZE
+ * before any launch (about 11 MB per E-ELT frame with FP32 vectors: 2 frames;
+ * a few hundred KB per 8 m frame).  Every call on one GPU shares that GPU's
+ * array and leaves its contents behind: calls that overlap on one GPU (other
+ * streams, other threads, other plans) race, so callers serialise them. */
+int wmcao_solve_noalloc(wmcao_plan_t plan, const void* slopes, void* coeffs, int batch,
+                        int n_iter, int warm_start, double* resid_dev, int* status_dev,
+                        void* hip_stream);
+
 /* Kernel kinds for per-kernel timing. */
 #define WMCAO_K_IDWT_COARSE 0   /* W^-1, low-pass block in LDS            */
 #define WMCAO_K_IDWT_TILE 1     /* W^-1, one tiled level                  */

@@ -67,6 +67,8 @@ def lib():
         L.wmcao_precond_diag.argtypes = [vp, vp, vp]
         L.wmcao_solve.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
         L.wmcao_solve_graph.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
+        L.wmcao_solve_noalloc.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
+        L.wmcao_solve_noalloc.restype = C.c_int
         for name in ("wmcao_solve_multi", "wmcao_solve_multi_graph"):
             getattr(L, name).argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                          C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int, vp]
@@ -98,7 +100,8 @@ def check(rc, where):
 
 EXPORTED = ("wmcao_plan", "wmcao_sizes", "wmcao_coeffs_to_layers", "wmcao_layers_to_coeffs",
             "wmcao_forward_layers", "wmcao_rhs", "wmcao_apply_A", "wmcao_precond_diag",
-            "wmcao_solve", "wmcao_solve_multi", "wmcao_solve_multi_graph", "wmcao_solve_graph",
+            "wmcao_solve", "wmcao_solve_noalloc", "wmcao_solve_multi", "wmcao_solve_multi_graph",
+            "wmcao_solve_graph",
             "wmcao_profile_enable",
             "wmcao_profile_read", "wmcao_axpby", "wmcao_plan_destroy",
             "wmcao_strerror", "wmcao_last_error")

@@ -182,6 +182,7 @@ void launch_axpby(int64_t n, double a, const T* x, double b, const T* y, T* out,
 template <class S, class D>
 void launch_cast(const S* in, D* out, int64_t n, hipStream_t s);
 
+constexpr size_t NOALLOC_BYTES = size_t(32) << 20;   // scratch of the allocation-free solve
 constexpr int FUSE_LDS = 32 * 1024;   // largest low-pass block a synthesis tile rebuilds
 constexpr int TILE_NT = 256;          // threads of a wavelet tile block
 constexpr int VEC_CHUNK = 2048;   // elements per block of the vector kernels

@@ -171,6 +171,7 @@ struct wmcao_plan_s {
     int adj_taps = 2;     // most nodes feeding one footprint row or column (2 to 4)
     std::vector<int64_t> layer_off, slope_off;
     std::map<std::pair<int, int>, std::unique_ptr<Sched>> sched;   // by (first frame, frames)
+    Sched* full_sched = nullptr;     // max_batch frames, built with the plan
     int streams = 2;                 // 2: solves of >= SPLIT_MIN frames run as two halves
     hipStream_t side = nullptr;      // stream of the second half
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -843,6 +844,80 @@ int enqueue_multi(const wmcao_plan_t* plans, const void* const* slopes, void* co
     return check_launch();
 }
 
+// ------------------------------------------------ allocation-free solve ----
+// Scratch of wmcao_solve_noalloc lives in `scratch`, a file-scope device array
+// of NOALLOC_BYTES: every GPU the library runs on holds its own copy until the
+// process ends.  Host code reaches it only through the device address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in, not a device address), looked up once per device.
+std::mutex g_noalloc_mu;
+constexpr int NOALLOC_DEVICES = 64;
+void* g_noalloc_ptr[NOALLOC_DEVICES] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[wm::NOALLOC_BYTES];
+
+namespace {
+
+// Device address of `scratch` on device dev (which must be current).
+int noalloc_base(int dev, char** out) {
+    if (dev < 0 || dev >= NOALLOC_DEVICES) return fail(WMCAO_ERR_UNSUPPORTED, "device index too large");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(WMCAO_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = static_cast<char*>(g_noalloc_ptr[dev]);
+    return WMCAO_OK;
+}
+
+// Carves the per-frame scratch of a solve of `batch` frames out of base (or,
+// with base NULL, only measures it): the PCG vectors b, r, p, A p, the
+// operator scratch, the slope sums, the partial sums and the per-frame scalars
+// and status.  Returns the bytes needed.
+size_t carve_noalloc(const wmcao_plan_s* p, int batch, char* base, JobPlan* J) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* q = base ? base + off : nullptr;
+        off += (bytes + 255) & ~size_t(255);
+        return static_cast<void*>(q);
+    };
+    const size_t B = static_cast<size_t>(batch);
+    void* vb = take(p->n * p->esz * B);
+    void* vr = take(p->n * p->esz * B);
+    void* vp = take(p->n * p->esz * B);
+    void* vq = take(p->n * p->esz * B);
+    void* vphi = take(p->n * p->osz * B);
+    void* vll = take(p->ll_size * 8 * B);
+    void* vnode = take(p->n_nodes * p->osz * B);
+    void* vu = take(p->n_nodes * 8 * B);
+    void* vfp = take(p->n_fpimg * p->osz * B);
+    void* vsp = take(p->n_spart * 8 * B);
+    void* part = take(sizeof(double) * NPT * p->host.slots * B);
+    void* scal = take(sizeof(double) * 4 * B);
+    void* status = take(sizeof(int) * B);
+    if (J && base) {
+        J->vec[V_B] = vb;
+        J->vec[V_R] = vr;
+        J->vec[V_P] = vp;
+        J->vec[V_Q] = vq;
+        J->vec[V_PHI] = vphi;
+        J->vec[V_LL] = vll;
+        J->vec[V_NODE] = vnode;
+        J->vec[V_U] = vu;
+        J->vec[V_FP] = vfp;
+        J->vec[V_SPART] = vsp;
+        J->part = static_cast<double*>(part);
+        J->alpha = static_cast<double*>(scal);
+        J->status = static_cast<int*>(status);
+    }
+    return off;
+}
+
 }  // namespace
 
 // =================================================================== ABI ====
@@ -1401,6 +1476,13 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         WM_HIP(hipDeviceSynchronize());
     }
 #undef UP
+    // the max_batch schedule (its frame prefixes serve the allocation-free
+    // solve) and this device's address of the allocation-free scratch
+    rc = get_sched(p.get(), p->max_batch, &p->full_sched);
+    if (rc) return rc;
+    char* nb = nullptr;
+    rc = noalloc_base(p->device, &nb);
+    if (rc) return rc;
     *out = p.release();
     return WMCAO_OK;
 }
@@ -1564,6 +1646,54 @@ int wmcao_solve_graph(wmcao_plan_t plan, const void* slopes, void* coeffs, int b
     WM_HIP(hipGraphLaunch(plan->gexec, s));
     WM_HIP(hipEventRecord(plan->gdone, s));
     return WMCAO_OK;
+}
+
+int wmcao_solve_noalloc(wmcao_plan_t plan, const void* slopes, void* coeffs, int batch, int n_iter,
+                        int warm_start, double* resid_dev, int* status_dev, void* hip_stream) {
+    int rc = check_batch(plan, batch);
+    if (rc) return rc;
+    if (!slopes || !coeffs) return fail(WMCAO_ERR_INVALID_ARG, "NULL buffer");
+    if (n_iter < 0) return fail(WMCAO_ERR_INVALID_ARG, "n_iter < 0");
+    const size_t need = carve_noalloc(plan, batch, nullptr, nullptr);
+    if (need > NOALLOC_BYTES)
+        return fail(WMCAO_ERR_SIZE, "wmcao_solve_noalloc: " + std::to_string(batch) + " frames need " +
+                                        std::to_string(need) + " bytes of scratch, more than its " +
+                                        std::to_string(NOALLOC_BYTES) + " bytes");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    DevGuard g(plan->device);
+    char* base = nullptr;
+    rc = noalloc_base(plan->device, &base);
+    if (rc) return rc;
+    const Sched* full = plan->full_sched;
+    if (!full || full->frames != plan->max_batch) return fail(WMCAO_ERR_INVALID_ARG, "plan has no schedule");
+    // the first `batch` frames of the max_batch schedule: every stage's item
+    // list is frame-major, so its prefix is the schedule of those frames
+    Sched v = *full;
+    const int fb = full->frames;
+    auto scale = [&](int cnt) { return cnt / fb * batch; };
+    v.n_coarse = scale(full->n_coarse);
+    v.n_coarse_syn = scale(full->n_coarse_syn);
+    for (int k = 0; k <= WM_MAXLEV; ++k) v.n_tiled[k] = scale(full->n_tiled[k]);
+    v.n_sensor = scale(full->n_sensor);
+    v.n_proj = scale(full->n_proj);
+    v.n_adj = scale(full->n_adj);
+    v.n_vec = scale(full->n_vec);
+    v.frames = batch;
+    JobArgs a{};
+    a.njp = 1;
+    a.jp[0] = make_jobplan(plan, batch);
+    carve_noalloc(plan, batch, base, &a.jp[0]);
+    a.jp[0].vec[V_X] = coeffs;
+    a.jp[0].vec[V_SLOPES] = const_cast<void*>(slopes);
+    if (status_dev) a.jp[0].status = status_dev;
+    a.jp[0].resid = resid_dev;
+    a.jp[0].resid_ld = n_iter + 1;
+    ProfScope ps(nullptr);   // no event timing: it would create events
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    with_types(plan, [&]<class T, class Sv>() {
+        run_solve<T, Sv>(a, v, n_iter, warm_start, plan->resid_replace, plan->c64, s);
+    });
+    return check_launch();
 }
 
 int wmcao_solve_multi(const wmcao_plan_t* plans, const void* const* slopes, void* const* coeffs,
