@@ -106,18 +106,25 @@ def pctl(v, q):
     return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
 
 
-def served_stream(duration_s, rate_hz, n_iter, plain_fp64=False):
+SERVED = ["C4-8m-ngs", "C4-16m-ngs", "C4-39m-lgs", "C4-42m-lgs"]
+# one lane per configuration: measured faster than packing the two E-ELT-class
+# configurations into one lane (their launches overlap on two lanes)
+SERVED_LANES = {"C4-8m-ngs": 0, "C4-16m-ngs": 1, "C4-39m-lgs": 2, "C4-42m-lgs": 3}
+
+
+def served_stream(duration_s, rate_hz, n_iter, dtype="f32", plain=False, tuned=True):
     """Poisson arrivals over four telescope configurations (8 m and 16 m
     NGS-only, 39 m and 42 m LGS-only), one stream each at rate_hz/4, served
-    with continuous batching in FP32 (one HIP stream per configuration,
-    backlogs batched); frozen-flow frames from a pool of 8 per stream.  With
-    plain_fp64 the same arrivals are served the plain way instead: FP64, one
-    frame per launch, one launch at a time.  Returns latency percentiles and
-    throughput."""
+    with continuous batching (one lane per configuration, two launches in
+    flight per lane, backlogs batched); frozen-flow frames from a pool of 8
+    per stream.  The
+    same server runs in FP32 or FP64.  With plain, the arrivals are served the
+    plain way instead: one frame per launch, one launch at a time (FP64).
+    Returns latency percentiles and throughput."""
     import torch
     from paper_1302_3734_amd import Plan
     from paper_1302_3734_amd.serve import Server
-    names = ["C4-8m-ngs", "C4-16m-ngs", "C4-39m-lgs", "C4-42m-lgs"]
+    names = SERVED
     cfgs, pools = {}, {}
     for nm in names:
         cfg = WL.config_by_name(nm)
@@ -132,16 +139,16 @@ def served_stream(duration_s, rate_hz, n_iter, plain_fp64=False):
                                           for m in range(len(sig))]), device="cuda")
         pools[nm] = [(lay[t] + sv * torch.tensor(WL.noise_draw(cfg["cfg_id"], t, fwd.n_slopes),
                                                  device="cuda")) for t in range(8)]
-        if not plain_fp64:
+        if dtype == "f32":
             pools[nm] = [v.float() for v in pools[nm]]
         cfgs[nm] = (cfg, sig)
         fwd.close()
-    if plain_fp64:
-        srv = Server(cfgs, {nm: nm for nm in names}, dtype="f64", n_iter=n_iter, hip_streams=1,
-                     tile=16, pack=False, depth=1, max_frames=1)
+    if plain:
+        srv = Server(cfgs, {nm: nm for nm in names}, dtype=dtype, n_iter=n_iter, hip_streams=1,
+                     pack=False, depth=1, max_frames=1, tuned=tuned)
     else:
-        srv = Server(cfgs, {nm: nm for nm in names}, dtype="f32", n_iter=n_iter, hip_streams=4,
-                     tile=16, pack=True)
+        srv = Server(cfgs, {nm: nm for nm in names}, dtype=dtype, n_iter=n_iter,
+                     lane_map=SERVED_LANES, pack=True, depth=2, max_frames=4, tuned=tuned)
     switch = sys.getswitchinterval()
     sys.setswitchinterval(1e-4)       # hand the interpreter lock to the server threads promptly
     arrivals = sorted((t, nm) for k, nm in enumerate(names)
@@ -163,17 +170,23 @@ def served_stream(duration_s, rate_hz, n_iter, plain_fp64=False):
     srv.close()
     lat = srv.latencies_ms()
     wait, run = srv.waits_ms()
-    return {"mode": ("plain FP64, one frame per launch, one launch at a time" if plain_fp64 else
-                     "FP32 continuous batching, one HIP stream per configuration"),
-            "configs": names, "rate_hz": rate_hz, "duration_s": duration_s, "frames": len(lat),
-            "frames_per_s": round(len(lat) / elapsed, 1),
+    per_cfg = {}
+    for nm in names:
+        lv = [1e3 * (r[3] - r[2]) for r in srv.records if r[0] == nm]
+        per_cfg[nm] = {"p50_ms": round(pctl(lv, 0.5), 4), "p99_ms": round(pctl(lv, 0.99), 4)}
+    mode = ("plain FP64, one frame per launch, one launch at a time" if plain else
+            f"{dtype.upper()} continuous batching: lanes {SERVED_LANES}, depth 2, up to 4 "
+            f"frames per telescope stream per launch")
+    return {"mode": mode, "configs": names, "rate_hz": rate_hz, "duration_s": duration_s,
+            "frames": len(lat), "frames_per_s": round(len(lat) / elapsed, 1),
             "p50_frame_latency_ms": round(pctl(lat, 0.5), 4),
             "p99_frame_latency_ms": round(pctl(lat, 0.99), 4),
             "p99_queue_wait_ms": round(pctl(wait, 0.99), 4),
             "p50_launch_to_result_ms": round(pctl(run, 0.5), 4),
             "p99_launch_to_result_ms": round(pctl(run, 0.99), 4),
             "launches": srv.launches,
-            "mean_frames_per_launch": round(float(np.mean(srv.frames_in_launch)), 3)}
+            "mean_frames_per_launch": round(float(np.mean(srv.frames_in_launch)), 3),
+            "per_config": per_cfg, "work_shapes": srv.work_shapes}
 
 
 # Stages of one operator apply and of the PCG updates, the library kernels
@@ -452,7 +465,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=32, help="frames per step")
     ap.add_argument("--iters", type=int, default=10, help="PCG iterations per frame")
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0, help="wavelet tile edge (0: autotuned)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="library default work shapes instead of autotuned ones")
     ap.add_argument("--streams", type=int, default=0,
                     help="plan streams: 1 one stream, 2 two concurrent half batches, 0 library default")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -514,8 +529,22 @@ def main():
     slopes32 = slopes64.float().contiguous()
     print("[bench] inputs ready", flush=True)
 
+    # ---- work shapes: autotuned for this device, configuration and batch -----
+    from paper_1302_3734_amd import autotune
+
+    def shapes(dtype, batch, **kw):
+        sh = dict(autotune.DEFAULTS) if args.no_tune else autotune.tune(cfg, sig, dtype, batch, IT, **kw)
+        if args.tile:
+            sh["tile"] = args.tile
+        return sh
+
+    t_tune = time.perf_counter()
+    shapes32 = shapes("f32", B, streams=args.streams)
+    print(f"[bench] work shapes for {B} frames: {shapes32} ({time.perf_counter() - t_tune:.1f} s)",
+          flush=True)
+
     # ---- batched FP32 plan --------------------------------------------------
-    p32 = Plan(cfg, sig, dtype="f32", max_batch=B, tile=args.tile, streams=args.streams)
+    p32 = Plan(cfg, sig, dtype="f32", max_batch=B, streams=args.streams, **shapes32)
     X = torch.zeros(B, n, dtype=torch.float32, device="cuda")
     p32.solve(slopes32[0], X, n_iter=30)           # frame 0 of every stream from zero
     torch.cuda.synchronize()
@@ -557,7 +586,7 @@ def main():
     # On one stream (the same kernels over the whole batch of B frames), so a
     # launch's event time is its own: with two concurrent halves it would also
     # hold the other half's kernels.
-    p1 = p32 if not halves else Plan(cfg, sig, dtype="f32", max_batch=B, tile=args.tile, streams=1)
+    p1 = p32 if not halves else Plan(cfg, sig, dtype="f32", max_batch=B, streams=1, **shapes32)
 
     def step1(i):
         t = 1 + (i % N_FRAMES_ROT)
@@ -617,7 +646,7 @@ def main():
             plan.solve(frames_all[0, :1].contiguous(), x1, n_iter=30)
             torch.cuda.synchronize()
             stream = torch.cuda.Stream()
-            lat, nf = [], 40
+            lat, nf = [], 100
             frames = [frames_all[1 + (i % N_FRAMES_ROT), :1].contiguous() for i in range(nf)]
             buf = torch.empty_like(frames[0])
             with torch.cuda.stream(stream):
@@ -655,10 +684,12 @@ def main():
             ls = sorted(e0.elapsed_time(e) for e in ends)
             return pctl(ls, 0.5), pctl(ls, 0.99), ls[-1]
 
-        p64 = Plan(cfg, sig, dtype="f64", max_batch=1, tile=16)
+        shapes1_64 = shapes("f64", 1)
+        shapes1_32 = shapes("f32", 1)
+        p64 = Plan(cfg, sig, dtype="f64", max_batch=1, **shapes1_64)
         fps64, p99_64 = per_frame(p64, slopes64, torch.float64)
         b50, b99, bmax = burst(p64, slopes64, torch.float64, B)
-        q32 = Plan(cfg, sig, dtype="f32", max_batch=1, tile=16)
+        q32 = Plan(cfg, sig, dtype="f32", max_batch=1, **shapes1_32)
         fps32, p99_32 = per_frame(q32, slopes32, torch.float32)
         q32.close()
         # equal reconstruction: FP32 and FP64 solves of stream 0 frame 1, both
@@ -676,10 +707,10 @@ def main():
         rms_0, _ = onaxis_residual(cfg, np.zeros_like(tr), tr)
         result["fp64_per_frame"] = {"frames_per_s": round(fps64, 2),
                                     "p99_frame_latency_ms": round(p99_64, 4),
-                                    "mode": "batch 1, hipGraph replay, tile 16"}
+                                    "mode": "batch 1, hipGraph replay", "work_shapes": shapes1_64}
         result["fp32_per_frame"] = {"frames_per_s": round(fps32, 2),
                                     "p99_frame_latency_ms": round(p99_32, 4),
-                                    "mode": "batch 1, hipGraph replay, tile 16"}
+                                    "mode": "batch 1, hipGraph replay", "work_shapes": shapes1_32}
         print(f"[bench] per frame: FP64 {fps64:.1f} frames/s p99 {p99_64:.3f} ms; "
               f"FP32 {fps32:.1f} frames/s p99 {p99_32:.3f} ms", flush=True)
         result["burst"] = {
@@ -718,11 +749,16 @@ def main():
                   f"cold {v['strehl_K_cold']}", flush=True)
 
     if args.serve_seconds > 0:
-        result["served"] = served_stream(args.serve_seconds, args.serve_rate, IT)
+        tuned = not args.no_tune
+        result["served"] = served_stream(args.serve_seconds, args.serve_rate, IT, "f32", tuned=tuned)
         print(f"[bench] served {result['served']}", flush=True)
         if not args.no_fp64:
+            result["served_fp64"] = served_stream(args.serve_seconds, args.serve_rate, IT, "f64",
+                                                  tuned=tuned)
+            print(f"[bench] served FP64 (same server) {result['served_fp64']}", flush=True)
             result["served_plain_fp64"] = served_stream(min(2.0, args.serve_seconds),
-                                                        args.serve_rate, IT, plain_fp64=True)
+                                                        args.serve_rate, IT, "f64", plain=True,
+                                                        tuned=tuned)
             print(f"[bench] served plain FP64 {result['served_plain_fp64']}", flush=True)
 
     out = {
@@ -741,7 +777,11 @@ def main():
         "config": {"workload": "E-ELT 42 m, 6 LGS 84x84 + 3 TT NGS, 9 layers 128-256 px, "
                                "db3 5 levels, Jacobi PCG 10 its warm",
                    "frames_per_step": B, "pcg_iters": IT, "n_unknowns": n, "n_slopes": ns,
-                   "concurrent_halves": bool(halves)},
+                   "concurrent_halves": bool(halves),
+                   "precision": "FP32 vectors and operator storage; W^-1 and P^T in FP32, "
+                                "W and every inner product and step scalar in FP64",
+                   "work_shapes": shapes32, "work_shapes_source": "defaults" if args.no_tune
+                   else "autotuned on this device"},
         "p50_frame_latency_ms": round(p50, 4),
         "p99_frame_latency_ms": round(p99, 4),
         "roofline": {"bound": "hbm", "kernel": dom, "kernels": D["kernels"],

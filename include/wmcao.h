@@ -163,7 +163,17 @@ typedef struct {
  *                         2 (P^T) and 4 (W, with the sum of the P^T images);
  *                         -1 = library default (4: the forward transform takes
  *                         small differences of the summed P^T image, the other
- *                         two stages run in FP32). */
+ *                         two stages run in FP32).
+ *   proj_rows             sensor node rows per work item of the projection and
+ *                         the noise weighting: 4 or 8 (0 = 8)
+ *   vec_chunk             vector elements per work item of the PCG updates:
+ *                         1024, 2048, 4096 or 8192 (0 = 2048)
+ *   adj_lds               LDS bytes one adjoint-projection work item may use
+ *                         for its staged node rows and row pass, 8 KiB to
+ *                         96 KiB (0 = 32 KiB); fewer footprint rows per item
+ *                         when smaller
+ * tile, lds_budget, streams and the last three change only how the work is
+ * cut and in which order partial sums are formed; results agree to rounding. */
 typedef struct {
     double alpha;
     double r0_m;
@@ -177,6 +187,9 @@ typedef struct {
     int streams;
     int op_precision;
     int op_fp64_stages;
+    int proj_rows;
+    int vec_chunk;
+    int adj_lds;
 } wmcao_options;
 
 /* Build a plan on the current HIP device: validates the geometry, builds the

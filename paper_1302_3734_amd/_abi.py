@@ -37,7 +37,8 @@ class Options(C.Structure):
     _fields_ = [("alpha", C.c_double), ("r0_m", C.c_double), ("L0_m", C.c_double),
                 ("dtype", C.c_int), ("max_batch", C.c_int), ("resid_replace_every", C.c_int),
                 ("precond", C.c_int), ("tile", C.c_int), ("lds_budget", C.c_int),
-                ("streams", C.c_int), ("op_precision", C.c_int), ("op_fp64_stages", C.c_int)]
+                ("streams", C.c_int), ("op_precision", C.c_int), ("op_fp64_stages", C.c_int),
+                ("proj_rows", C.c_int), ("vec_chunk", C.c_int), ("adj_lds", C.c_int)]
 
 
 class WmcaoError(RuntimeError):

@@ -72,6 +72,8 @@ struct WfsInfo {
 struct PlanDev {
     int L, W, levels, dtype;
     int op64;               // 1: operator storage S = double, 0: S = float
+    int proj_rows;          // sensor node rows per work item of the projection and weighting
+    int vec_chunk;          // elements per work item of the vector kernels
     int precond;
     int n_fdwt_slots;       // partial slots written by one wavelet-analysis pass per frame
     int pq_base;            // first of the L per-layer <p, Ap> totals
@@ -185,18 +187,19 @@ void launch_cast(const S* in, D* out, int64_t n, hipStream_t s);
 constexpr size_t NOALLOC_BYTES = size_t(32) << 20;   // scratch of the allocation-free solve
 constexpr int FUSE_LDS = 32 * 1024;   // largest low-pass block a synthesis tile rebuilds
 constexpr int TILE_NT = 256;          // threads of a wavelet tile block
-constexpr int VEC_CHUNK = 2048;   // elements per block of the vector kernels
-constexpr int PROJ_ROWS = 8;      // sensor node rows per block of the projection
+constexpr int VEC_CHUNK = 2048;   // default elements per work item of the vector kernels
+constexpr int PROJ_ROWS = 8;      // default (and most) node rows per projection work item
+constexpr int PROJ_ROWS_MIN = 4;  // fewest node rows per projection work item
 
 // Dynamic LDS of k_weights for a sensor of nn nodes and ns subapertures per
 // side: the band's node rows with one halo row on each side and the weighted
 // x and y slopes of the subaperture rows next to the band (FP64).
-constexpr int weights_lds_bytes(int nn, int ns) {
-    return ((PROJ_ROWS + 2) * nn + 2 * (PROJ_ROWS + 1) * ns) * 8;
+constexpr int weights_lds_bytes(int nn, int ns, int rows) {
+    return ((rows + 2) * nn + 2 * (rows + 1) * ns) * 8;
 }
 constexpr int SP_K = 2 * WM_MAXCELL;   // doubles per slope-sum record
 constexpr int ADJ_BAND = 32;      // footprint rows per adjoint work item (at most)
 constexpr int ADJ_TAPS_MAX = 4;   // most fast-path taps of the adjoint
-constexpr int ADJ_LDS = 32 * 1024;   // LDS of the adjoint's row-pass buffer (at most)
+constexpr int ADJ_LDS = 32 * 1024;   // default LDS of the adjoint's staged rows and row-pass buffer
 
 }  // namespace wm

@@ -741,7 +741,7 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
 // --------------------------------------------------------- projection ----
 // P: sensor node field u_m = sum over layers of the bilinear samples of each
 // layer at the node's projected position (Sec. 2.1, cone factor for LGS), in
-// FP64.  One block per (frame, sensor, band of PROJ_ROWS node rows).  With
+// FP64.  One block per (frame, sensor, band of P.proj_rows node rows).  With
 // sums set (operator applies), the block also forms the Fried slopes of the
 // band's subapertures (Sec. 2.2; one extra halo node row) and writes their
 // sums for the tip/tilt projection and the low-order cells (one record per
@@ -767,10 +767,11 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
     const int m = it.a;
     const WfsInfo& w = P.wfs[m];
     const int nn = w.nn, L = P.L;
-    const int r0 = it.b * PROJ_ROWS;
-    const int rows = min(PROJ_ROWS, nn - r0);
+    const int PR = P.proj_rows;
+    const int r0 = it.b * PR;
+    const int rows = min(PR, nn - r0);
     const bool slopes = sums && w.kind == 0;
-    const int rows_c = slopes ? min(PROJ_ROWS + 1, nn - r0) : rows;
+    const int rows_c = slopes ? min(PR + 1, nn - r0) : rows;
     const int K = rows_c + nn;
     if (threadIdx.x < L) {
         lay_n[threadIdx.x] = P.layer[threadIdx.x].N;
@@ -821,7 +822,7 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
     __syncthreads();
     const int ns = w.n_sub;
     double* rec = vptr<double>(J, V_SPART, it.frame) + w.sp_off + it.b * SP_K;
-    const int nsub_rows = min(PROJ_ROWS, min(ns - r0, rows_c - 1));
+    const int nsub_rows = min(PR, min(ns - r0, rows_c - 1));
     if (!w.agg) {
         Acc p0 = 0, p1 = 0, p2 = 0, p3 = 0;
         for (int e = threadIdx.x; e < nsub_rows * ns; e += blockDim.x) {
@@ -884,22 +885,23 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
 template <class T, class SO>
 __global__ void __launch_bounds__(256)
 k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
-    // su, swx, swy: dynamic LDS of weights_lds_bytes(nn, ns) for this sensor
+    // su, swx, swy: dynamic LDS of weights_lds_bytes(nn, ns, rows) for this sensor
     // (the launch gives the largest over its sensors)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double cval[2 * WM_MAXCELL], cwx[WM_MAXCELL], cwy[WM_MAXCELL];
-    __shared__ double srec[((WM_NSUB_MAX + 1 + PROJ_ROWS - 1) / PROJ_ROWS) * SP_K];
+    __shared__ double srec[((WM_NSUB_MAX + 1 + PROJ_ROWS_MIN - 1) / PROJ_ROWS_MIN) * SP_K];
     const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const int m = it.a;
     const WfsInfo& w = P.wfs[m];
     const int nn = w.nn, ns = w.n_sub;
-    const int r0 = it.b * PROJ_ROWS;
-    const int rows = min(PROJ_ROWS, nn - r0);
+    const int PR = P.proj_rows;
+    const int r0 = it.b * PR;
+    const int rows = min(PR, nn - r0);
     double* su = reinterpret_cast<double*>(smem_raw);
-    double* swx = su + (PROJ_ROWS + 2) * nn;
-    double* swy = swx + (PROJ_ROWS + 1) * ns;
+    double* swx = su + (PR + 2) * nn;
+    double* swy = swx + (PR + 1) * ns;
     const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
     SO* vout = vptr<SO>(J, out_vec, it.frame) + w.node_off;
     if (w.kind == 1) {
@@ -910,10 +912,10 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
         }
         return;
     }
-    const int ua = max(r0 - 1, 0), ub = min(r0 + PROJ_ROWS, nn - 1);
+    const int ua = max(r0 - 1, 0), ub = min(r0 + PR, nn - 1);
     for (int e = threadIdx.x; e < (ub - ua + 1) * nn; e += blockDim.x) su[e] = ug[ua * nn + e];
     // the band records of this sensor, gathered in parallel
-    const int nb = (nn + PROJ_ROWS - 1) / PROJ_ROWS;
+    const int nb = (nn + PR - 1) / PR;
     const int K = w.agg ? 2 * w.S : 4;
     {
         const double* rec = vptr<double>(J, V_SPART, it.frame) + w.sp_off;
@@ -982,7 +984,7 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     }
     __syncthreads();
     // weighted slopes of subaperture rows ia..ib (the rows next to the band)
-    const int ia = ua, ib = min(r0 + PROJ_ROWS - 1, ns - 1);
+    const int ia = ua, ib = min(r0 + PR - 1, ns - 1);
     for (int e = threadIdx.x; e < (ib - ia + 1) * ns; e += blockDim.x) {
         const int li = e / ns, j = e % ns;
         const int i = ia + li;
@@ -1400,7 +1402,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
 // ------------------------------------------------------------- PCG steps ----
 // The vector kernels move 4 consecutive elements per access (16 B for FP32,
 // 2 x 16 B for FP64) when the frame length is a multiple of 4; otherwise
-// element by element.  One block covers VEC_CHUNK elements of one frame.
+// element by element.  One block covers P.vec_chunk elements of one frame.
 // True when the frame length is a multiple of 4 and every pointer allows
 // 16-byte accesses (a caller's vector may be any element-aligned address).
 __device__ __forceinline__ bool can_vec4(int64_t n, std::initializer_list<const void*> ptrs) {
@@ -1462,12 +1464,13 @@ k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
     const T* jac = reinterpret_cast<const T*>(P.jac);
     const bool vec = can_vec4(P.n, {x, b, q, r, p, jac});
     Acc rz = 0.0, rr = 0.0;
-    const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
+    const int chunk = P.vec_chunk;
+    const int64_t i0 = static_cast<int64_t>(it.b) * chunk;
     const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
     const bool pre_ = P.precond != 0;
     auto sweep = [&](auto vec_tag) {
         constexpr bool VEC = decltype(vec_tag)::value;
-        for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
+        for (int k = 4 * threadIdx.x; k < chunk; k += 4 * blockDim.x) {
             const int64_t i = i0 + k;
             if (i >= n_) break;
             Acc bv[4], qv[4], jv[4];
@@ -1551,12 +1554,13 @@ k_update_r(const JobArgs args, const Item* __restrict__ items, int iter, int fre
     const T* jac = reinterpret_cast<const T*>(P.jac);
     const bool vec = can_vec4(P.n, {r, q, jac});
     Acc rz = 0.0, rr = 0.0;
-    const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
+    const int chunk = P.vec_chunk;
+    const int64_t i0 = static_cast<int64_t>(it.b) * chunk;
     const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
     const bool pre_ = P.precond != 0;
     auto sweep = [&](auto vec_tag) {
         constexpr bool VEC = decltype(vec_tag)::value;
-        for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
+        for (int k = 4 * threadIdx.x; k < chunk; k += 4 * blockDim.x) {
             const int64_t i = i0 + k;
             if (i >= n_) break;
             Acc rv[4], qv[4], jv[4];
@@ -1621,12 +1625,13 @@ k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
     const T* r = vptr<T>(J, V_R, it.frame);
     const T* jac = reinterpret_cast<const T*>(P.jac);
     const bool vec = can_vec4(P.n, {x, p, r, jac});
-    const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
+    const int chunk = P.vec_chunk;
+    const int64_t i0 = static_cast<int64_t>(it.b) * chunk;
     const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
     const bool pre_ = P.precond != 0;
     auto sweep = [&](auto vec_tag) {
         constexpr bool VEC = decltype(vec_tag)::value;
-        for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
+        for (int k = 4 * threadIdx.x; k < chunk; k += 4 * blockDim.x) {
             const int64_t i = i0 + k;
             if (i >= n_) break;
             Acc pv[4], xv[4], rv[4], jv[4];
@@ -1666,12 +1671,13 @@ k_replace_r(const JobArgs args, const Item* __restrict__ items, int iter) {
     const T* jac = reinterpret_cast<const T*>(P.jac);
     const bool vec = can_vec4(P.n, {b, q, r, jac});
     Acc rz = 0.0, rr = 0.0;
-    const int64_t i0 = static_cast<int64_t>(it.b) * VEC_CHUNK;
+    const int chunk = P.vec_chunk;
+    const int64_t i0 = static_cast<int64_t>(it.b) * chunk;
     const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
     const bool pre_ = P.precond != 0;
     auto sweep = [&](auto vec_tag) {
         constexpr bool VEC = decltype(vec_tag)::value;
-        for (int k = 4 * threadIdx.x; k < VEC_CHUNK; k += 4 * blockDim.x) {
+        for (int k = 4 * threadIdx.x; k < chunk; k += 4 * blockDim.x) {
             const int64_t i = i0 + k;
             if (i >= n_) break;
             Acc bv[4], qv[4], jv[4];

@@ -168,6 +168,7 @@ struct wmcao_plan_s {
     int64_t n_spart = 0;  // doubles of the per-band slope sums of one frame
     int lds_adjoint[2] = {};  // staged rows + row-pass buffer of the adjoint, FP32 / FP64 arithmetic
     int c64 = 7;              // stages computing in FP64 (C_IDWT | C_ADJ | C_FDWT)
+    int adj_lds = ADJ_LDS;    // LDS budget of one adjoint work item
     int adj_taps = 2;     // most nodes feeding one footprint row or column (2 to 4)
     std::vector<int64_t> layer_off, slope_off;
     std::map<std::pair<int, int>, std::unique_ptr<Sched>> sched;   // by (first frame, frames)
@@ -315,13 +316,13 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
             taps_a = std::max(taps_a, P->adj_taps);
             for (int m = 0; m < P->W; ++m) {
                 sensor.push_back(Item{jp, f, m, 0, 0, 0, 0, 0});
-                const int nb = ceil_div(P->host.wfs[m].nn, PROJ_ROWS);
+                const int nb = ceil_div(P->host.wfs[m].nn, P->host.proj_rows);
                 for (int b = 0; b < nb; ++b) proj.push_back(Item{jp, f, m, b, 0, 0, 0, 0});
                 const int nn = P->host.wfs[m].nn;
                 lds_s = std::max(lds_s, static_cast<int>(nn * nn * sizeof(double)));
-                lds_w = std::max(lds_w, weights_lds_bytes(nn, P->host.wfs[m].n_sub));
+                lds_w = std::max(lds_w, weights_lds_bytes(nn, P->host.wfs[m].n_sub, P->host.proj_rows));
             }
-            const int nch = static_cast<int>((P->n + VEC_CHUNK - 1) / VEC_CHUNK);
+            const int nch = static_cast<int>((P->n + P->host.vec_chunk - 1) / P->host.vec_chunk);
             for (int c = 0; c < nch; ++c) vec.push_back(Item{jp, f, 0, c, c, 0, 0, 0});
         }
         // bytes each launch reads and writes as designed (see the kernel table
@@ -967,6 +968,13 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         return fail(WMCAO_ERR_INVALID_ARG, "FP64 plans have FP64 operators");
     if (opts->op_fp64_stages < -1 || opts->op_fp64_stages > 7)
         return fail(WMCAO_ERR_INVALID_ARG, "op_fp64_stages must be -1 or a mask of 1, 2 and 4");
+    if (opts->proj_rows != 0 && opts->proj_rows != 4 && opts->proj_rows != 8)
+        return fail(WMCAO_ERR_INVALID_ARG, "proj_rows must be 0, 4 or 8");
+    if (opts->vec_chunk != 0 && opts->vec_chunk != 1024 && opts->vec_chunk != 2048 &&
+        opts->vec_chunk != 4096 && opts->vec_chunk != 8192)
+        return fail(WMCAO_ERR_INVALID_ARG, "vec_chunk must be 0, 1024, 2048, 4096 or 8192");
+    if (opts->adj_lds != 0 && (opts->adj_lds < 8 * 1024 || opts->adj_lds > 96 * 1024))
+        return fail(WMCAO_ERR_INVALID_ARG, "adj_lds must be 0 or 8 KiB .. 96 KiB");
     if (!(pupil->diameter_m > 0.0) || pupil->obstruction_ratio < 0.0 || pupil->obstruction_ratio >= 1.0)
         return fail(WMCAO_ERR_INVALID_ARG, "pupil");
     bool seen_ngs = false;
@@ -1034,6 +1042,9 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     H.levels = levels;
     H.dtype = opts->dtype;
     H.op64 = p->op64;
+    H.proj_rows = opts->proj_rows ? opts->proj_rows : PROJ_ROWS;
+    H.vec_chunk = opts->vec_chunk ? opts->vec_chunk : VEC_CHUNK;
+    p->adj_lds = opts->adj_lds ? opts->adj_lds : ADJ_LDS;
     H.precond = opts->precond;
     H.alpha = opts->alpha;
     db3_filters(H.h, H.g);
@@ -1180,7 +1191,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             for (int q = 0; q < I.S; ++q) I.bsum[k] += blocksd[3 * (I.boff + q) + k];
         }
         I.sp_off = static_cast<int>(p->n_spart);
-        p->n_spart += static_cast<int64_t>(ceil_div(nn, PROJ_ROWS)) * SP_K;
+        p->n_spart += static_cast<int64_t>(ceil_div(nn, H.proj_rows)) * SP_K;
         soff += (I.kind == 1 ? 1 : 2) * I.S;
         p->slope_off.push_back(soff);
         I.node_off = noff;
@@ -1247,7 +1258,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     // adjoint footprints (Sec. 2.1 read backwards): per (sensor, layer) the
     // pixel rectangle the nodes' bilinear stencils reach, the node range that
     // feeds each of its rows and columns, and the rows per work item that keep
-    // the staged node rows and the row-pass buffer within ADJ_LDS
+    // the staged node rows and the row-pass buffer within the plan's adjoint LDS
     std::vector<int> fprc;
     for (int m = 0; m < n_wfs; ++m) {
         const int nn = H.wfs[m].nn;
@@ -1308,7 +1319,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
                     const int vbytes = ahi < alo ? 0 : ((ahi - alo + ADJ_TAPS_MAX) * nn * 8 + 15) & ~15;
                     need = std::max(need, vbytes + rows * nn * 8);
                 }
-                if (need <= ADJ_LDS) break;
+                if (need <= p->adj_lds) break;
             }
             if (br < 1)
                 return fail(WMCAO_ERR_UNSUPPORTED, "sensor footprint too wide for the adjoint projection");
@@ -1412,7 +1423,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         }
         H.pq_base = nf;   // per-layer totals follow the tile partials
         H.n_fdwt_slots = nf + n_layers;
-        H.n_vec_slots = static_cast<int>((p->n + VEC_CHUNK - 1) / VEC_CHUNK);
+        H.n_vec_slots = static_cast<int>((p->n + H.vec_chunk - 1) / H.vec_chunk);
         H.slots = std::max(H.n_fdwt_slots, H.n_vec_slots);
     }
     const int B = p->max_batch;

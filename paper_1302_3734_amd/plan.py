@@ -32,7 +32,7 @@ class Plan:
 
     def __init__(self, cfg, sigmas, dtype="f64", max_batch=1, cinv_blocks=None,
                  precond=True, resid_replace_every=0, tile=0, lds_budget=0, streams=0,
-                 op_precision=0, op_fp64_stages=-1):
+                 op_precision=0, op_fp64_stages=-1, proj_rows=0, vec_chunk=0, adj_lds=0):
         lib = _abi.lib()
         code, self.torch_dtype = _DT[dtype]
         self.dtype = dtype
@@ -63,7 +63,7 @@ class Plan:
         opts = _abi.Options(cfg["alpha"], cfg["r0"], cfg["L0"], code, self.max_batch,
                             int(resid_replace_every), 1 if precond else 0, int(tile),
                             int(lds_budget), int(streams), int(op_precision),
-                            int(op_fp64_stages))
+                            int(op_fp64_stages), int(proj_rows), int(vec_chunk), int(adj_lds))
         h = C.c_void_p()
         rc = lib.wmcao_plan(C.byref(pupil), Ls, len(layers), Ws, len(wfs), _abi.Wavelet(0, 3),
                             int(cfg["levels"]), C.byref(opts), C.byref(h))

@@ -75,11 +75,13 @@ class Server:
     invariance checks).  graphs: replay captured launches.  tile: tile edge of
     the wavelet kernels (0 = library default; 16 favours latency).  pack: when
     a lane serves several configurations, put their frames into one launch;
-    otherwise one configuration per launch, in turn."""
+    otherwise one configuration per launch, in turn.  tuned: each
+    configuration's plan takes the work shapes the autotuner finds for
+    single-frame solves on this device (tile is then ignored)."""
 
     def __init__(self, configs, streams, dtype="f32", n_iter=10, hip_streams=None,
                  hbm_budget=None, keep_inputs=False, graphs=True, tile=0, pack=True, depth=2,
-                 max_frames=8, lane_map=None):
+                 max_frames=8, lane_map=None, tuned=False):
         self.dtype = dtype
         self.n_iter = int(n_iter)
         self.keep_inputs = keep_inputs
@@ -103,8 +105,14 @@ class Server:
         # the concurrency: plans that also split large batches onto a second
         # stream of their own made served frames slower (p50 1.2 to 3.0 ms at
         # 2000 frames/s), so the plans here use one stream each.
+        shapes = {c: {"tile": tile} for c in names}
+        if tuned:
+            from . import autotune
+            shapes = {c: autotune.tune(configs[c][0], configs[c][1], dtype, 1, self.n_iter, streams=1)
+                      for c in names}
+        self.work_shapes = shapes
         self.plans = {c: Plan(configs[c][0], configs[c][1], dtype=dtype, max_batch=count[c],
-                              tile=tile, streams=1) for c in names}
+                              streams=1, **shapes[c]) for c in names}
         self.n = {c: p.n for c, p in self.plans.items()}
         self.n_slopes = {c: p.n_slopes for c, p in self.plans.items()}
         tdt = self.plans[names[0]].torch_dtype
@@ -118,13 +126,24 @@ class Server:
                       for c in names}
         if graphs:
             # capture the one-configuration launches up front, so that no frame
-            # waits for a graph to be recorded
+            # waits for a graph to be recorded; on a lane that packs two
+            # configurations, every combination of frame counts too
             for c, plan in self.plans.items():
                 Sb, Xb = self.stage[c]
                 with torch.cuda.stream(self.lanes[self.lane_of[c]]):
                     for k in range(1, count[c] + 1):
                         solve_multi([plan], [Sb[:k]], [Xb[:k]], n_iter=self.n_iter,
                                     warm_start=True, graph=True)
+            for lane, cs in enumerate(self.lane_cfgs):
+                if not pack or len(cs) != 2:
+                    continue
+                (c0, c1), pl = cs, [self.plans[c] for c in cs]
+                with torch.cuda.stream(self.lanes[lane]):
+                    for k0 in range(1, count[c0] + 1):
+                        for k1 in range(1, count[c1] + 1):
+                            solve_multi(pl, [self.stage[c0][0][:k0], self.stage[c1][0][:k1]],
+                                        [self.stage[c0][1][:k0], self.stage[c1][1][:k1]],
+                                        n_iter=self.n_iter, warm_start=True, graph=True)
             torch.cuda.synchronize()
         esz = torch.empty(0, dtype=tdt).element_size()
         # bytes a frame in flight reserves: slopes + state + the plan scratch of one frame

@@ -96,7 +96,7 @@ def test_served_c5_geometries_equal_alone_and_match_oracle():
         pools[nm] = [torch.tensor(v, dtype=torch.float32, device="cuda") for v in sl]
     streams = {nm: nm for nm in names}
     lanes = {"C4-8m-ngs": 0, "C4-16m-ngs": 1, "C4-39m-lgs": 2, "C4-42m-lgs": 2}
-    srv = Server(cfgs, streams, dtype="f32", n_iter=10, keep_inputs=True, lane_map=lanes)
+    srv = Server(cfgs, streams, dtype="f32", n_iter=10, keep_inputs=True, lane_map=lanes, max_frames=4)
     futs = []
     say("[serve-c5] submitting")
     for f in range(n_frames):
