@@ -33,6 +33,7 @@ import workloads as WL  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_eelt_b32.txt")
+TRAFFIC_FILE_B128 = os.path.join(ROOT, "profiles", "hbm_traffic_eelt_b128.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1302_3734_amd", "csrc", "wmcao_kernels.hip")
 N_FRAMES_ROT = 4            # distinct frozen-flow frames per stream in rotation
 
@@ -217,7 +218,34 @@ def stage_elements(n, Q, steps, iters):
             "PCG updates": steps * (iters * 11 * n + 5 * n)}
 
 
-def measured_traffic(prof, kernels):
+def stage_table(prof, n, Q, steps, iters, B, traffic_file, esz=4):
+    """Per-stage times, launches and achieved GB/s by the algorithmic bytes of
+    `steps` solves of B frames (profile_read output of those steps), and the
+    per-kernel averages."""
+    elems = stage_elements(n, Q, steps, iters)
+    stages = {}
+    for name, ks in STAGES:
+        ms = sum(prof[k][0] for k in ks)
+        launches = sum(prof[k][1] for k in ks)
+        if not launches:
+            continue
+        abytes = elems[name] * esz * B                      # over the profiled window
+        design = sum(prof[k][2] for k in ks)
+        stages[name] = {"kernels": list(ks), "ms": round(ms, 4), "launches": launches,
+                        "avg_launch_us": round(1e3 * ms / launches, 3),
+                        "bytes_per_launch": round(abytes / launches),
+                        "achieved_gbs": round(abytes / (ms / 1e3) / 1e9, 1),
+                        "frac": round(abytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "design_bytes_per_launch": round(design / launches),
+                        "traffic_per_launch": measured_traffic(prof, ks, traffic_file)}
+    tot_ms = sum(v[0] for v in prof.values())
+    kernels = {k: {"avg_us": round(1e3 * v[0] / v[1], 3), "launches": v[1],
+                   "share": round(v[0] / tot_ms, 4)}
+               for k, v in prof.items() if v[1]}
+    return stages, kernels
+
+
+def measured_traffic(prof, kernels, traffic_file=None):
     """HBM bytes per launch of a group of library kernels from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by its
     copy-kernel calibration factor), weighted by the launches of each kernel
@@ -225,7 +253,7 @@ def measured_traffic(prof, kernels):
     kernel source has changed since the counters were taken."""
     import hashlib
     try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
+        lines = open(traffic_file or TRAFFIC_FILE).read().splitlines()
     except OSError:
         return None
     meta, rows = {}, {}
@@ -399,6 +427,43 @@ def onaxis_residual(cfg, layers_vec, truth_vec, truth_cfg=None):
     return rms, float(np.exp(-(rms * 0.5 / 2.2) ** 2))
 
 
+def large_batch(cfg, sig, slopes32, shapes, n_iter=10, frames=128, steps=8):
+    """Measurement only: `frames` E-ELT frames per FP32 solve (about 1.5 GB
+    live, far beyond the 256 MB Infinity Cache), one stream, so that HBM
+    bandwidth figures rest on traffic that cannot stay in the cache.  The
+    inputs repeat the batch-32 frames.  Returns frames/s and the per-stage
+    table."""
+    import torch
+    from paper_1302_3734_amd import Plan
+    nrot, b0 = slopes32.shape[0], slopes32.shape[1]
+    sl = [slopes32[t].repeat((frames + b0 - 1) // b0, 1)[:frames].contiguous() for t in range(nrot)]
+    plan = Plan(cfg, sig, dtype="f32", max_batch=frames, streams=1, **shapes)
+    X = torch.zeros(frames, plan.n, dtype=torch.float32, device="cuda")
+    plan.solve(sl[0], X, n_iter=30)
+    for i in range(2):
+        plan.solve(sl[1 + i % (nrot - 1)], X, n_iter=n_iter, warm_start=True)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(steps):
+        plan.solve(sl[1 + i % (nrot - 1)], X, n_iter=n_iter, warm_start=True)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / steps
+    plan.profile(True)
+    for i in range(3):
+        plan.solve(sl[1 + i % (nrot - 1)], X, n_iter=n_iter, warm_start=True)
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    stages, kernels = stage_table(prof, plan.n, n_nodes(cfg), 3, n_iter, frames, TRAFFIC_FILE_B128)
+    plan.close()
+    return {"workload": f"{frames} E-ELT frames per solve, FP32, 10 warm its, one stream "
+                        "(measurement only)",
+            "ms_per_solve": round(ms, 4), "frames_per_s": round(frames / ms * 1e3, 1),
+            "work_shapes": shapes, "stages": stages, "kernels": kernels}
+
+
 def iteration_sweep(frames=(1, 11, 21, 31), iters=(1, 2, 3, 4, 6, 8, 10, 15, 20)):
     """Speed/quality trade-off of the paper's three solvers on the same E-ELT
     frames (Sec. 5.2-5.3; a synthetic stand-in for its iteration study): nine
@@ -469,7 +534,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="library default work shapes instead of autotuned ones")
     ap.add_argument("--streams", type=int, default=0,
-                    help="plan streams: 1 one stream, 2 two concurrent half batches, 0 library default")
+                    help="concurrent parts of a solve: 1..4, 0 library default (2)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the per-frame FP64 comparison")
     ap.add_argument("--cpu-workers", type=int, default=0)
@@ -477,7 +542,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 128-frame 8 m batch and the mixed-size batch")
+                    help="skip the extra workloads (same as --extra none)")
+    ap.add_argument("--extra", default="c2x128,c3,c4,sweep",
+                    help="comma list of extra workloads: c2x128 (128 E-ELT frames per solve), c3 "
+                         "(128 8 m frames), c4 (mixed sizes), sweep (iteration study), or none")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 256 MiB device copy (byte-counter calibration)")
     args = ap.parse_args()
@@ -532,14 +600,16 @@ def main():
     # ---- work shapes: autotuned for this device, configuration and batch -----
     from paper_1302_3734_amd import autotune
 
-    def shapes(dtype, batch, **kw):
-        sh = dict(autotune.DEFAULTS) if args.no_tune else autotune.tune(cfg, sig, dtype, batch, IT, **kw)
+    def shapes(dtype, batch):
+        """Work shapes tuned for the library's default plan (two concurrent
+        parts where large enough); --streams runs use the same shapes."""
+        sh = dict(autotune.DEFAULTS) if args.no_tune else autotune.tune(cfg, sig, dtype, batch, IT)
         if args.tile:
             sh["tile"] = args.tile
         return sh
 
     t_tune = time.perf_counter()
-    shapes32 = shapes("f32", B, streams=args.streams)
+    shapes32 = shapes("f32", B)
     print(f"[bench] work shapes for {B} frames: {shapes32} ({time.perf_counter() - t_tune:.1f} s)",
           flush=True)
 
@@ -602,28 +672,7 @@ def main():
     p1.profile(False)
     if p1 is not p32:
         p1.close()
-    esz = 4
-    Q = n_nodes(cfg)
-    elems = stage_elements(n, Q, prof_steps, IT)
-    stages = {}
-    for name, ks in STAGES:
-        ms = sum(prof[k][0] for k in ks)
-        launches = sum(prof[k][1] for k in ks)
-        if not launches:
-            continue
-        abytes = elems[name] * esz * B                      # over the profiled window
-        design = sum(prof[k][2] for k in ks)
-        stages[name] = {"kernels": list(ks), "ms": round(ms, 4), "launches": launches,
-                        "avg_launch_us": round(1e3 * ms / launches, 3),
-                        "bytes_per_launch": round(abytes / launches),
-                        "achieved_gbs": round(abytes / (ms / 1e3) / 1e9, 1),
-                        "frac": round(abytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                        "design_bytes_per_launch": round(design / launches),
-                        "traffic_per_launch": measured_traffic(prof, ks)}
-    tot_ms = sum(v[0] for v in prof.values())
-    kernels = {k: {"avg_us": round(1e3 * v[0] / v[1], 3), "launches": v[1],
-                   "share": round(v[0] / tot_ms, 4)}
-               for k, v in prof.items() if v[1]}
+    stages, kernels = stage_table(prof, n, n_nodes(cfg), prof_steps, IT, B, TRAFFIC_FILE)
     dom = max((nm for nm in stages if nm != "PCG updates"), key=lambda nm: stages[nm]["ms"])
     D = stages[dom]
     print(f"[bench] dominant operator stage {dom}: {D['avg_launch_us']:.1f} us/launch, "
@@ -733,13 +782,20 @@ def main():
             "strehl_rel_diff": abs(strehl_a - strehl_b) / strehl_a}
         p64.close()
 
-    if not args.no_extra:
+    extras = set() if args.no_extra else set(args.extra.split(",")) - {"none"}
+    if "c2x128" in extras:
+        result["c2_batch128"] = large_batch(cfg, sig, slopes32, shapes("f32", 128))
+        r128 = result["c2_batch128"]
+        print(f"[bench] c2 x128: {r128['ms_per_solve']:.3f} ms per solve, "
+              f"{r128['frames_per_s']:.0f} frames/s; stage fracs "
+              f"{ {k: v['frac'] for k, v in r128['stages'].items()} }", flush=True)
+    if "c3" in extras:
         result["c3_batched"] = batched_small()
         print(f"[bench] c3 {result['c3_batched']}", flush=True)
+    if "c4" in extras:
         result["c4_mixed"] = mixed_batch()
         print(f"[bench] c4 {result['c4_mixed']}", flush=True)
-
-    if not args.no_extra:
+    if "sweep" in extras:
         result["iteration_sweep"] = iteration_sweep()
         sw = result["iteration_sweep"]
         for name in ("C2", "C2-cg9", "C2-dm3"):

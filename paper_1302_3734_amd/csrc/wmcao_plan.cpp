@@ -173,9 +173,9 @@ struct wmcao_plan_s {
     std::vector<int64_t> layer_off, slope_off;
     std::map<std::pair<int, int>, std::unique_ptr<Sched>> sched;   // by (first frame, frames)
     Sched* full_sched = nullptr;     // max_batch frames, built with the plan
-    int streams = 2;                 // 2: solves of >= SPLIT_MIN frames run as two halves
-    hipStream_t side = nullptr;      // stream of the second half
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int streams = 2;                 // concurrent parts a large solve may run as (1..4)
+    hipStream_t side[3] = {};        // streams of parts 2..4
+    hipEvent_t ev_fork = nullptr, ev_join[3] = {};
     // captured graph of one wmcao_solve_graph argument set, and the event
     // recorded after its latest replay
     hipGraphExec_t gexec = nullptr;
@@ -468,36 +468,46 @@ int get_sched(wmcao_plan_s* p, int batch, Sched** out, int first = 0) {
     return WMCAO_OK;
 }
 
-// A solve runs as two concurrent halves when the plan allows two streams and
-// each half holds at least SPLIT_MIN_UNKNOWNS coefficients: the kernels of one
-// half fill the gaps the other half's leave (E-ELT frames: 7 % faster at 6
+// A solve runs as up to `streams` concurrent parts of its frames when each
+// part holds at least SPLIT_MIN_UNKNOWNS coefficients: the kernels of one part
+// fill the gaps the others' leave (E-ELT frames, two parts: 7 % faster at 6
 // frames, 9 % at 8 to 16, 8 % at 32, 5 % at 64; 4 frames, 0.75 M per half,
-// gain nothing).  Smaller halves are launch-bound and can lose (128 frames of
+// gain nothing).  Smaller parts are launch-bound and can lose (128 frames of
 // the 8 m system, 0.79 M per half: 18 % slower), so they stay on one stream.
 constexpr int64_t SPLIT_MIN_UNKNOWNS = 1024 * 1024;
 
-bool splits(const wmcao_plan_s* p, int batch) {
-    return p->streams > 1 && batch >= 2 && (batch / 2) * p->n >= SPLIT_MIN_UNKNOWNS;
+int parts_of(const wmcao_plan_s* p, int batch) {
+    for (int k = std::min(p->streams, batch); k >= 2; --k)
+        if (static_cast<int64_t>(batch / k) * p->n >= SPLIT_MIN_UNKNOWNS) return k;
+    return 1;
 }
 
-// The plan's second stream and its fork/join events, created on first use
-// (outside any graph capture: callers prepare them before capturing).
-int ensure_side(wmcao_plan_s* p) {
-    if (p->side) return WMCAO_OK;
-    WM_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
-    WM_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
-    WM_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+// First frame of part i of k.
+int part_first(int batch, int k, int i) { return static_cast<int>(static_cast<int64_t>(batch) * i / k); }
+
+// The plan's streams for parts 2..k and their fork/join events, created on
+// first use (outside any graph capture: callers prepare them before capturing).
+int ensure_side(wmcao_plan_s* p, int k = 2) {
+    if (!p->ev_fork) WM_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    for (int i = 0; i + 1 < k; ++i) {
+        if (p->side[i]) continue;
+        WM_HIP(hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking));
+        WM_HIP(hipEventCreateWithFlags(&p->ev_join[i], hipEventDisableTiming));
+    }
     return WMCAO_OK;
 }
 
-// Everything a solve of this batch needs that allocates (schedules, side stream).
+// Everything a solve of this batch needs that allocates (schedules, streams).
 int prepare_solve(wmcao_plan_s* p, int batch) {
     Sched* S = nullptr;
-    if (!splits(p, batch)) return get_sched(p, batch, &S);
-    const int h = batch / 2;
-    int rc = get_sched(p, h, &S, 0);
-    if (!rc) rc = get_sched(p, batch - h, &S, h);
-    if (!rc) rc = ensure_side(p);
+    const int k = parts_of(p, batch);
+    if (k == 1) return get_sched(p, batch, &S);
+    int rc = WMCAO_OK;
+    for (int i = 0; i < k && !rc; ++i) {
+        const int f0 = part_first(batch, k, i), f1 = part_first(batch, k, i + 1);
+        rc = get_sched(p, f1 - f0, &S, f0);
+    }
+    if (!rc) rc = ensure_side(p, k);
     return rc;
 }
 
@@ -687,26 +697,30 @@ int enqueue_solve(wmcao_plan_s* p, const void* slopes, void* coeffs, int batch, 
     auto run = [&](const Sched& S, hipStream_t st) {
         with_types(p, [&]<class T, class Sv>() { run_solve<T, Sv>(a, S, n_iter, warm, p->resid_replace, p->c64, st); });
     };
-    if (!splits(p, batch)) {
+    const int k = parts_of(p, batch);
+    if (k == 1) {
         Sched* S = nullptr;
         rc = get_sched(p, batch, &S);
         if (rc) return rc;
         run(*S, s);
         return check_launch();
     }
-    // two halves: the second forks onto the plan's stream after everything
-    // the caller queued before, and the caller's stream waits for it to end
-    const int h = batch / 2;
-    Sched *S0 = nullptr, *S1 = nullptr;
-    rc = get_sched(p, h, &S0, 0);
-    if (!rc) rc = get_sched(p, batch - h, &S1, h);
+    // k parts: parts 2..k fork onto the plan's streams after everything the
+    // caller queued before, and the caller's stream waits for them to end
+    Sched* Sp[4] = {};
+    for (int i = 0; i < k && !rc; ++i) {
+        const int f0 = part_first(batch, k, i), f1 = part_first(batch, k, i + 1);
+        rc = get_sched(p, f1 - f0, &Sp[i], f0);
+    }
     if (rc) return rc;
     WM_HIP(hipEventRecord(p->ev_fork, s));
-    WM_HIP(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-    run(*S0, s);
-    run(*S1, p->side);
-    WM_HIP(hipEventRecord(p->ev_join, p->side));
-    WM_HIP(hipStreamWaitEvent(s, p->ev_join, 0));
+    for (int i = 1; i < k; ++i) WM_HIP(hipStreamWaitEvent(p->side[i - 1], p->ev_fork, 0));
+    run(*Sp[0], s);
+    for (int i = 1; i < k; ++i) run(*Sp[i], p->side[i - 1]);
+    for (int i = 1; i < k; ++i) {
+        WM_HIP(hipEventRecord(p->ev_join[i - 1], p->side[i - 1]));
+        WM_HIP(hipStreamWaitEvent(s, p->ev_join[i - 1], 0));
+    }
     return check_launch();
 }
 
@@ -827,7 +841,7 @@ int enqueue_multi(const wmcao_plan_t* plans, const void* const* slopes, void* co
     Sched* S[2] = {nullptr, nullptr};
     int rc = packed(grp[0], &S[0]);
     if (!rc && two_groups) rc = packed(grp[1], &S[1]);
-    if (!rc && two_groups && side_ok) rc = ensure_side(plans[0]);
+    if (!rc && two_groups && side_ok) rc = ensure_side(plans[0], 2);
     if (rc) return rc;
     if (prepare_only) return WMCAO_OK;
     if (!two_groups || !side_ok) {
@@ -837,11 +851,11 @@ int enqueue_multi(const wmcao_plan_t* plans, const void* const* slopes, void* co
     }
     wmcao_plan_s* p0 = plans[0];
     WM_HIP(hipEventRecord(p0->ev_fork, s));
-    WM_HIP(hipStreamWaitEvent(p0->side, p0->ev_fork, 0));
+    WM_HIP(hipStreamWaitEvent(p0->side[0], p0->ev_fork, 0));
     run(args_for(grp[0], idx[0]), *S[0], plans[idx[0][0]], s);
-    run(args_for(grp[1], idx[1]), *S[1], plans[idx[1][0]], p0->side);
-    WM_HIP(hipEventRecord(p0->ev_join, p0->side));
-    WM_HIP(hipStreamWaitEvent(s, p0->ev_join, 0));
+    run(args_for(grp[1], idx[1]), *S[1], plans[idx[1][0]], p0->side[0]);
+    WM_HIP(hipEventRecord(p0->ev_join[0], p0->side[0]));
+    WM_HIP(hipStreamWaitEvent(s, p0->ev_join[0], 0));
     return check_launch();
 }
 
@@ -961,7 +975,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         return fail(WMCAO_ERR_INVALID_ARG, "tile must be 0, 16, 32 or 64");
     if (opts->precond != 0 && opts->precond != 1) return fail(WMCAO_ERR_INVALID_ARG, "precond");
     if (opts->resid_replace_every < 0) return fail(WMCAO_ERR_INVALID_ARG, "resid_replace_every < 0");
-    if (opts->streams < 0 || opts->streams > 2) return fail(WMCAO_ERR_INVALID_ARG, "streams must be 0, 1 or 2");
+    if (opts->streams < 0 || opts->streams > 4) return fail(WMCAO_ERR_INVALID_ARG, "streams must be 0..4");
     if (opts->op_precision != 0 && opts->op_precision != 32 && opts->op_precision != 64)
         return fail(WMCAO_ERR_INVALID_ARG, "op_precision must be 0, 32 or 64");
     if (opts->dtype == WMCAO_F64 && opts->op_precision == 32)
@@ -1846,8 +1860,10 @@ void wmcao_plan_destroy(wmcao_plan_t plan) {
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
     if (plan->gdone) (void)hipEventDestroy(plan->gdone);
     if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
-    if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
-    if (plan->side) (void)hipStreamDestroy(plan->side);
+    for (int i = 0; i < 3; ++i) {
+        if (plan->ev_join[i]) (void)hipEventDestroy(plan->ev_join[i]);
+        if (plan->side[i]) (void)hipStreamDestroy(plan->side[i]);
+    }
     delete plan;
 }
 

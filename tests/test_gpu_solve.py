@@ -337,22 +337,25 @@ def test_edge_batches_and_zero_iterations():
     plan.close()
 
 
-@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
-def test_two_stream_halves_equal_one_stream(graph):
-    """Seven E-ELT frames (1.1 M coefficients per half) run as halves of 3
-    and 4 frames on two streams (the default; the launch counts show the
-    split): coefficients, residual histories and statuses are bitwise those
-    of the same solve on one stream, for warm starts and a residual
-    replacement, and twice in a row on the same buffers."""
+@pytest.mark.parametrize("graph,parts", [(False, 2), (True, 2), (False, 4), (True, 4)],
+                         ids=["eager-2", "graph-2", "eager-4", "graph-4"])
+def test_concurrent_parts_equal_one_stream(graph, parts):
+    """E-ELT frames run as concurrent parts on several streams (7 frames as
+    halves of 3 and 4; 13 frames as four parts of 3, 3, 3 and 4; each part
+    holds at least 2^20 coefficients, and the launch counts show the split):
+    coefficients, residual histories and statuses are bitwise those of the
+    same solve on one stream, for warm starts and a residual replacement, and
+    twice in a row on the same buffers."""
     require_gpu()
     import torch
     from paper_1302_3734_amd import Plan
     cfg = WL.config_c2()
-    B, n_it = 7, 5
+    B = 7 if parts == 2 else 13
+    n_it = 5
     sig = [0.2] * 6 + [0.02, 0.006, 0.004]
     gen = torch.Generator(device="cuda").manual_seed(5)
     outs = {}
-    for streams in (1, 2):
+    for streams in (1, parts):
         plan = Plan(cfg, sig, dtype="f32", max_batch=B, streams=streams, resid_replace_every=3)
         if streams == 1:
             s32 = torch.randn(B, plan.n_slopes, dtype=torch.float32, device="cuda", generator=gen) * 0.1
@@ -369,11 +372,11 @@ def test_two_stream_halves_equal_one_stream(graph):
                 plan.solve(s32, x, n_iter=n_it, warm_start=True, resid=resid, status=status,
                            graph=graph, stream=stream)
         stream.synchronize()
-        if not graph:   # one update_r launch per iteration and half
+        if not graph:   # one update_r launch per iteration and part
             assert plan.profile_read()["update_r"][1] == 2 * n_it * streams
             plan.profile(False)
         outs[streams] = (x.clone(), resid.clone(), status.clone())
         plan.close()
-    for a, b in zip(outs[1], outs[2]):
+    for a, b in zip(outs[1], outs[parts]):
         assert torch.equal(a, b)
-    assert int(outs[2][2].min()) >= 0
+    assert int(outs[parts][2].min()) >= 0
