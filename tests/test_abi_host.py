@@ -32,11 +32,14 @@ def test_strerror_and_last_error():
     assert isinstance(L.wmcao_last_error(), bytes)
 
 
-def _args(n=64, levels=4, order=3, n_sub=16, agg=0, dtype=0, tile=0, sigma=0.1, streams=0):
+def _args(n=64, levels=4, order=3, n_sub=16, agg=0, dtype=0, tile=0, sigma=0.1, streams=0, **opt):
     Ls = (_abi.Layer * 1)(_abi.Layer(0.0, 1.0, 0.5, n))
     Ws = (_abi.Wfs * 1)(_abi.Wfs(0, 0.0, 0.0, 90e3, n_sub, agg, -1, -1, sigma, None, 0))
     pupil = _abi.Pupil(8.0, 0.0)
     opts = _abi.Options(1.0, 0.15, 25.0, dtype, 1, 0, 1, tile, 0, streams)
+    opts.op_fp64_stages = -1
+    for k, v in opt.items():
+        setattr(opts, k, v)
     return pupil, Ls, Ws, _abi.Wavelet(0, order), levels, opts
 
 
@@ -49,8 +52,14 @@ def _args(n=64, levels=4, order=3, n_sub=16, agg=0, dtype=0, tile=0, sigma=0.1, 
     ({"dtype": 7}, -1),
     ({"tile": 48}, -1),
     ({"sigma": 0.0}, -1),
-    ({"streams": 3}, -1),            # one stream or two concurrent halves
+    ({"streams": 5}, -1),            # one to four concurrent parts
     ({"streams": -1}, -1),
+    ({"op_precision": 16}, -1),      # operators are FP32 or FP64
+    ({"dtype": 1, "op_precision": 32}, -1),
+    ({"op_fp64_stages": 9}, -1),     # a mask of 1, 2 and 4
+    ({"proj_rows": 6}, -1),
+    ({"vec_chunk": 3000}, -1),
+    ({"adj_lds": 1024}, -1),
 ])
 def test_invalid_plans_rejected_on_host(kw, code):
     L = _abi.lib()
