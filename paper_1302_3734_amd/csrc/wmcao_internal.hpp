@@ -157,7 +157,8 @@ template <class T, class S, class C>
 void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int in_vec,
                         int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s);
 template <class T, class S>
-void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, hipStream_t s);
+void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, int lds_bytes,
+                    hipStream_t s);
 template <class T, class S>
 void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, int lds_bytes,
                     hipStream_t s);
@@ -188,7 +189,7 @@ constexpr size_t NOALLOC_BYTES = size_t(32) << 20;   // scratch of the allocatio
 constexpr int FUSE_LDS = 32 * 1024;   // largest low-pass block a synthesis tile rebuilds
 constexpr int TILE_NT = 256;          // threads of a wavelet tile block
 constexpr int VEC_CHUNK = 2048;   // default elements per work item of the vector kernels
-constexpr int PROJ_ROWS = 8;      // default (and most) node rows per projection work item
+constexpr int PROJ_ROWS = 8;      // default node rows per projection work item (4, 8 or 16)
 constexpr int PROJ_ROWS_MIN = 4;  // fewest node rows per projection work item
 
 // Dynamic LDS of k_weights for a sensor of nn nodes and ns subapertures per
@@ -196,6 +197,12 @@ constexpr int PROJ_ROWS_MIN = 4;  // fewest node rows per projection work item
 // x and y slopes of the subaperture rows next to the band (FP64).
 constexpr int weights_lds_bytes(int nn, int ns, int rows) {
     return ((rows + 2) * nn + 2 * (rows + 1) * ns) * 8;
+}
+// Dynamic LDS of k_project for L layers, a sensor of nn nodes per side and
+// `rows` node rows per item: the u window of rows + 1 node rows (FP64), then
+// per layer an FP64 weight and an int per node column and per window row.
+constexpr int proj_lds_bytes(int L, int nn, int rows) {
+    return (rows + 1) * nn * 8 + L * nn * 12 + L * (rows + 1) * 12;
 }
 constexpr int SP_K = 2 * WM_MAXCELL;   // doubles per slope-sum record
 constexpr int ADJ_BAND = 32;      // footprint rows per adjoint work item (at most)

@@ -311,14 +311,55 @@ __device__ __forceinline__ void node_stencil(double pa, double pb, int i, int N,
     t = u - i0;
 }
 
+// Raw buffer resource over the `bytes` bytes at `base`.  The hardware checks
+// every raw-buffer offset against the size and returns 0 for a load at or past
+// it (an offset that wrapped below zero is a large unsigned value, so also
+// past it) without touching memory: reads that may fall outside an image need
+// no bounds branch and no select.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes),
+                                             0x00020000);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+constexpr uint32_t BUF_OOB = 0x80000000u;   // a byte offset past every image
+constexpr int GNS = 2;                      // footprint images per gather step
+
+// Two consecutive elements (a = x[i], b = x[i + 1]) from a raw buffer at a
+// byte offset (element aligned): one 8-byte load for floats, two for doubles.
+template <class S>
+struct Pair {
+    S a, b;
+};
+template <class S>
+__device__ __forceinline__ Pair<S> ld_pair(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (sizeof(S) == 4) {
+        // the whole 8-byte value is reinterpreted (element access of the
+        // builtin's vector result is not used)
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const f2 v = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        return {v.x, v.y};
+    } else {
+        return {buf_ld(r, off, S()), buf_ld(r, off + 8u, S())};
+    }
+}
+
 // P^T over a window of PR x PC pixels of layer l starting at (px0, py0)
 // (periodic indices, px0 + PR < 2N), written into G (row stride ldg):
 // the sum, in sensor order, of the footprint images of the sensors in mask
 // (k_adjoint).  A thread owns one window column and every rstep-th row, so
 // each G entry has one writer: no atomics and no barrier.  Rows go in chunks
-// of RC held in registers, two sensors per step; every load goes to a valid
-// address (clamped) with the value selected afterwards, so the 2 RC loads of
-// a step are all in flight before the first is added.
+// of RC held in registers, GNS sensors per step, with all GNS RC loads in
+// flight before the first is added.  Loads go through raw buffers over each image, so
+// a pixel outside a footprint reads 0: the byte offset of row k of a chunk is
+// that of row 0 plus k rstep W (modulo 2^32, exact for rows inside the image;
+// rows above or below it land past its end), and a column outside the
+// footprint starts from BUF_OOB.  Windows that wrap around the layer's last
+// row take the offsets row by row.
 template <class S, class C, int RC>
 __device__ void pt_gather_window(const PlanDev& P, const S* img, int l, int N, int px0, int py0,
                                  int PR, int PC, C* G, int ldg, unsigned mask) {
@@ -336,56 +377,51 @@ __device__ void pt_gather_window(const PlanDev& P, const S* img, int l, int N, i
         rstep = 1;
         cstep = bd;
     }
+    const bool wrap = px0 + PR > N;   // uniform
     for (int c = c0; c < PC; c += cstep) {
         int gy = py0 + c;
         if (gy >= N) gy -= N;
         for (int rb = r0; rb < PR; rb += RC * rstep) {
-            int gx[RC];
             C g[RC];
 #pragma unroll
-            for (int k = 0; k < RC; ++k) {
-                const int r = rb + k * rstep;
-                gx[k] = px0 + r >= N ? px0 + r - N : px0 + r;
-                gx[k] = r < PR ? gx[k] : -1;   // a row past the window is in no footprint
-                g[k] = 0.0;
-            }
+            for (int k = 0; k < RC; ++k) g[k] = 0.0;
             // the mask is the same for every lane: keep it (and the sensor
             // indices drawn from it) in scalar registers, so the footprint
             // fields below are scalar loads
             unsigned mm = __builtin_amdgcn_readfirstlane(mask);
             while (mm) {
-                const int ma = __builtin_amdgcn_readfirstlane(__ffs(static_cast<int>(mm)) - 1);
-                mm &= mm - 1;
-                const int mb = __builtin_amdgcn_readfirstlane(mm ? __ffs(static_cast<int>(mm)) - 1 : ma);
-                const bool hb = mm != 0;
-                if (hb) mm &= mm - 1;
-                const int yca = gy - P.fp_y0[ma][l], Wa = P.fp_w[ma][l];
-                const int ycb = gy - P.fp_y0[mb][l], Wb = P.fp_w[mb][l];
-                // one unsigned compare per bound pair: negative offsets wrap high
-                const bool ca = static_cast<unsigned>(yca) < static_cast<unsigned>(Wa);
-                const bool cb = hb && static_cast<unsigned>(ycb) < static_cast<unsigned>(Wb);
-                const int xa = P.fp_x0[ma][l], Ha = P.fp_h[ma][l];
-                const int xb = P.fp_x0[mb][l], Hb = P.fp_h[mb][l];
-                // image bases are uniform; byte offsets within an image fit 32 bits
-                const char* ia = reinterpret_cast<const char*>(img + P.fp_off[ma][l]);
-                const char* ib = reinterpret_cast<const char*>(img + P.fp_off[mb][l]);
-                S va[RC], vb[RC];
-                bool la[RC], lb[RC];
+                // the next GNS sensors of the mask (a step past the last one
+                // reads nothing: its buffer holds no bytes)
+                S v[GNS][RC];
 #pragma unroll
-                for (int k = 0; k < RC; ++k) {
-                    const int ra = gx[k] - xa, rb2 = gx[k] - xb;
-                    la[k] = ca && static_cast<unsigned>(ra) < static_cast<unsigned>(Ha);
-                    lb[k] = cb && static_cast<unsigned>(rb2) < static_cast<unsigned>(Hb);
-                    const uint32_t oa = la[k] ? static_cast<uint32_t>(ra * Wa + yca) * sizeof(S) : 0u;
-                    const uint32_t ob = lb[k] ? static_cast<uint32_t>(rb2 * Wb + ycb) * sizeof(S) : 0u;
-                    va[k] = *reinterpret_cast<const S*>(ia + oa);
-                    vb[k] = *reinterpret_cast<const S*>(ib + ob);
+                for (int s = 0; s < GNS; ++s) {
+                    const bool has = mm != 0;
+                    const int ms = __builtin_amdgcn_readfirstlane(has ? __ffs(static_cast<int>(mm)) - 1 : 0);
+                    if (has) mm &= mm - 1;
+                    const int W = P.fp_w[ms][l], yc = gy - P.fp_y0[ms][l], x0 = P.fp_x0[ms][l];
+                    const __amdgpu_buffer_rsrc_t rs =
+                        buf_rsrc(img + P.fp_off[ms][l], has ? static_cast<uint32_t>(P.fp_h[ms][l] * W * sizeof(S)) : 0u);
+                    // one unsigned compare per bound pair: negative offsets wrap high
+                    const bool cok = static_cast<unsigned>(yc) < static_cast<unsigned>(W);
+                    if (!wrap) {
+                        const uint32_t o = cok ? static_cast<uint32_t>(((px0 + rb - x0) * W + yc) * static_cast<int>(sizeof(S))) : BUF_OOB;
+                        const uint32_t st = static_cast<uint32_t>(rstep * W * static_cast<int>(sizeof(S)));
+#pragma unroll
+                        for (int k = 0; k < RC; ++k) v[s][k] = buf_ld(rs, o + k * st, S());
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < RC; ++k) {
+                            int gx = px0 + rb + k * rstep;
+                            gx -= gx >= N ? N : 0;
+                            const uint32_t o = cok ? static_cast<uint32_t>(((gx - x0) * W + yc) * static_cast<int>(sizeof(S))) : BUF_OOB;
+                            v[s][k] = buf_ld(rs, o, S());
+                        }
+                    }
                 }
 #pragma unroll
-                for (int k = 0; k < RC; ++k) {
-                    if (la[k]) g[k] += static_cast<C>(va[k]);
-                    if (lb[k]) g[k] += static_cast<C>(vb[k]);
-                }
+                for (int s = 0; s < GNS; ++s)
+#pragma unroll
+                    for (int k = 0; k < RC; ++k) g[k] += static_cast<C>(v[s][k]);
             }
 #pragma unroll
             for (int k = 0; k < RC; ++k)
@@ -747,86 +783,109 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
 // sums for the tip/tilt projection and the low-order cells (one record per
 // band, reduced in a fixed order by k_weights).  u is kept in FP64 so that the
 // Fried differences do not cancel single-precision digits.
-constexpr int PROJ_LB = 9;   // layers whose samples a thread loads together
+constexpr int PROJ_LB = 3;   // layers whose samples a thread loads together
 
+// At most 64 VGPRs (eight waves per SIMD): left free, the compiler keeps
+// every layer's weights in registers and halves the occupancy.
 template <class T, class S>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8)))
 k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int sums) {
-    __shared__ double su[(PROJ_ROWS + 1) * (WM_NSUB_MAX + 1)];
     __shared__ double red[68];
-    // bilinear stencils of the block's node rows and of every node column, per layer
-    __shared__ int ri0[WM_MAXL][PROJ_ROWS + 1], cj0[WM_MAXL][WM_NSUB_MAX + 1];
-    __shared__ double rtw[WM_MAXL][PROJ_ROWS + 1], csw[WM_MAXL][WM_NSUB_MAX + 1];
-    // layer sizes and offsets, read before any store (the stores could alias
-    // the plan, which would otherwise be read again from memory in the loop)
-    __shared__ int lay_n[WM_MAXL];
-    __shared__ int64_t lay_off[WM_MAXL];
     const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
     const int m = it.a;
     const WfsInfo& w = P.wfs[m];
     const int nn = w.nn, L = P.L;
-    const int PR = P.proj_rows;
+    const int PR = P.proj_rows, PR1 = PR + 1;
     const int r0 = it.b * PR;
     const int rows = min(PR, nn - r0);
     const bool slopes = sums && w.kind == 0;
-    const int rows_c = slopes ? min(PR + 1, nn - r0) : rows;
+    const int rows_c = slopes ? min(PR1, nn - r0) : rows;
     const int K = rows_c + nn;
-    if (threadIdx.x < L) {
-        lay_n[threadIdx.x] = P.layer[threadIdx.x].N;
-        lay_off[threadIdx.x] = P.layer[threadIdx.x].coff;
-    }
+    // dynamic LDS (proj_lds_bytes): the u window for the slopes, then per
+    // layer the bilinear stencils of every node column (weight s of the
+    // second pixel column, first pixel column) and of the block's node rows
+    // (weight t of the second pixel row, element offset of the first sample
+    // in the frame's pixel vector)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* su = reinterpret_cast<double*>(smem_raw);
+    double* cs = su + PR1 * nn;
+    double* rt = cs + L * nn;
+    int* cj0 = reinterpret_cast<int*>(rt + L * PR1);
+    int* rbase = cj0 + L * nn;
+    // e = l K + k, split with a float reciprocal: exact here, since the
+    // quotient's fractional part is at least 1 / (2 K) away from an integer
+    // and e < 2^12 keeps the product's error near 2^-12
+    const float rK = 1.0f / static_cast<float>(K);
     for (int e = threadIdx.x; e < L * K; e += blockDim.x) {
-        const int l = e / K, k = e - (e / K) * K;
+        const int l = static_cast<int>((static_cast<float>(e) + 0.5f) * rK), k = e - l * K;
         const int N = P.layer[l].N;
-        if (k < rows_c)
-            node_stencil(P.pa[m][l], P.pb[0][m][l], r0 + k, N, ri0[l][k], rtw[l][k]);
-        else
-            node_stencil(P.pa[m][l], P.pb[1][m][l], k - rows_c, N, cj0[l][k - rows_c],
-                         csw[l][k - rows_c]);
+        int i0;
+        Acc t;
+        if (k < rows_c) {
+            node_stencil(P.pa[m][l], P.pb[0][m][l], r0 + k, N, i0, t);
+            rbase[l * PR1 + k] = static_cast<int>(P.layer[l].coff) + i0 * N;
+            rt[l * PR1 + k] = t;
+        } else {
+            const int c = k - rows_c;
+            node_stencil(P.pa[m][l], P.pb[1][m][l], c, N, i0, t);
+            cj0[l * nn + c] = i0;
+            cs[l * nn + c] = t;
+        }
     }
     __syncthreads();
-    const S* phi = vptr<S>(J, in_vec, it.frame);
-    double* u = vptr<double>(J, V_U, it.frame) + w.node_off;
-    for (int e = threadIdx.x; e < rows_c * nn; e += blockDim.x) {
-        const int li = e / nn, j = e - (e / nn) * nn;
-        Acc acc = 0;
-        // PROJ_LB layers per step: their samples are loaded before any is used
-        for (int l0 = 0; l0 < L; l0 += PROJ_LB) {
-            S v[PROJ_LB][4];
+    // a thread owns node column j and rows g, g + G, ... of the block (G =
+    // threads per column); the two samples of a node's sample row on a layer
+    // (pixels i0 and i0 + 1) are one load, through a raw buffer over the
+    // frame's pixels with 32-bit offsets
+    const int G = blockDim.x / nn;
+    const int j = threadIdx.x % nn, g = threadIdx.x / nn;
+    if (g < G) {
+        const __amdgpu_buffer_rsrc_t rp =
+            buf_rsrc(vptr<S>(J, in_vec, it.frame), static_cast<uint32_t>(P.n * sizeof(S)));
+        double* u = vptr<double>(J, V_U, it.frame) + w.node_off;
+        for (int li = g; li < rows_c; li += G) {
+            Acc acc = 0;
+            // PROJ_LB layers per step: their samples are loaded before any is used
+            for (int l0 = 0; l0 < L; l0 += PROJ_LB) {
+                Pair<S> v[PROJ_LB][2];
 #pragma unroll
-            for (int k = 0; k < PROJ_LB; ++k) {
-                const int l = min(l0 + k, L - 1);   // past the last layer: a valid load, unused
-                const int N = lay_n[l];
-                const S* f = phi + lay_off[l] + static_cast<int64_t>(ri0[l][li]) * N + cj0[l][j];
-                v[k][0] = f[0];
-                v[k][1] = f[1];
-                v[k][2] = f[N];
-                v[k][3] = f[N + 1];
-            }
+                for (int k = 0; k < PROJ_LB; ++k) {
+                    const int l = min(l0 + k, L - 1);   // past the last layer: a valid load, unused
+                    const uint32_t o = static_cast<uint32_t>((rbase[l * PR1 + li] + cj0[l * nn + j]) * static_cast<int>(sizeof(S)));
+                    v[k][0] = ld_pair<S>(rp, o);
+                    v[k][1] = ld_pair<S>(rp, o + static_cast<uint32_t>(P.layer[l].N * static_cast<int>(sizeof(S))));
+                }
 #pragma unroll
-            for (int k = 0; k < PROJ_LB; ++k) {
-                const int l = l0 + k;
-                if (l < L) {
-                    const Acc t = rtw[l][li], s = csw[l][j];
-                    acc += (1.0 - t) * ((1.0 - s) * static_cast<Acc>(v[k][0]) + s * static_cast<Acc>(v[k][1])) +
-                           t * ((1.0 - s) * static_cast<Acc>(v[k][2]) + s * static_cast<Acc>(v[k][3]));
+                for (int k = 0; k < PROJ_LB; ++k) {
+                    const int l = l0 + k;
+                    if (l < L) {
+                        // bilinear: lerp along y in both sample rows, then along x
+                        const Acc s = cs[l * nn + j], t = rt[l * PR1 + li];
+                        const Acc a0 = static_cast<Acc>(v[k][0].a), a1 = static_cast<Acc>(v[k][0].b);
+                        const Acc b0 = static_cast<Acc>(v[k][1].a), b1 = static_cast<Acc>(v[k][1].b);
+                        const Acc x = fma(s, a1 - a0, a0), y = fma(s, b1 - b0, b0);
+                        acc += fma(t, y - x, x);
+                    }
                 }
             }
+            if (li < rows) u[(r0 + li) * nn + j] = acc;
+            if (slopes) su[li * nn + j] = acc;
         }
-        if (e < rows * nn) u[(r0 + li) * nn + j] = acc;
-        if (slopes) su[e] = acc;
     }
     if (!slopes) return;
     __syncthreads();
     const int ns = w.n_sub;
     double* rec = vptr<double>(J, V_SPART, it.frame) + w.sp_off + it.b * SP_K;
     const int nsub_rows = min(PR, min(ns - r0, rows_c - 1));
+    // a thread owns subaperture column js and rows gs, gs + GS, ...
+    const int GS = blockDim.x / ns, js = threadIdx.x % ns;
+    const int gs = threadIdx.x / ns < GS ? threadIdx.x / ns : nsub_rows;   // spare threads: no rows
     if (!w.agg) {
         Acc p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-        for (int e = threadIdx.x; e < nsub_rows * ns; e += blockDim.x) {
-            const int li = e / ns, j = e % ns;
+        for (int li = gs; li < nsub_rows; li += GS) {
+            const int j = js;
             const int q = w.maskmap[(r0 + li) * ns + j];
             if (q < 0) continue;
             const Acc u00 = su[li * nn + j], u10 = su[(li + 1) * nn + j];
@@ -848,8 +907,8 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
         // two cells per pass: x and y sums of cells c and c + 1
         for (int c = 0; c < w.S; c += 2) {
             double pv[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int e = threadIdx.x; e < nsub_rows * ns; e += blockDim.x) {
-                const int li = e / ns, j = e % ns;
+            for (int li = gs; li < nsub_rows; li += GS) {
+                const int j = js;
                 const int k = w.maskmap[(r0 + li) * ns + j] - c;
                 if (k != 0 && k != 1) continue;
                 const Acc u00 = su[li * nn + j], u10 = su[(li + 1) * nn + j];
@@ -1901,9 +1960,10 @@ void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int
 }
 
 template <class T, class S>
-void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, hipStream_t s) {
+void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, int lds_bytes,
+                    hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL((k_project<T, S>), dim3(n), dim3(512), 0, s, a, items, in_vec, sums);
+    hipLaunchKernelGGL((k_project<T, S>), dim3(n), dim3(512), lds_bytes, s, a, items, in_vec, sums);
 }
 
 template <class T, class S>
@@ -2026,7 +2086,7 @@ void configure_kernels() {
 // Projection and sensor stages (FP64 arithmetic): vector storage T, operator storage S.
 #define WM_INSTANTIATE_SENSORS(T, S)                                                               \
     template void launch_sensor<T, S>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
-    template void launch_project<T, S>(const JobArgs&, const Item*, int, int, int, hipStream_t);  \
+    template void launch_project<T, S>(const JobArgs&, const Item*, int, int, int, int, hipStream_t);  \
     template void launch_weights<T, S>(const JobArgs&, const Item*, int, int, int, hipStream_t);
 
 // The PCG vector steps: storage T.

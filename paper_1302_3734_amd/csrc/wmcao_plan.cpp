@@ -73,6 +73,7 @@ struct Sched {
     int lds_fdwt[2] = {};  // the whole-band analysis
     int lds_sensor = 0;
     int lds_weights = 0;   // dynamic LDS of k_weights
+    int lds_project = 0;   // dynamic LDS of k_project
     int tile = 32;
     // algorithmic bytes one launch of each stage moves (all frames of the job)
     double b_idwt_coarse = 0, b_idwt_tile[WM_MAXLEV + 1] = {};
@@ -275,7 +276,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj;
     int lds_lvl[2][WM_MAXLEV + 1] = {};
     std::vector<Item> tiled[WM_MAXLEV + 1];
-    int maxk0 = 0, lds_i[2] = {}, lds_f[2] = {}, lds_s = 0, lds_a[2] = {}, lds_w = 0, taps_a = 2;
+    int maxk0 = 0, lds_i[2] = {}, lds_f[2] = {}, lds_s = 0, lds_a[2] = {}, lds_w = 0, lds_p = 0, taps_a = 2;
     for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
         const wmcao_plan_s* P = jobs[jp].plan;
         for (int f = jobs[jp].first; f < jobs[jp].first + jobs[jp].count; ++f) {
@@ -321,6 +322,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                 const int nn = P->host.wfs[m].nn;
                 lds_s = std::max(lds_s, static_cast<int>(nn * nn * sizeof(double)));
                 lds_w = std::max(lds_w, weights_lds_bytes(nn, P->host.wfs[m].n_sub, P->host.proj_rows));
+                lds_p = std::max(lds_p, proj_lds_bytes(P->L, nn, P->host.proj_rows));
             }
             const int nch = static_cast<int>((P->n + P->host.vec_chunk - 1) / P->host.vec_chunk);
             for (int c = 0; c < nch; ++c) vec.push_back(Item{jp, f, 0, c, c, 0, 0, 0});
@@ -413,6 +415,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     }
     S->lds_sensor = lds_s;
     S->lds_weights = lds_w;
+    S->lds_project = lds_p;
     S->tile = tile;
     return WMCAO_OK;
 }
@@ -608,7 +611,7 @@ void run_adjoint(const JobArgs& a, const Sched& Sc, int c64, hipStream_t s) {
 template <class T, class S>
 void run_apply(const JobArgs& a, const Sched& Sc, int x_vec, int y_vec, int c64, hipStream_t s) {
     run_idwt<T, S>(a, Sc, x_vec, V_PHI, c64, s);
-    timed(WMCAO_K_PROJECT, Sc.b_project, s, [&] { launch_project<T, S>(a, Sc.proj, Sc.n_proj, V_PHI, 1, s); });
+    timed(WMCAO_K_PROJECT, Sc.b_project, s, [&] { launch_project<T, S>(a, Sc.proj, Sc.n_proj, V_PHI, 1, Sc.lds_project, s); });
     timed(WMCAO_K_WEIGHTS, Sc.b_sensor[0], s,
           [&] { launch_weights<T, S>(a, Sc.proj, Sc.n_proj, V_NODE, Sc.lds_weights, s); });
     run_adjoint<T, S>(a, Sc, c64, s);
@@ -982,8 +985,8 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         return fail(WMCAO_ERR_INVALID_ARG, "FP64 plans have FP64 operators");
     if (opts->op_fp64_stages < -1 || opts->op_fp64_stages > 7)
         return fail(WMCAO_ERR_INVALID_ARG, "op_fp64_stages must be -1 or a mask of 1, 2 and 4");
-    if (opts->proj_rows != 0 && opts->proj_rows != 4 && opts->proj_rows != 8)
-        return fail(WMCAO_ERR_INVALID_ARG, "proj_rows must be 0, 4 or 8");
+    if (opts->proj_rows != 0 && opts->proj_rows != 4 && opts->proj_rows != 8 && opts->proj_rows != 16)
+        return fail(WMCAO_ERR_INVALID_ARG, "proj_rows must be 0, 4, 8 or 16");
     if (opts->vec_chunk != 0 && opts->vec_chunk != 1024 && opts->vec_chunk != 2048 &&
         opts->vec_chunk != 4096 && opts->vec_chunk != 8192)
         return fail(WMCAO_ERR_INVALID_ARG, "vec_chunk must be 0, 1024, 2048, 4096 or 8192");
@@ -1567,7 +1570,7 @@ static int simple_call(wmcao_plan_t p, const void* in, void* out, int batch, voi
                 if (!same)
                     launch_cast<T, Sv>(static_cast<const T*>(in), static_cast<Sv*>(p->vphi),
                                        p->n * batch, s);
-                launch_project<T, Sv>(a, S->proj, S->n_proj, same ? V_IN : V_PHI, 0, s);
+                launch_project<T, Sv>(a, S->proj, S->n_proj, same ? V_IN : V_PHI, 0, S->lds_project, s);
                 launch_sensor<T, Sv>(a, S->sensor, S->n_sensor, SM_FWD, V_U, V_OUT, S->lds_sensor, s);
                 break;
             case 3:   // rhs

@@ -43,6 +43,10 @@ CASES = [
     ("max-f32-op32", tiny_max_config, "f32", {"tile": 16, "op_precision": 32}),
     ("c1-f32", WL.config_c1, "f32", {}),
     ("c2-f32-op64", WL.config_c2, "f32", {"op_precision": 64}),
+    # every work shape the autotuner may choose away from the defaults
+    ("c2-f32-rows16", WL.config_c2, "f32", {"proj_rows": 16, "adj_lds": 64 * 1024}),
+    ("c2-f64-rows4", WL.config_c2, "f64", {"proj_rows": 4, "adj_lds": 16 * 1024, "vec_chunk": 4096}),
+    ("max-f64-rows16", tiny_max_config, "f64", {"proj_rows": 16, "vec_chunk": 1024}),
 ]
 
 _cache = {}
