@@ -72,7 +72,8 @@ struct WfsInfo {
 struct PlanDev {
     int L, W, levels, dtype;
     int op64;               // 1: operator storage S = double, 0: S = float
-    int proj_rows;          // sensor node rows per work item of the projection and weighting
+    int proj_rows;          // sensor node rows per work item of the projection (one slope record each)
+    int wgt_rows;           // sensor node rows per work item of the noise weighting
     int vec_chunk;          // elements per work item of the vector kernels
     int precond;
     int n_fdwt_slots;       // partial slots written by one wavelet-analysis pass per frame
@@ -191,6 +192,7 @@ constexpr int TILE_NT = 256;          // threads of a wavelet tile block
 constexpr int VEC_CHUNK = 2048;   // default elements per work item of the vector kernels
 constexpr int PROJ_ROWS = 8;      // default node rows per projection work item (4, 8 or 16)
 constexpr int PROJ_ROWS_MIN = 4;  // fewest node rows per projection work item
+constexpr int WGT_ROWS_MAX = 8;   // most node rows per weighting work item
 
 // Dynamic LDS of k_weights for a sensor of nn nodes and ns subapertures per
 // side: the band's node rows with one halo row on each side and the weighted

@@ -486,8 +486,31 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
     load_filters(P, hf, gf);
     const T* src = vptr<T>(J, in_vec, it.frame) + Ly.coff;
     const C* llg = ll_ptr<C>(J, it.frame) + Ly.ll_off[level];
-    const C* lll = nullptr;    // LL_k rebuilt in LDS by this tile, else read from llg
-    if (level == Ly.k0 && Ly.fuse) {
+    // the window's detail coefficients (and, from scratch, its low-pass
+    // values) are loaded first into registers, so that a fused tile's coarse
+    // rebuild overlaps their latency; clamped, always valid addresses
+    const int cx0 = (x0 >> 1) - 2, cy0 = (y0 >> 1) - 2;
+    constexpr int WIT = (CW * CW + TILE_NT - 1) / TILE_NT;
+    int wo[WIT];
+    T rLH[WIT], rHL[WIT], rHH[WIT];
+    C rLL[WIT];
+    const bool fused = level == Ly.k0 && Ly.fuse;
+#pragma unroll
+    for (int k = 0; k < WIT; ++k) {
+        const int e = min(static_cast<int>(threadIdx.x) + k * TILE_NT, CW * CW - 1);
+        const int a = e / CW, b = e % CW;
+        int gx = cx0 + a, gy = cy0 + b;   // periodic wrap (|offset| < 2H)
+        gx += gx < 0 ? H : 0;
+        gy += gy < 0 ? H : 0;
+        while (gx >= H) gx -= H;
+        while (gy >= H) gy -= H;
+        wo[k] = gx * H + gy;
+        rLH[k] = src[static_cast<int64_t>(gx) * N + H + gy];
+        rHL[k] = src[static_cast<int64_t>(H + gx) * N + gy];
+        rHH[k] = src[static_cast<int64_t>(H + gx) * N + H + gy];
+        rLL[k] = fused ? C(0) : llg[wo[k]];
+    }
+    if (fused) {
         // rebuild LL_k0 = the synthesis of levels J..k0+1 of the coarse block
         // (Mallat top-left M0 x M0) in LDS; every tile of this level repeats it
         extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -501,21 +524,19 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
             syn_pass(Ac, M0, Mc, 0, hf, gf);
             syn_pass(Ac, M0, Mc, 1, hf, gf);
         }
-        lll = Ac;
-    }
-    const int cx0 = (x0 >> 1) - 2, cy0 = (y0 >> 1) - 2;
 #pragma unroll
-    for (int e = threadIdx.x; e < CW * CW; e += TILE_NT) {
-        const int a = e / CW, b = e % CW;
-        int gx = cx0 + a, gy = cy0 + b;   // periodic wrap (|offset| < 2H)
-        gx += gx < 0 ? H : 0;
-        gy += gy < 0 ? H : 0;
-        while (gx >= H) gx -= H;
-        while (gy >= H) gy -= H;
-        sLL[a][b] = lll ? lll[gx * H + gy] : llg[gx * H + gy];
-        sLH[a][b] = static_cast<C>(src[static_cast<int64_t>(gx) * N + H + gy]);
-        sHL[a][b] = static_cast<C>(src[static_cast<int64_t>(H + gx) * N + gy]);
-        sHH[a][b] = static_cast<C>(src[static_cast<int64_t>(H + gx) * N + H + gy]);
+        for (int k = 0; k < WIT; ++k) rLL[k] = Ac[wo[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < WIT; ++k) {
+        const int e = static_cast<int>(threadIdx.x) + k * TILE_NT;
+        if (e < CW * CW) {
+            const int a = e / CW, b = e % CW;
+            sLL[a][b] = rLL[k];
+            sLH[a][b] = static_cast<C>(rLH[k]);
+            sHL[a][b] = static_cast<C>(rHL[k]);
+            sHH[a][b] = static_cast<C>(rHH[k]);
+        }
     }
     __syncthreads();
     // along x: output rows 2p and 2p + 1 (x0 is even) from coarse rows p + 2 - t
@@ -955,7 +976,7 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     const int m = it.a;
     const WfsInfo& w = P.wfs[m];
     const int nn = w.nn, ns = w.n_sub;
-    const int PR = P.proj_rows;
+    const int PR = P.wgt_rows;
     const int r0 = it.b * PR;
     const int rows = min(PR, nn - r0);
     double* su = reinterpret_cast<double*>(smem_raw);
@@ -972,9 +993,21 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
         return;
     }
     const int ua = max(r0 - 1, 0), ub = min(r0 + PR, nn - 1);
+    // measurement index of this thread's first WQ subapertures of the weighted
+    // rows ia..ib, loaded with the node rows (their latency then overlaps the
+    // means); clamped, always valid addresses
+    const int ia = ua, ib = min(r0 + PR - 1, ns - 1);
+    const int nsl = (ib - ia + 1) * ns;
+    constexpr int WQ = 4;
+    int qpre[WQ];
+#pragma unroll
+    for (int k = 0; k < WQ; ++k) {
+        const int e = min(static_cast<int>(threadIdx.x) + k * static_cast<int>(blockDim.x), nsl - 1);
+        qpre[k] = w.maskmap[(ia + e / ns) * ns + e % ns];
+    }
     for (int e = threadIdx.x; e < (ub - ua + 1) * nn; e += blockDim.x) su[e] = ug[ua * nn + e];
-    // the band records of this sensor, gathered in parallel
-    const int nb = (nn + PR - 1) / PR;
+    // the band records of this sensor (one per projection band), gathered in parallel
+    const int nb = (nn + P.proj_rows - 1) / P.proj_rows;
     const int K = w.agg ? 2 * w.S : 4;
     {
         const double* rec = vptr<double>(J, V_SPART, it.frame) + w.sp_off;
@@ -1043,11 +1076,14 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     }
     __syncthreads();
     // weighted slopes of subaperture rows ia..ib (the rows next to the band)
-    const int ia = ua, ib = min(r0 + PR - 1, ns - 1);
-    for (int e = threadIdx.x; e < (ib - ia + 1) * ns; e += blockDim.x) {
+    int kq = 0;
+    for (int e = threadIdx.x; e < nsl; e += blockDim.x, ++kq) {
         const int li = e / ns, j = e % ns;
         const int i = ia + li;
-        const int q = w.maskmap[i * ns + j];
+        int q = qpre[0];
+#pragma unroll
+        for (int k = 1; k < WQ; ++k) q = kq == k ? qpre[k] : q;
+        if (kq >= WQ) q = w.maskmap[i * ns + j];
         Acc wx = 0, wy = 0;
         if (q >= 0) {
             if (w.agg) {

@@ -62,6 +62,8 @@ struct Sched {
     int n_sensor = 0;
     const Item* proj = nullptr;
     int n_proj = 0;
+    const Item* wgt = nullptr;          // noise-weighting items (bands of wgt_rows node rows)
+    int n_wgt = 0;
     const Item* adj = nullptr;
     int n_adj = 0;
     int lds_adj[2] = {};
@@ -273,7 +275,7 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // layer's tile partials to its own and writes the layer total after them
 // (the consumer sums L totals); the vector passes use one slot per chunk.
 int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
-    std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj;
+    std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj, wgt;
     int lds_lvl[2][WM_MAXLEV + 1] = {};
     std::vector<Item> tiled[WM_MAXLEV + 1];
     int maxk0 = 0, lds_i[2] = {}, lds_f[2] = {}, lds_s = 0, lds_a[2] = {}, lds_w = 0, lds_p = 0, taps_a = 2;
@@ -319,9 +321,11 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                 sensor.push_back(Item{jp, f, m, 0, 0, 0, 0, 0});
                 const int nb = ceil_div(P->host.wfs[m].nn, P->host.proj_rows);
                 for (int b = 0; b < nb; ++b) proj.push_back(Item{jp, f, m, b, 0, 0, 0, 0});
+                const int nbw = ceil_div(P->host.wfs[m].nn, P->host.wgt_rows);
+                for (int b = 0; b < nbw; ++b) wgt.push_back(Item{jp, f, m, b, 0, 0, 0, 0});
                 const int nn = P->host.wfs[m].nn;
                 lds_s = std::max(lds_s, static_cast<int>(nn * nn * sizeof(double)));
-                lds_w = std::max(lds_w, weights_lds_bytes(nn, P->host.wfs[m].n_sub, P->host.proj_rows));
+                lds_w = std::max(lds_w, weights_lds_bytes(nn, P->host.wfs[m].n_sub, P->host.wgt_rows));
                 lds_p = std::max(lds_p, proj_lds_bytes(P->L, nn, P->host.proj_rows));
             }
             const int nch = static_cast<int>((P->n + P->host.vec_chunk - 1) / P->host.vec_chunk);
@@ -382,6 +386,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     add(proj);
     add(adj);
     for (int k = 1; k <= WM_MAXLEV; ++k) add(tiled[k]);
+    add(wgt);
     S->buf = std::make_shared<DevBuf>();
     const size_t bytes = std::max<size_t>(all.size(), 1) * sizeof(Item);
     hipError_t e = hipMalloc(&S->buf->p, bytes);
@@ -400,6 +405,8 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     S->n_proj = static_cast<int>(proj.size());
     S->adj = base + offs[5];
     S->n_adj = static_cast<int>(adj.size());
+    S->wgt = base + offs[6 + WM_MAXLEV];
+    S->n_wgt = static_cast<int>(wgt.size());
     for (int c = 0; c < 2; ++c) S->lds_adj[c] = lds_a[c];
     S->adj_taps = taps_a;
     for (int c = 0; c < 2; ++c)
@@ -613,7 +620,7 @@ void run_apply(const JobArgs& a, const Sched& Sc, int x_vec, int y_vec, int c64,
     run_idwt<T, S>(a, Sc, x_vec, V_PHI, c64, s);
     timed(WMCAO_K_PROJECT, Sc.b_project, s, [&] { launch_project<T, S>(a, Sc.proj, Sc.n_proj, V_PHI, 1, Sc.lds_project, s); });
     timed(WMCAO_K_WEIGHTS, Sc.b_sensor[0], s,
-          [&] { launch_weights<T, S>(a, Sc.proj, Sc.n_proj, V_NODE, Sc.lds_weights, s); });
+          [&] { launch_weights<T, S>(a, Sc.wgt, Sc.n_wgt, V_NODE, Sc.lds_weights, s); });
     run_adjoint<T, S>(a, Sc, c64, s);
     run_fdwt<T, S>(a, Sc, SRC_PT, V_FP, y_vec, EPI_APPLY, x_vec, c64, s);
 }
@@ -1060,6 +1067,7 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
     H.dtype = opts->dtype;
     H.op64 = p->op64;
     H.proj_rows = opts->proj_rows ? opts->proj_rows : PROJ_ROWS;
+    H.wgt_rows = std::min(H.proj_rows, WGT_ROWS_MAX);
     H.vec_chunk = opts->vec_chunk ? opts->vec_chunk : VEC_CHUNK;
     p->adj_lds = opts->adj_lds ? opts->adj_lds : ADJ_LDS;
     H.precond = opts->precond;
@@ -1704,6 +1712,7 @@ int wmcao_solve_noalloc(wmcao_plan_t plan, const void* slopes, void* coeffs, int
     for (int k = 0; k <= WM_MAXLEV; ++k) v.n_tiled[k] = scale(full->n_tiled[k]);
     v.n_sensor = scale(full->n_sensor);
     v.n_proj = scale(full->n_proj);
+    v.n_wgt = scale(full->n_wgt);
     v.n_adj = scale(full->n_adj);
     v.n_vec = scale(full->n_vec);
     v.frames = batch;
