@@ -275,6 +275,55 @@ def test_c4_mixed_sizes_one_launch_every_frame():
         p.close()
 
 
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["halves", "two-types"])
+def test_packed_concurrent_groups_equal_one_stream(mixed):
+    """A packed multi-plan solve of 7 E-ELT frames (2.6 M coefficients) and 8
+    frames of the 8 m system runs as two concurrent groups: the halves of
+    every plan's frames when all plans share one operator type ("halves": the
+    8 m plan with single-precision operators), or one group per operator type
+    ("two-types": the 8 m plan's default FP64 operators).  Coefficients equal,
+    bit for bit, those of the same packed solve with plans limited to one
+    stream, eager and as a graph replay."""
+    require_gpu()
+    import torch
+    from paper_1302_3734_amd import Plan, solve_multi
+    c2, c1 = WL.config_c2(), WL.config_c1()
+    sig2 = [0.2] * 6 + [0.02, 0.006, 0.004]
+    sig1 = [0.1] * len(c1["wfs"])
+    counts = [7, 8]
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    outs = {}
+    for streams in (1, 2):
+        kw1 = {} if mixed else {"op_precision": 32}
+        plans = [Plan(c2, sig2, dtype="f32", max_batch=counts[0], streams=streams),
+                 Plan(c1, sig1, dtype="f32", max_batch=counts[1], streams=streams, **kw1)]
+        if streams == 1:
+            slopes = [torch.randn(c, p.n_slopes, dtype=torch.float32, device="cuda", generator=gen) * 0.1
+                      for c, p in zip(counts, plans)]
+            x0 = [torch.randn(c, p.n, dtype=torch.float32, device="cuda", generator=gen) * 0.01
+                  for c, p in zip(counts, plans)]
+        say(f"[packed] mixed={mixed} streams={streams}")
+        res = []
+        coeffs = [x.clone() for x in x0]
+        solve_multi(plans, slopes, coeffs, n_iter=5, warm_start=True)
+        torch.cuda.synchronize()
+        res.append([c.clone() for c in coeffs])
+        stream = torch.cuda.Stream()
+        coeffs = [x.clone() for x in x0]
+        with torch.cuda.stream(stream):
+            solve_multi(plans, slopes, coeffs, n_iter=5, warm_start=True, graph=True)
+        stream.synchronize()
+        res.append([c.clone() for c in coeffs])
+        outs[streams] = res
+        for p in plans:
+            p.close()
+    for mode in range(2):
+        for a, b in zip(outs[1][mode], outs[2][mode]):
+            assert torch.equal(a, b), mode
+    for a, b in zip(outs[2][0], outs[2][1]):
+        assert torch.equal(a, b)
+
 def test_c2_batch32_bench_configuration_every_frame():
     """The benchmark's launch: E-ELT (C2) FP32, 32 frames of their own seeded
     noise in one eager solve with the default plan (single-precision
