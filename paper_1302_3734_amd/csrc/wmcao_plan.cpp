@@ -1107,6 +1107,9 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
             Ly.D[k - 1] = d * d * (std::pow(opts->L0_m, -11.0 / 3.0) + std::pow(nu, 11.0 / 3.0)) / c_rho;
         }
     }
+    // the projection addresses a frame's pixels with 32-bit byte offsets (FP64 at most)
+    if (off * 8 >= (int64_t(1) << 31))
+        return fail(WMCAO_ERR_UNSUPPORTED, "layers too large: a frame's pixels must stay under 2 GiB");
     p->n = off;
     p->ll_size = lloff;
     H.n = off;
