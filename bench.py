@@ -464,6 +464,43 @@ def large_batch(cfg, sig, slopes32, shapes, n_iter=10, frames=128, steps=8):
             "work_shapes": shapes, "stages": stages, "kernels": kernels}
 
 
+def control_loop(cfg, sig, slopes, steps=20, warmup=3):
+    """The paper's closed loop at E-ELT scale (Sec. 4.2, Alg. 4.1): one
+    pseudo-open-loop control step per frame (open-loop slopes through the
+    mirror-to-slope map, tomography by 10 warm PCG iterations, W^-1, fitting
+    of the three mirrors over 25 directions by 4 warm CG iterations, the
+    integrator), single frames as they arrive, FP32 and FP64.  Times per step
+    from HIP events; the loop starts from zero commands and is fed the
+    benchmark's frozen-flow slopes of one telescope stream."""
+    import torch
+    from paper_1302_3734_amd.fitting import PolcController
+    from workloads.fitting import fitting_systems, mirror_wfs_system
+    atm, dm = fitting_systems(cfg)
+    dmw = mirror_wfs_system(cfg)
+    out = {"workload": "E-ELT POLC step: open-loop slopes, tomography 10 warm its, W^-1, "
+                       "fitting of 3 mirrors (~10,500 actuators) over 25 directions, 4 warm its",
+           "actuators": None}
+    for dt, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        ctl = PolcController(cfg, sig, dmw, atm, dm, dtype=dt, gain=0.4, n_iter=10)
+        out["actuators"] = ctl.fitter.n_act
+        s = slopes.to(tdt)
+        for t in range(warmup):
+            ctl.step(s[t % s.shape[0]][None].contiguous())
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for t in range(steps):
+            ev[t][0].record()
+            ctl.step(s[(warmup + t) % s.shape[0]][None].contiguous())
+            ev[t][1].record()
+        torch.cuda.synchronize()
+        lat = sorted(a.elapsed_time(b) for a, b in ev)
+        out[dt] = {"p50_ms_per_step": round(statistics.median(lat), 4),
+                   "p99_ms_per_step": round(pctl(lat, 0.99), 4)}
+        ctl.close()
+    return out
+
+
 def iteration_sweep(frames=(1, 11, 21, 31), iters=(1, 2, 3, 4, 6, 8, 10, 15, 20)):
     """Speed/quality trade-off of the paper's three solvers on the same E-ELT
     frames (Sec. 5.2-5.3; a synthetic stand-in for its iteration study): nine
@@ -543,9 +580,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the extra workloads (same as --extra none)")
-    ap.add_argument("--extra", default="c2x128,c3,c4,sweep",
+    ap.add_argument("--extra", default="c2x128,c3,c4,polc,sweep",
                     help="comma list of extra workloads: c2x128 (128 E-ELT frames per solve), c3 "
-                         "(128 8 m frames), c4 (mixed sizes), sweep (iteration study), or none")
+                         "(128 8 m frames), c4 (mixed sizes), polc (closed-loop control steps), "
+                         "sweep (iteration study), or none")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 256 MiB device copy (byte-counter calibration)")
     args = ap.parse_args()
@@ -795,6 +833,9 @@ def main():
     if "c4" in extras:
         result["c4_mixed"] = mixed_batch()
         print(f"[bench] c4 {result['c4_mixed']}", flush=True)
+    if "polc" in extras:
+        result["control_loop"] = control_loop(cfg, sig, slopes32[1:, 0])
+        print(f"[bench] control loop {result['control_loop']}", flush=True)
     if "sweep" in extras:
         result["iteration_sweep"] = iteration_sweep()
         sw = result["iteration_sweep"]
