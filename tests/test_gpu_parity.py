@@ -9,7 +9,7 @@ import pytest
 import oracle as O
 import workloads as WL
 from tests.gpu_common import maxrel, rel, require_gpu, say, setup, to_dev, to_np
-from tests.tiny import tiny_config, tiny_max_config, tiny_ragged_config
+from tests.tiny import tiny_config, tiny_edge_config, tiny_max_config, tiny_ragged_config
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +47,9 @@ CASES = [
     ("c2-f32-rows16", WL.config_c2, "f32", {"proj_rows": 16, "adj_lds": 64 * 1024}),
     ("c2-f64-rows4", WL.config_c2, "f64", {"proj_rows": 4, "adj_lds": 16 * 1024, "vec_chunk": 4096}),
     ("max-f64-rows16", tiny_max_config, "f64", {"proj_rows": 16, "vec_chunk": 1024}),
+    # footprints at the layer edges, read through windows that wrap around them
+    ("edge-tiled-f64", tiny_edge_config, "f64", {"tile": 16, "lds_budget": 512}),
+    ("edge-tiled-f32-op32", tiny_edge_config, "f32", {"tile": 16, "lds_budget": 256, "op_precision": 32}),
 ]
 
 _cache = {}

@@ -51,3 +51,20 @@ def tiny_max_config():
     wfs.append(_wfs(False, (0.1 * ARCMIN, -0.2 * ARCMIN), 8, tt_aggregate=2))
     cfg["wfs"] = wfs
     return _check(cfg)
+
+
+def tiny_edge_config():
+    """Footprints that reach the layers' first pixel row and column: two
+    16 x 16 layers (2 levels) and a high-order NGS 1.1 arcmin off axis in both
+    directions, whose nodes on the 6 km layer start 0.16 pixel from the edge,
+    plus an on-axis LGS.  With 16-pixel tiles the one level-1 analysis tile
+    of a layer reads a window that wraps around both edges back into that
+    footprint."""
+    cfg = tiny_config(tt=False)
+    cfg = copy.deepcopy(cfg)
+    cfg["name"] = "tiny-edge"
+    cfg["cfg_id"] = 903
+    cfg["layers"] = _layers([0.0, 6e3], [0.7, 0.3], [16, 16])
+    cfg["levels"] = 2
+    cfg["wfs"] = [_wfs(True, (0.0, 0.0), 8), _wfs(False, (-1.1 * ARCMIN, -1.1 * ARCMIN), 8)]
+    return _check(cfg)
