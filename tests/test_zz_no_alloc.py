@@ -26,9 +26,12 @@ def _noalloc(plan, slopes, x, batch, n_iter, warm, resid=None, status=None):
                                    _stream_ptr())
 
 
-@pytest.mark.parametrize("name,dt,batches", [("C1", "f32", (16, 5)), ("C1", "f64", (8, 3)),
-                                              ("C2", "f32", (2, 1))])
-def test_noalloc_solve_equals_solve(name, dt, batches):
+@pytest.mark.parametrize("name,dt,batches,kw", [("C1", "f32", (16, 5), {}), ("C1", "f64", (8, 3), {}),
+                                                 ("C2", "f32", (2, 1), {}),
+                                                 # projection and weighting items of different sizes
+                                                 ("C2", "f32", (2, 1), {"proj_rows": 16})],
+                         ids=["C1-f32", "C1-f64", "C2-f32", "C2-f32-rows16"])
+def test_noalloc_solve_equals_solve(name, dt, batches, kw):
     require_gpu()
     import torch
     from paper_1302_3734_amd import Plan
@@ -37,7 +40,7 @@ def test_noalloc_solve_equals_solve(name, dt, batches):
     tdt = torch.float32 if dt == "f32" else torch.float64
     B = batches[0]
     sl = to_dev(np.stack([slopes_for(S, cfg, sig, 1 + f, seed_frame=0) for f in range(B)]), tdt)
-    plan = Plan(cfg, sig, dtype=dt, max_batch=B)
+    plan = Plan(cfg, sig, dtype=dt, max_batch=B, **kw)
     gen = torch.Generator(device="cuda").manual_seed(3)
     x0 = torch.randn(B, plan.n, dtype=tdt, device="cuda", generator=gen) * 0.01
     n_it = 6
