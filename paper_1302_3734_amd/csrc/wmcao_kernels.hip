@@ -835,9 +835,10 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
     double* rt = cs + L * nn;
     int* cj0 = reinterpret_cast<int*>(rt + L * PR1);
     int* rbase = cj0 + L * nn;
-    // e = l K + k, split with a float reciprocal: exact here, since the
-    // quotient's fractional part is at least 1 / (2 K) away from an integer
-    // and e < 2^12 keeps the product's error near 2^-12
+    // e = l K + k, split with a float reciprocal: exact here, since
+    // (e + 1/2) / K is at least 1 / (2 K) > 2^-9 away from an integer, while
+    // the product's error is below 2^-19 (quotient under 16, relative error
+    // under 2^-23)
     const float rK = 1.0f / static_cast<float>(K);
     for (int e = threadIdx.x; e < L * K; e += blockDim.x) {
         const int l = static_cast<int>((static_cast<float>(e) + 0.5f) * rK), k = e - l * K;
