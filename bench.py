@@ -17,6 +17,7 @@ one stream, where a launch's event time is its own), the per-frame FP64 solve
 as a comparison, and the CPU oracle on a bounded sample.
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -111,14 +112,19 @@ SERVED = ["C4-8m-ngs", "C4-16m-ngs", "C4-39m-lgs", "C4-42m-lgs"]
 # one lane per configuration: measured faster than packing the two E-ELT-class
 # configurations into one lane (their launches overlap on two lanes)
 SERVED_LANES = {"C4-8m-ngs": 0, "C4-16m-ngs": 1, "C4-39m-lgs": 2, "C4-42m-lgs": 3}
+# two lanes per configuration, one launch in flight on each: measured p99
+# 3.0-3.1 ms against 3.2-5.4 ms for one lane each with two in flight (and
+# 3 lanes per configuration no better)
+SERVED_SLOTS, SERVED_DEPTH = 2, 1
 
 
-def served_stream(duration_s, rate_hz, n_iter, dtype="f32", plain=False, tuned=True):
+def served_stream(duration_s, rate_hz, n_iter, dtype="f32", plain=False, tuned=True,
+                  slots=SERVED_SLOTS, depth=SERVED_DEPTH):
     """Poisson arrivals over four telescope configurations (8 m and 16 m
     NGS-only, 39 m and 42 m LGS-only), one stream each at rate_hz/4, served
-    with continuous batching (one lane per configuration, two launches in
-    flight per lane, backlogs batched); frozen-flow frames from a pool of 8
-    per stream.  The
+    with continuous batching (`slots` lanes per configuration with `depth`
+    launches in flight each, or with slots = 1 one lane per configuration;
+    backlogs batched); frozen-flow frames from a pool of 8 per stream.  The
     same server runs in FP32 or FP64.  With plain, the arrivals are served the
     plain way instead: one frame per launch, one launch at a time (FP64).
     Returns latency percentiles and throughput."""
@@ -147,11 +153,18 @@ def served_stream(duration_s, rate_hz, n_iter, dtype="f32", plain=False, tuned=T
     if plain:
         srv = Server(cfgs, {nm: nm for nm in names}, dtype=dtype, n_iter=n_iter, hip_streams=1,
                      pack=False, depth=1, max_frames=1, tuned=tuned)
+    elif slots > 1:
+        srv = Server(cfgs, {nm: nm for nm in names}, dtype=dtype, n_iter=n_iter, slots=slots,
+                     depth=depth, max_frames=4, tuned=tuned)
     else:
         srv = Server(cfgs, {nm: nm for nm in names}, dtype=dtype, n_iter=n_iter,
-                     lane_map=SERVED_LANES, pack=True, depth=2, max_frames=4, tuned=tuned)
+                     lane_map=SERVED_LANES, pack=True, depth=depth, max_frames=4, tuned=tuned)
     switch = sys.getswitchinterval()
     sys.setswitchinterval(1e-4)       # hand the interpreter lock to the server threads promptly
+    # no cyclic garbage collection while frames are served: its passes over the
+    # growing records would stall the server threads for milliseconds
+    gc.collect()
+    gc.disable()
     arrivals = sorted((t, nm) for k, nm in enumerate(names)
                       for t in WL.poisson_arrivals(500 + k, rate_hz / len(names), duration_s))
     torch.cuda.synchronize()
@@ -167,6 +180,7 @@ def served_stream(duration_s, rate_hz, n_iter, dtype="f32", plain=False, tuned=T
     for f in futs:
         f.result(timeout=120)
     elapsed = time.perf_counter() - t0
+    gc.enable()
     sys.setswitchinterval(switch)
     srv.close()
     lat = srv.latencies_ms()
@@ -175,8 +189,9 @@ def served_stream(duration_s, rate_hz, n_iter, dtype="f32", plain=False, tuned=T
     for nm in names:
         lv = [1e3 * (r[3] - r[2]) for r in srv.records if r[0] == nm]
         per_cfg[nm] = {"p50_ms": round(pctl(lv, 0.5), 4), "p99_ms": round(pctl(lv, 0.99), 4)}
+    lanes = (f"{slots} lanes per configuration" if slots > 1 else f"lanes {SERVED_LANES}")
     mode = ("plain FP64, one frame per launch, one launch at a time" if plain else
-            f"{dtype.upper()} continuous batching: lanes {SERVED_LANES}, depth 2, up to 4 "
+            f"{dtype.upper()} continuous batching: {lanes}, depth {depth}, up to 4 "
             f"frames per telescope stream per launch")
     return {"mode": mode, "configs": names, "rate_hz": rate_hz, "duration_s": duration_s,
             "frames": len(lat), "frames_per_s": round(len(lat) / elapsed, 1),
@@ -185,7 +200,7 @@ def served_stream(duration_s, rate_hz, n_iter, dtype="f32", plain=False, tuned=T
             "p99_queue_wait_ms": round(pctl(wait, 0.99), 4),
             "p50_launch_to_result_ms": round(pctl(run, 0.5), 4),
             "p99_launch_to_result_ms": round(pctl(run, 0.99), 4),
-            "launches": srv.launches,
+            "launches": srv.launches, "launches_per_lane": srv.lane_launches,
             "mean_frames_per_launch": round(float(np.mean(srv.frames_in_launch)), 3),
             "per_config": per_cfg, "work_shapes": srv.work_shapes}
 

@@ -261,6 +261,26 @@ int wmcao_solve_multi_graph(const wmcao_plan_t* plans, const void* const* slopes
                             void* const* coeffs, const int* counts, int n_plans, int n_iter,
                             int warm_start, void* hip_stream);
 
+/* One launch of a request loop that serves frames as they arrive, in three
+ * steps on hip_stream (not the default stream), for a caller whose host time
+ * per launch matters: one kernel copies frame i's slopes (slopes[i],
+ * n_slopes values) and warm start (warm[i], n_coeffs values) into row i of
+ * the staging buffers stage_slopes and stage_coeffs (the plan's dtype, at
+ * least count rows each); the count frames are then solved as
+ * wmcao_solve_multi_graph solves them with those buffers (warm start, n_iter
+ * iterations, the capture kept and replayed for later calls with the same
+ * buffers and count); one kernel then copies staging row out_rows[i] of the
+ * solution to out_ptrs[i] (n_coeffs values) for i < n_out.  All pointers are
+ * device pointers; the inputs must be complete when hip_stream reaches the
+ * call.  The outputs are written after the solve, so an output may be one of
+ * the call's inputs, but none may overlap the staging buffers.
+ * count: 1 .. min(max_batch, 20); n_out: 0 .. 40.  Returns
+ * WMCAO_ERR_INVALID_ARG for NULL pointers or counts and rows out of range,
+ * otherwise as wmcao_solve_multi_graph. */
+int wmcao_serve_launch(wmcao_plan_t plan, void* stage_slopes, void* stage_coeffs, int count,
+                       const void* const* slopes, const void* const* warm, int n_out,
+                       const int* out_rows, void* const* out_ptrs, int n_iter, void* hip_stream);
+
 /* Capture the launches of wmcao_solve with these arguments into a HIP graph
  * owned by the plan, replacing any earlier capture, and replay it: later
  * wmcao_solve_graph calls with the same arguments replay without re-recording.

@@ -76,6 +76,9 @@ def lib():
         L.wmcao_profile_enable.argtypes = [vp, C.c_int]
         L.wmcao_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int),
                                          C.POINTER(C.c_double)]
+        L.wmcao_serve_launch.argtypes = [vp, vp, vp, C.c_int, C.POINTER(vp), C.POINTER(vp), C.c_int,
+                                         C.POINTER(C.c_int), C.POINTER(vp), C.c_int, vp]
+        L.wmcao_serve_launch.restype = C.c_int
         L.wmcao_axpby.argtypes = [C.c_int, C.c_int64, C.c_double, vp, C.c_double, vp, vp, vp]
         L.wmcao_axpby.restype = C.c_int
         L.wmcao_plan_destroy.argtypes = [vp]
@@ -102,7 +105,7 @@ def check(rc, where):
 EXPORTED = ("wmcao_plan", "wmcao_sizes", "wmcao_coeffs_to_layers", "wmcao_layers_to_coeffs",
             "wmcao_forward_layers", "wmcao_rhs", "wmcao_apply_A", "wmcao_precond_diag",
             "wmcao_solve", "wmcao_solve_noalloc", "wmcao_solve_multi", "wmcao_solve_multi_graph",
-            "wmcao_solve_graph",
+            "wmcao_solve_graph", "wmcao_serve_launch",
             "wmcao_profile_enable",
             "wmcao_profile_read", "wmcao_axpby", "wmcao_plan_destroy",
             "wmcao_strerror", "wmcao_last_error")

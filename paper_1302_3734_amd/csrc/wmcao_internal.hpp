@@ -186,6 +186,14 @@ void launch_axpby(int64_t n, double a, const T* x, double b, const T* y, T* out,
 template <class S, class D>
 void launch_cast(const S* in, D* out, int64_t n, hipStream_t s);
 
+constexpr int SERVE_ROWS = 40;   // rows of one staging copy (2 x 16 frames in, or results out)
+struct CopyRows {
+    const void* src[SERVE_ROWS];
+    void* dst[SERVE_ROWS];
+    int64_t len[SERVE_ROWS];   // 4-byte words
+};
+void launch_copy_rows(const CopyRows& c, int rows, int64_t max_len, hipStream_t s);
+
 constexpr size_t NOALLOC_BYTES = size_t(32) << 20;   // scratch of the allocation-free solve
 constexpr int FUSE_LDS = 32 * 1024;   // largest low-pass block a synthesis tile rebuilds
 constexpr int TILE_NT = 256;          // threads of a wavelet tile block

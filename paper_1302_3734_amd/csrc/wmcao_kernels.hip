@@ -30,6 +30,7 @@
 // accumulated in FP64 and reduced in a fixed order (one partial per block,
 // summed by the consumer), so a frame's result does not depend on what else
 // is in the batch.
+#include <algorithm>
 #include <initializer_list>
 #include <type_traits>
 
@@ -1947,6 +1948,33 @@ void launch_axpby(int64_t n, double a, const T* x, double b, const T* y, T* out,
     if (n <= 0) return;
     hipLaunchKernelGGL(k_axpby<T>, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
                        n, a, x, b, y, out);
+}
+
+// Row i copies len[i] 4-byte words from src[i] to dst[i] (blockIdx.y = row),
+// 16 bytes per access where the row allows it: the staging copies of a
+// served launch, in one launch before and one after the solve.
+__global__ void __launch_bounds__(256)
+k_copy_rows(const CopyRows c) {
+    const int i = blockIdx.y;
+    const int64_t n = c.len[i];
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const uintptr_t al = reinterpret_cast<uintptr_t>(c.src[i]) | reinterpret_cast<uintptr_t>(c.dst[i]);
+    if ((al & 15) == 0 && (n & 3) == 0) {
+        const uint4* s4 = static_cast<const uint4*>(c.src[i]);
+        uint4* d4 = static_cast<uint4*>(c.dst[i]);
+        for (int64_t e = t0; e < n / 4; e += step) d4[e] = s4[e];
+    } else {
+        const uint32_t* s1 = static_cast<const uint32_t*>(c.src[i]);
+        uint32_t* d1 = static_cast<uint32_t*>(c.dst[i]);
+        for (int64_t e = t0; e < n; e += step) d1[e] = s1[e];
+    }
+}
+
+void launch_copy_rows(const CopyRows& c, int rows, int64_t max_len, hipStream_t s) {
+    if (rows <= 0 || max_len <= 0) return;
+    const unsigned bx = static_cast<unsigned>(std::min<int64_t>((max_len / 4 + 255) / 256 + 1, 256));
+    hipLaunchKernelGGL(k_copy_rows, dim3(bx, static_cast<unsigned>(rows)), dim3(256), 0, s, c);
 }
 
 template <class S, class D>

@@ -1835,6 +1835,52 @@ int wmcao_profile_read(wmcao_plan_t plan, int kind, double* total_ms, int* launc
     return WMCAO_OK;
 }
 
+int wmcao_serve_launch(wmcao_plan_t plan, void* stage_slopes, void* stage_coeffs, int count,
+                       const void* const* slopes, const void* const* warm, int n_out,
+                       const int* out_rows, void* const* out_ptrs, int n_iter, void* hip_stream) {
+    if (!plan || !stage_slopes || !stage_coeffs || !slopes || !warm || (n_out > 0 && (!out_rows || !out_ptrs)))
+        return fail(WMCAO_ERR_INVALID_ARG, "NULL argument");
+    if (count < 1 || count > plan->max_batch || 2 * count > SERVE_ROWS)
+        return fail(WMCAO_ERR_INVALID_ARG, "count must be 1 .. min(max_batch, " +
+                                               std::to_string(SERVE_ROWS / 2) + ")");
+    if (n_out < 0 || n_out > SERVE_ROWS)
+        return fail(WMCAO_ERR_INVALID_ARG, "n_out must be 0 .. " + std::to_string(SERVE_ROWS));
+    for (int i = 0; i < count; ++i)
+        if (!slopes[i] || !warm[i]) return fail(WMCAO_ERR_INVALID_ARG, "NULL frame pointer");
+    for (int i = 0; i < n_out; ++i)
+        if (!out_ptrs[i] || out_rows[i] < 0 || out_rows[i] >= count)
+            return fail(WMCAO_ERR_INVALID_ARG, "out row out of range");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int64_t wn = plan->n * static_cast<int64_t>(plan->esz) / 4;
+    const int64_t ws = plan->n_slopes * static_cast<int64_t>(plan->esz) / 4;
+    char* sb = static_cast<char*>(stage_slopes);
+    char* xb = static_cast<char*>(stage_coeffs);
+    DevGuard g(plan->device);
+    CopyRows in{};
+    for (int i = 0; i < count; ++i) {
+        in.src[i] = slopes[i];
+        in.dst[i] = sb + i * ws * 4;
+        in.len[i] = ws;
+        in.src[count + i] = warm[i];
+        in.dst[count + i] = xb + i * wn * 4;
+        in.len[count + i] = wn;
+    }
+    launch_copy_rows(in, 2 * count, std::max(wn, ws), s);
+    int rc = check_launch();
+    if (rc) return rc;
+    const void* sbc = stage_slopes;
+    rc = wmcao_solve_multi_graph(&plan, &sbc, &stage_coeffs, &count, 1, n_iter, 1, hip_stream);
+    if (rc) return rc;
+    CopyRows out{};
+    for (int i = 0; i < n_out; ++i) {
+        out.src[i] = xb + out_rows[i] * wn * 4;
+        out.dst[i] = out_ptrs[i];
+        out.len[i] = wn;
+    }
+    launch_copy_rows(out, n_out, wn, s);
+    return check_launch();
+}
+
 int wmcao_axpby(wmcao_dtype dtype, int64_t n, double a, const void* x, double b, const void* y,
                 void* out, void* hip_stream) {
     if (n < 0 || (n > 0 && (!x || !y || !out))) return fail(WMCAO_ERR_INVALID_ARG, "bad argument");

@@ -89,5 +89,6 @@ def test_null_arguments_rejected():
     L = _abi.lib()
     assert L.wmcao_solve(None, None, None, 1, 1, 0, None, None, None) == -1
     assert L.wmcao_apply_A(None, None, None, 1, None) == -1
+    assert L.wmcao_serve_launch(None, None, None, 1, None, None, 0, None, None, 1, None) == -1
     assert L.wmcao_sizes(None, None, None, None, None) == -1
     L.wmcao_plan_destroy(None)

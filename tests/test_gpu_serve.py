@@ -53,6 +53,49 @@ def test_served_mix_equals_alone(lanes):
         p.close()
 
 
+def test_served_slots_equal_alone():
+    """Two lanes per configuration (slots=2, one launch each in flight): a
+    frame that arrives while its predecessor is being solved starts at once
+    on the free lane from the newest result already complete.  Both lanes of
+    every configuration are used, every request completes, and every frame
+    equals the same frame solved alone from the warm start it was given,
+    bitwise."""
+    require_gpu()
+    import torch
+    from paper_1302_3734_amd import Plan
+    from paper_1302_3734_amd.serve import Server
+    c1 = WL.config_c1()
+    c8 = [c for c in WL.config_c4_classes() if c["name"] == "C4-8m-lgs"][0]
+    cfgs, pools = {}, {}
+    for cfg in (c1, c8):
+        S, sig, s, _ = setup(cfg)
+        cfgs[cfg["name"]] = (cfg, sig)
+        pools[cfg["name"]] = [torch.tensor(slopes_for(S, cfg, sig, f), dtype=torch.float32,
+                                           device="cuda") for f in range(6)]
+    streams = {"a": "C1", "b": "C4-8m-lgs"}
+    srv = Server(cfgs, streams, dtype="f32", n_iter=6, keep_inputs=True, slots=2, depth=1,
+                 max_frames=2)
+    futs = []
+    say("[serve-slots] submitting")
+    for f in range(12):
+        for st, c in streams.items():
+            futs.append((st, c, f, srv.submit(st, pools[c][f % 6])))
+        time.sleep(0.0002 * (f % 4))
+    results = [(st, c, f, fu.result(timeout=60)) for st, c, f, fu in futs]
+    srv.close()
+    say(f"[serve-slots] {len(results)} frames, launches per lane {srv.lane_launches}")
+    assert len(srv.records) == len(futs)
+    assert min(srv.lane_launches) > 0, srv.lane_launches
+    alone = {c: Plan(cfg, sig, dtype="f32", max_batch=1) for c, (cfg, sig) in cfgs.items()}
+    for st, c, f, (x, x0) in results:
+        xs = x0.clone()
+        alone[c].solve(pools[c][f % 6].reshape(1, -1), xs, n_iter=6, warm_start=True)
+        torch.cuda.synchronize()
+        assert torch.equal(xs, x), (st, f)
+    for p in alone.values():
+        p.close()
+
+
 def test_budget_queues_frames():
     """A budget that fits one frame at a time serialises the streams but
     every request still completes."""
