@@ -153,7 +153,7 @@ def served_stream(duration_s, rate_hz, n_iter, dtype="f32", plain=False, tuned=T
     if plain:
         srv = Server(cfgs, {nm: nm for nm in names}, dtype=dtype, n_iter=n_iter, hip_streams=1,
                      pack=False, depth=1, max_frames=1, tuned=tuned)
-    elif slots > 1:
+    elif slots != 1:
         srv = Server(cfgs, {nm: nm for nm in names}, dtype=dtype, n_iter=n_iter, slots=slots,
                      depth=depth, max_frames=4, tuned=tuned)
     else:
@@ -189,7 +189,7 @@ def served_stream(duration_s, rate_hz, n_iter, dtype="f32", plain=False, tuned=T
     for nm in names:
         lv = [1e3 * (r[3] - r[2]) for r in srv.records if r[0] == nm]
         per_cfg[nm] = {"p50_ms": round(pctl(lv, 0.5), 4), "p99_ms": round(pctl(lv, 0.99), 4)}
-    lanes = (f"{slots} lanes per configuration" if slots > 1 else f"lanes {SERVED_LANES}")
+    lanes = (f"lanes per configuration {slots}" if slots != 1 else f"lanes {SERVED_LANES}")
     mode = ("plain FP64, one frame per launch, one launch at a time" if plain else
             f"{dtype.upper()} continuous batching: {lanes}, depth {depth}, up to 4 "
             f"frames per telescope stream per launch")

@@ -77,9 +77,10 @@ class Server:
     configs: {name: (cfg dict, sigmas)}; streams: {stream name: config name}.
     hip_streams: number of lanes (default: one per configuration); configuration
     i uses lane i mod hip_streams, unless lane_map ({config name: lane index})
-    assigns the lanes.  slots > 1: every configuration gets that many lanes of
-    its own instead (hip_streams, lane_map and pack are then unused), so that
-    up to `slots` launches of one configuration run at once.  wait: how
+    assigns the lanes.  slots (an int, or {config name: int}) above 1: every
+    configuration gets that many lanes of its own instead (hip_streams,
+    lane_map and pack are then unused), so that up to that many launches of
+    one configuration run at once.  wait: how
     completions are found, "block" (a thread per lane waits on its oldest
     launch's event without holding the interpreter lock) or "poll" (one thread
     queries every lane's oldest event in turn, never while a launch may be
@@ -115,11 +116,13 @@ class Server:
         # frames of a configuration in one launch: max_frames per telescope stream
         count = {c: k * self.max_frames for c, k in collections.Counter(streams.values()).items()}
         names = [c for c in configs if count.get(c)]
-        self.slots = max(1, int(slots))
-        if self.slots > 1:
-            n_lanes = len(names) * self.slots
-            self.cfg_lanes = {c: [i * self.slots + j for j in range(self.slots)]
-                              for i, c in enumerate(names)}
+        per_cfg = slots if isinstance(slots, dict) else {c: slots for c in names}
+        self.slots = {c: max(1, int(per_cfg.get(c, 1))) for c in names}
+        if any(k > 1 for k in self.slots.values()):
+            self.cfg_lanes, n_lanes = {}, 0
+            for c in names:
+                self.cfg_lanes[c] = list(range(n_lanes, n_lanes + self.slots[c]))
+                n_lanes += self.slots[c]
         elif lane_map:
             n_lanes = max(int(lane_map[c]) for c in names) + 1
             self.cfg_lanes = {c: [int(lane_map[c])] for c in names}
@@ -200,6 +203,7 @@ class Server:
         self.running = True
         self.records = []
         self.launches = 0
+        self.failed = 0                    # frames whose launch raised (their futures hold the error)
         self.lane_launches = [0] * n_lanes
         self.frames_in_launch = []
         self.worker = threading.Thread(target=self._loop, daemon=True)
@@ -220,6 +224,9 @@ class Server:
         returns a Future resolving to (reconstruction coefficients, warm start
         or None)."""
         st = self.streams[stream]
+        if slopes.numel() != self.n_slopes[st.cfg]:
+            raise ValueError(f"stream {stream!r}: {slopes.numel()} slopes, the configuration "
+                             f"has {self.n_slopes[st.cfg]}")
         if slopes.dtype != self.torch_dtype or not slopes.is_cuda:
             slopes = slopes.to(device="cuda", dtype=self.torch_dtype)
         slopes = slopes.reshape(1, -1).contiguous()
@@ -306,8 +313,24 @@ class Server:
                         return
                     self.cv.wait(timeout=0.05)
             for lane, groups in work:
-                self._launch(lane, groups)
+                try:
+                    self._launch(lane, groups)
+                except Exception as e:   # the launch's frames fail; the server goes on
+                    self._fail(groups, e)
                 pending[lane] -= 1
+
+    def _fail(self, groups, exc):
+        """Resolve the futures of frames whose launch raised with that error."""
+        t = time.perf_counter()
+        frames = [f for per_stream in groups.values() for _, frs in per_stream for f in frs]
+        with self.cv:
+            for f in frames:
+                f.t_done = t
+                self.reserved -= self.frame_bytes[f.stream.cfg]
+                self.failed += 1
+            self.cv.notify()
+        for f in frames:
+            f.future.set_exception(exc)
 
     def _launch(self, lane, groups):
         if self.graphs and len(groups) == 1:

@@ -96,6 +96,43 @@ def test_served_slots_equal_alone():
         p.close()
 
 
+def test_failed_launch_resolves_its_futures():
+    """A launch that raises hands the error to its frames' futures; later
+    frames are still served.  A frame of the wrong size is refused at
+    submission."""
+    require_gpu()
+    import torch
+    from paper_1302_3734_amd.serve import Server
+    cfg = WL.config_c1()
+    S, sig, s, _ = setup(cfg)
+    sl = torch.tensor(s, dtype=torch.float32, device="cuda")
+
+    class Boom(RuntimeError):
+        pass
+
+    srv = Server({"C1": (cfg, sig)}, {"a": "C1"}, dtype="f32", n_iter=4, depth=1, max_frames=1)
+    with pytest.raises(ValueError):
+        srv.submit("a", sl[:-1])
+    launch = srv._launch
+    calls = []
+
+    def flaky(lane, groups):
+        calls.append(lane)
+        if len(calls) == 2:
+            raise Boom("injected")
+        return launch(lane, groups)
+
+    srv._launch = flaky
+    futs = []
+    for _ in range(4):
+        futs.append(srv.submit("a", sl))
+        futs[-1].exception(timeout=60)   # one frame at a time: the second launch is the failing one
+    srv.close()
+    outcomes = [type(f.exception()) for f in futs]
+    assert outcomes == [type(None), Boom, type(None), type(None)], outcomes
+    assert srv.failed == 1 and len(srv.records) == 3
+
+
 def test_budget_queues_frames():
     """A budget that fits one frame at a time serialises the streams but
     every request still completes."""
