@@ -159,7 +159,7 @@ void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int
                         int out_vec, int epi, int aux_vec, int lds_bytes, hipStream_t s);
 template <class T, class S>
 void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, int lds_bytes,
-                    hipStream_t s);
+                    int max_layers, hipStream_t s);
 template <class T, class S>
 void launch_weights(const JobArgs& a, const Item* items, int n, int out_vec, int lds_bytes,
                     hipStream_t s);

@@ -805,12 +805,16 @@ k_fdwt_coarse(const JobArgs args, const Item* __restrict__ items, int src, int i
 // sums for the tip/tilt projection and the low-order cells (one record per
 // band, reduced in a fixed order by k_weights).  u is kept in FP64 so that the
 // Fried differences do not cancel single-precision digits.
-constexpr int PROJ_LB = 3;   // layers whose samples a thread loads together
-
-// At most 64 VGPRs (eight waves per SIMD): left free, the compiler keeps
-// every layer's weights in registers and halves the occupancy.
-template <class T, class S>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8)))
+// LB: layers whose samples a thread loads together.  Three, at most 64 VGPRs
+// (eight waves per SIMD), for launches that fill the GPU: left free, the
+// compiler keeps every layer's weights in registers and halves the
+// occupancy.  Nine (one round of loads per node) for small launches, where
+// occupancy does not bind and every round trip is on the critical path.
+constexpr int PROJ_LB = 3;
+constexpr int PROJ_LB_WIDE = 9;
+constexpr int PROJ_WIDE_MAX = 256;    // most work items of a launch that loads nine at once
+template <class T, class S, int LB>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(LB > PROJ_LB ? 4 : 8)))
 k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int sums) {
     __shared__ double red[68];
     const Item it = items[xcd_item()];
@@ -870,18 +874,18 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
         double* u = vptr<double>(J, V_U, it.frame) + w.node_off;
         for (int li = g; li < rows_c; li += G) {
             Acc acc = 0;
-            // PROJ_LB layers per step: their samples are loaded before any is used
-            for (int l0 = 0; l0 < L; l0 += PROJ_LB) {
-                Pair<S> v[PROJ_LB][2];
+            // LB layers per step: their samples are loaded before any is used
+            for (int l0 = 0; l0 < L; l0 += LB) {
+                Pair<S> v[LB][2];
 #pragma unroll
-                for (int k = 0; k < PROJ_LB; ++k) {
+                for (int k = 0; k < LB; ++k) {
                     const int l = min(l0 + k, L - 1);   // past the last layer: a valid load, unused
                     const uint32_t o = static_cast<uint32_t>((rbase[l * PR1 + li] + cj0[l * nn + j]) * static_cast<int>(sizeof(S)));
                     v[k][0] = ld_pair<S>(rp, o);
                     v[k][1] = ld_pair<S>(rp, o + static_cast<uint32_t>(P.layer[l].N * static_cast<int>(sizeof(S))));
                 }
 #pragma unroll
-                for (int k = 0; k < PROJ_LB; ++k) {
+                for (int k = 0; k < LB; ++k) {
                     const int l = l0 + k;
                     if (l < L) {
                         // bilinear: lerp along y in both sample rows, then along x
@@ -2026,9 +2030,12 @@ void launch_fdwt_coarse(const JobArgs& a, const Item* items, int n, int src, int
 
 template <class T, class S>
 void launch_project(const JobArgs& a, const Item* items, int n, int in_vec, int sums, int lds_bytes,
-                    hipStream_t s) {
+                    int max_layers, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL((k_project<T, S>), dim3(n), dim3(512), lds_bytes, s, a, items, in_vec, sums);
+    if (n <= PROJ_WIDE_MAX && max_layers > PROJ_LB)
+        hipLaunchKernelGGL((k_project<T, S, PROJ_LB_WIDE>), dim3(n), dim3(512), lds_bytes, s, a, items, in_vec, sums);
+    else
+        hipLaunchKernelGGL((k_project<T, S, PROJ_LB>), dim3(n), dim3(512), lds_bytes, s, a, items, in_vec, sums);
 }
 
 template <class T, class S>
@@ -2151,7 +2158,7 @@ void configure_kernels() {
 // Projection and sensor stages (FP64 arithmetic): vector storage T, operator storage S.
 #define WM_INSTANTIATE_SENSORS(T, S)                                                               \
     template void launch_sensor<T, S>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
-    template void launch_project<T, S>(const JobArgs&, const Item*, int, int, int, int, hipStream_t);  \
+    template void launch_project<T, S>(const JobArgs&, const Item*, int, int, int, int, int, hipStream_t); \
     template void launch_weights<T, S>(const JobArgs&, const Item*, int, int, int, hipStream_t);
 
 // The PCG vector steps: storage T.

@@ -76,6 +76,7 @@ struct Sched {
     int lds_sensor = 0;
     int lds_weights = 0;   // dynamic LDS of k_weights
     int lds_project = 0;   // dynamic LDS of k_project
+    int max_layers = 0;    // most layers of a plan of the schedule
     int tile = 32;
     // algorithmic bytes one launch of each stage moves (all frames of the job)
     double b_idwt_coarse = 0, b_idwt_tile[WM_MAXLEV + 1] = {};
@@ -423,6 +424,7 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     S->lds_sensor = lds_s;
     S->lds_weights = lds_w;
     S->lds_project = lds_p;
+    for (const JobSpec& j : jobs) S->max_layers = std::max(S->max_layers, j.plan->L);
     S->tile = tile;
     return WMCAO_OK;
 }
@@ -618,7 +620,7 @@ void run_adjoint(const JobArgs& a, const Sched& Sc, int c64, hipStream_t s) {
 template <class T, class S>
 void run_apply(const JobArgs& a, const Sched& Sc, int x_vec, int y_vec, int c64, hipStream_t s) {
     run_idwt<T, S>(a, Sc, x_vec, V_PHI, c64, s);
-    timed(WMCAO_K_PROJECT, Sc.b_project, s, [&] { launch_project<T, S>(a, Sc.proj, Sc.n_proj, V_PHI, 1, Sc.lds_project, s); });
+    timed(WMCAO_K_PROJECT, Sc.b_project, s, [&] { launch_project<T, S>(a, Sc.proj, Sc.n_proj, V_PHI, 1, Sc.lds_project, Sc.max_layers, s); });
     timed(WMCAO_K_WEIGHTS, Sc.b_sensor[0], s,
           [&] { launch_weights<T, S>(a, Sc.wgt, Sc.n_wgt, V_NODE, Sc.lds_weights, s); });
     run_adjoint<T, S>(a, Sc, c64, s);
@@ -1581,7 +1583,7 @@ static int simple_call(wmcao_plan_t p, const void* in, void* out, int batch, voi
                 if (!same)
                     launch_cast<T, Sv>(static_cast<const T*>(in), static_cast<Sv*>(p->vphi),
                                        p->n * batch, s);
-                launch_project<T, Sv>(a, S->proj, S->n_proj, same ? V_IN : V_PHI, 0, S->lds_project, s);
+                launch_project<T, Sv>(a, S->proj, S->n_proj, same ? V_IN : V_PHI, 0, S->lds_project, S->max_layers, s);
                 launch_sensor<T, Sv>(a, S->sensor, S->n_sensor, SM_FWD, V_U, V_OUT, S->lds_sensor, s);
                 break;
             case 3:   // rhs
