@@ -1842,6 +1842,7 @@ int wmcao_serve_launch(wmcao_plan_t plan, void* stage_slopes, void* stage_coeffs
                        const int* out_rows, void* const* out_ptrs, int n_iter, void* hip_stream) {
     if (!plan || !stage_slopes || !stage_coeffs || !slopes || !warm || (n_out > 0 && (!out_rows || !out_ptrs)))
         return fail(WMCAO_ERR_INVALID_ARG, "NULL argument");
+    if (!hip_stream) return fail(WMCAO_ERR_INVALID_ARG, "a served launch needs a non-default stream");
     if (count < 1 || count > plan->max_batch || 2 * count > SERVE_ROWS)
         return fail(WMCAO_ERR_INVALID_ARG, "count must be 1 .. min(max_batch, " +
                                                std::to_string(SERVE_ROWS / 2) + ")");
