@@ -330,16 +330,18 @@ def _synthetic_slopes(cfg, plan, frames, seeds=None, sig=None):
     return torch.stack(out), sig
 
 
-def batched_small(n_frames=128, n_iter=10, reps=20):
+def batched_small(n_frames=128, n_iter=10, reps=20, tuned=True):
     """C3: independent 8 m frames (own seeded screens and noise) in one FP32
-    batched solve replayed as a HIP graph."""
+    batched solve replayed as a HIP graph, with the work shapes the
+    autotuner picks for this batch."""
     import torch
-    from paper_1302_3734_amd import Plan
+    from paper_1302_3734_amd import Plan, autotune
     cfg = WL.config_c1()
     fwd = Plan(cfg, [1.0] * len(cfg["wfs"]), dtype="f64", max_batch=1)
     sl, sig = _synthetic_slopes(cfg, fwd, range(n_frames))
     fwd.close()
-    plan = Plan(cfg, sig, dtype="f32", max_batch=n_frames)
+    shapes = autotune.tune(cfg, sig, "f32", n_frames, n_iter) if tuned else dict(autotune.DEFAULTS)
+    plan = Plan(cfg, sig, dtype="f32", max_batch=n_frames, **shapes)
     s32 = sl.float().contiguous()
     x = torch.zeros(n_frames, plan.n, dtype=torch.float32, device="cuda")
     st = torch.cuda.Stream()
@@ -360,7 +362,8 @@ def batched_small(n_frames=128, n_iter=10, reps=20):
     ms = statistics.median(ts)
     return {"workload": "8 m, 3 NGS 16x16, 3 layers 64 px, db3 4 levels, 10 its from zero",
             "frames_per_launch": n_frames, "ms_per_launch": round(ms, 4),
-            "frames_per_s": round(n_frames / ms * 1e3, 1), "mode": "FP32, hipGraph replay"}
+            "frames_per_s": round(n_frames / ms * 1e3, 1), "mode": "FP32, hipGraph replay",
+            "work_shapes": shapes}
 
 
 def mixed_batch(n_frames=64, n_iter=10, reps=10):
@@ -843,7 +846,7 @@ def main():
               f"{r128['frames_per_s']:.0f} frames/s; stage fracs "
               f"{ {k: v['frac'] for k, v in r128['stages'].items()} }", flush=True)
     if "c3" in extras:
-        result["c3_batched"] = batched_small()
+        result["c3_batched"] = batched_small(tuned=not args.no_tune)
         print(f"[bench] c3 {result['c3_batched']}", flush=True)
     if "c4" in extras:
         result["c4_mixed"] = mixed_batch()
