@@ -140,7 +140,13 @@ def test_c2_warm_10_iterations(dt, kw):
     plan.close()
 
 
-def test_c3_batched_fp32_every_frame_and_batch_invariance():
+# the work shapes the autotuner picks for the 128-frame C1 batch on MI355X
+# (the C3 leg of the bench runs with them)
+C3_TUNED = {"lds_budget": 2048, "proj_rows": 16}
+
+
+@pytest.mark.parametrize("shapes", [{}, C3_TUNED], ids=["default-shapes", "tuned-shapes"])
+def test_c3_batched_fp32_every_frame_and_batch_invariance(shapes):
     """128 independent C1 frames (own seeded screens and noise) in one batched
     FP32 solve of 10 iterations captured as a HIP graph: every frame against
     the FP64 oracle, and sampled frames bitwise equal to their solo solves."""
@@ -153,8 +159,8 @@ def test_c3_batched_fp32_every_frame_and_batch_invariance():
     say("[c3] slopes")
     slopes = np.stack(oracle_pool_map(oracle_jobs.slopes, [("C1", sig, f, None) for f in range(B)]))
     s32 = to_dev(slopes, torch.float32)
-    plan = Plan(cfg, sig, dtype="f32", max_batch=B)
-    say("[c3] batched solve (graph)")
+    plan = Plan(cfg, sig, dtype="f32", max_batch=B, **shapes)
+    say(f"[c3] batched solve (graph), shapes {shapes}")
     out = torch.zeros(B, plan.n, dtype=torch.float32, device="cuda")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
