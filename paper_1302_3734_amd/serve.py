@@ -41,6 +41,9 @@ from . import _abi
 from .plan import Plan, solve_multi
 
 
+GRAPH_CACHE = 64   # captures the library keeps (wmcao_solve_multi_graph)
+
+
 class _Stream:
     def __init__(self, name, cfg_name, n, dtype, lanes):
         self.name = name
@@ -84,9 +87,9 @@ class Server:
     completions are found, "block" (a thread per lane waits on its oldest
     launch's event without holding the interpreter lock) or "poll" (one thread
     queries every lane's oldest event in turn, never while a launch may be
-    capturing a graph: used whenever a lane packs two configurations, whose
-    launches can outnumber the library's graph cache and so capture while
-    frames are in flight).  hbm_budget: bytes that frames in flight may
+    capturing a graph: used whenever a lane packs two configurations or the
+    lanes' launches outnumber the library's 64 kept captures, since a launch
+    may then capture while frames are in flight).  hbm_budget: bytes that frames in flight may
     reserve (default: half of the free device memory at start).  depth: launches
     a lane may hold in flight.  max_frames: frames of one telescope stream in
     one launch.  keep_inputs: keep each frame's warm start (for
@@ -131,11 +134,12 @@ class Server:
             self.cfg_lanes = {c: [i % n_lanes] for i, c in enumerate(names)}
         self.lanes = [torch.cuda.Stream() for _ in range(n_lanes)]
         self.lane_cfgs = [[c for c in names if i in self.cfg_lanes[c]] for i in range(n_lanes)]
-        # one plan per configuration (its launches are ordered on its lane),
-        # batch = the telescope streams of that configuration.  The lanes are
-        # the concurrency: plans that also split large batches onto a second
-        # stream of their own made served frames slower (p50 1.2 to 3.0 ms at
-        # 2000 frames/s), so the plans here use one stream each.
+        # a plan per configuration and lane (its launches are ordered on that
+        # lane), batch = the telescope streams of the configuration times
+        # max_frames.  The lanes are the concurrency: plans that also split
+        # large batches onto a second stream of their own made served frames
+        # slower (p50 1.2 to 3.0 ms at 2000 frames/s), so the plans here use
+        # one stream each.
         shapes = {c: {"tile": tile} for c in names}
         if tuned:
             from . import autotune
@@ -207,8 +211,11 @@ class Server:
         self.lane_launches = [0] * n_lanes
         self.frames_in_launch = []
         self.worker = threading.Thread(target=self._loop, daemon=True)
-        # every graph of a lane that serves one configuration is captured above
-        self.wait = wait if (not graphs or all(len(cs) == 1 for cs in self.lane_cfgs)) else "poll"
+        # blocking waits need every graph captured above and kept: lanes of one
+        # configuration each, and no more captures than the library keeps (64)
+        n_graphs = sum(count[c] for c, _ in self.plans)
+        kept = n_graphs <= GRAPH_CACHE and all(len(cs) == 1 for cs in self.lane_cfgs)
+        self.wait = wait if (not graphs or kept) else "poll"
         if self.wait == "block":
             self.completers = [threading.Thread(target=self._complete_lane, args=(lane,), daemon=True)
                                for lane in range(n_lanes)]
