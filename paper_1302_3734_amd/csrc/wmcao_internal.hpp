@@ -138,7 +138,7 @@ struct Item {
 
 enum SrcMode : int { SRC_LL = 0, SRC_PIX = 1, SRC_PT = 2 };
 enum EpiMode : int { EPI_NONE = 0, EPI_APPLY = 1 };
-enum SensorMode : int { SM_APPLY = 0, SM_RHS = 1, SM_FWD = 2 };
+enum SensorMode : int { SM_APPLY = 0, SM_RHS = 1, SM_FWD = 2, SM_PAPPLY = 3 };
 
 // ---- launchers (defined in wmcao_kernels.hip) --------------------------------
 // T: storage of the PCG vectors and of the caller's slopes; S: storage of the
@@ -201,6 +201,7 @@ constexpr int VEC_CHUNK = 2048;   // default elements per work item of the vecto
 constexpr int PROJ_ROWS = 8;      // default node rows per projection work item (4, 8 or 16)
 constexpr int PROJ_ROWS_MIN = 4;  // fewest node rows per projection work item
 constexpr int WGT_ROWS_MAX = 8;   // most node rows per weighting work item
+constexpr int SENSOR_FUSE_NN = 40;   // sensors of at most this many nodes per side project in k_sensor
 
 // Dynamic LDS of k_weights for a sensor of nn nodes and ns subapertures per
 // side: the band's node rows with one halo row on each side and the weighted

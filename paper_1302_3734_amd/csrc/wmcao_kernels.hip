@@ -1256,9 +1256,37 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
 }
 
 // ----------------------------------------------------------- one sensor ----
+// u of one sensor at every node (Sec. 2.1): the sum over layers of the
+// bilinear samples of the layer pixels (in_vec), with the stencils and the
+// order of operations of k_project, into U (FP64, nn x nn).
+template <class S>
+__device__ void project_sensor(const JobPlan& J, const PlanDev& P, int m, int frame, int in_vec,
+                               int nn, Acc* U) {
+    const S* pix = vptr<S>(J, in_vec, frame);
+    for (int e = threadIdx.x; e < nn * nn; e += blockDim.x) {
+        const int r = e / nn, c = e % nn;
+        Acc acc = 0;
+        for (int l = 0; l < P.L; ++l) {
+            const int N = P.layer[l].N;
+            int i0, j0;
+            Acc t, sw;
+            node_stencil(P.pa[m][l], P.pb[0][m][l], r, N, i0, t);
+            node_stencil(P.pa[m][l], P.pb[1][m][l], c, N, j0, sw);
+            const S* q = pix + P.layer[l].coff + static_cast<int64_t>(i0) * N + j0;
+            const Acc a0 = static_cast<Acc>(q[0]), a1 = static_cast<Acc>(q[1]);
+            const Acc b0 = static_cast<Acc>(q[N]), b1 = static_cast<Acc>(q[N + 1]);
+            const Acc x = fma(sw, a1 - a0, a0), y = fma(sw, b1 - b0, b0);
+            acc += fma(t, y - x, x);
+        }
+        U[e] = acc;
+    }
+}
+
 // SM_APPLY: node field u (from k_project) -> Fried slopes (aggregated for a
 //           low-order sensor) -> C^-1 with (I - T) for tip/tilt-removed
 //           sensors -> Gamma^T -> node field v.
+// SM_PAPPLY: the same, with u formed here from the layer pixels (in_vec):
+//           the projection and the weighting of a small sensor in one launch.
 // SM_RHS:   input slopes -> C^-1 (and (I - T)) -> Gamma^T -> v.
 // SM_FWD:   node field u -> raw slopes to the output.
 // One block of 1024 threads per (frame, sensor); the node field and the
@@ -1283,7 +1311,10 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
 
     if (w.kind == 1) {
         // phase at the pupil nodes: measurement q is node act[q], weight a_q
-        if (mode != SM_RHS) {
+        if (mode == SM_PAPPLY) {
+            project_sensor<SO>(J, P, m, it.frame, in_vec, nn, U);
+            __syncthreads();
+        } else if (mode != SM_RHS) {
             const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
             for (int e = tid; e < nn * nn; e += bd) U[e] = ug[e];
             __syncthreads();
@@ -1318,8 +1349,12 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
     }
 
     if (mode != SM_RHS) {
-        const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
-        for (int e = tid; e < nn * nn; e += bd) U[e] = ug[e];
+        if (mode == SM_PAPPLY) {
+            project_sensor<SO>(J, P, m, it.frame, in_vec, nn, U);
+        } else {
+            const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
+            for (int e = tid; e < nn * nn; e += bd) U[e] = ug[e];
+        }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < QM; ++r) {

@@ -64,6 +64,10 @@ struct Sched {
     int n_proj = 0;
     const Item* wgt = nullptr;          // noise-weighting items (bands of wgt_rows node rows)
     int n_wgt = 0;
+    const Item* proj_ap = nullptr;      // projection items of an operator apply (banded plans)
+    int n_proj_ap = 0;
+    const Item* papply = nullptr;       // one item per small sensor: projection and weighting
+    int n_papply = 0;
     const Item* adj = nullptr;
     int n_adj = 0;
     int lds_adj[2] = {};
@@ -276,12 +280,16 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // layer's tile partials to its own and writes the layer total after them
 // (the consumer sums L totals); the vector passes use one slot per chunk.
 int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
-    std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj, wgt;
+    std::vector<Item> coarse, coarse_syn, sensor, vec, proj, adj, wgt, proj_ap, papply;
     int lds_lvl[2][WM_MAXLEV + 1] = {};
     std::vector<Item> tiled[WM_MAXLEV + 1];
     int maxk0 = 0, lds_i[2] = {}, lds_f[2] = {}, lds_s = 0, lds_a[2] = {}, lds_w = 0, lds_p = 0, taps_a = 2;
     for (int jp = 0; jp < static_cast<int>(jobs.size()); ++jp) {
         const wmcao_plan_s* P = jobs[jp].plan;
+        // a plan whose sensors are all small projects and weights them in one
+        // block per sensor (k_sensor); the others in bands (k_project, k_weights)
+        bool fused = true;
+        for (int m = 0; m < P->W; ++m) fused = fused && P->host.wfs[m].nn <= SENSOR_FUSE_NN;
         for (int f = jobs[jp].first; f < jobs[jp].first + jobs[jp].count; ++f) {
             // <p, Ap> partials: one per analysis tile, numbered layer by layer,
             // then one total per layer (written by the layer's whole-band block)
@@ -322,8 +330,13 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
                 sensor.push_back(Item{jp, f, m, 0, 0, 0, 0, 0});
                 const int nb = ceil_div(P->host.wfs[m].nn, P->host.proj_rows);
                 for (int b = 0; b < nb; ++b) proj.push_back(Item{jp, f, m, b, 0, 0, 0, 0});
-                const int nbw = ceil_div(P->host.wfs[m].nn, P->host.wgt_rows);
-                for (int b = 0; b < nbw; ++b) wgt.push_back(Item{jp, f, m, b, 0, 0, 0, 0});
+                if (fused) {
+                    papply.push_back(Item{jp, f, m, 0, 0, 0, 0, 0});
+                } else {
+                    for (int b = 0; b < nb; ++b) proj_ap.push_back(Item{jp, f, m, b, 0, 0, 0, 0});
+                    const int nbw = ceil_div(P->host.wfs[m].nn, P->host.wgt_rows);
+                    for (int b = 0; b < nbw; ++b) wgt.push_back(Item{jp, f, m, b, 0, 0, 0, 0});
+                }
                 const int nn = P->host.wfs[m].nn;
                 lds_s = std::max(lds_s, static_cast<int>(nn * nn * sizeof(double)));
                 lds_w = std::max(lds_w, weights_lds_bytes(nn, P->host.wfs[m].n_sub, P->host.wgt_rows));
@@ -388,6 +401,8 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     add(adj);
     for (int k = 1; k <= WM_MAXLEV; ++k) add(tiled[k]);
     add(wgt);
+    add(proj_ap);
+    add(papply);
     S->buf = std::make_shared<DevBuf>();
     const size_t bytes = std::max<size_t>(all.size(), 1) * sizeof(Item);
     hipError_t e = hipMalloc(&S->buf->p, bytes);
@@ -408,6 +423,10 @@ int build_sched(const std::vector<JobSpec>& jobs, int tile, Sched* S) {
     S->n_adj = static_cast<int>(adj.size());
     S->wgt = base + offs[6 + WM_MAXLEV];
     S->n_wgt = static_cast<int>(wgt.size());
+    S->proj_ap = base + offs[7 + WM_MAXLEV];
+    S->n_proj_ap = static_cast<int>(proj_ap.size());
+    S->papply = base + offs[8 + WM_MAXLEV];
+    S->n_papply = static_cast<int>(papply.size());
     for (int c = 0; c < 2; ++c) S->lds_adj[c] = lds_a[c];
     S->adj_taps = taps_a;
     for (int c = 0; c < 2; ++c)
@@ -620,9 +639,17 @@ void run_adjoint(const JobArgs& a, const Sched& Sc, int c64, hipStream_t s) {
 template <class T, class S>
 void run_apply(const JobArgs& a, const Sched& Sc, int x_vec, int y_vec, int c64, hipStream_t s) {
     run_idwt<T, S>(a, Sc, x_vec, V_PHI, c64, s);
-    timed(WMCAO_K_PROJECT, Sc.b_project, s, [&] { launch_project<T, S>(a, Sc.proj, Sc.n_proj, V_PHI, 1, Sc.lds_project, Sc.max_layers, s); });
-    timed(WMCAO_K_WEIGHTS, Sc.b_sensor[0], s,
-          [&] { launch_weights<T, S>(a, Sc.wgt, Sc.n_wgt, V_NODE, Sc.lds_weights, s); });
+    if (Sc.n_proj_ap > 0) {
+        timed(WMCAO_K_PROJECT, Sc.b_project, s, [&] {
+            launch_project<T, S>(a, Sc.proj_ap, Sc.n_proj_ap, V_PHI, 1, Sc.lds_project, Sc.max_layers, s);
+        });
+        timed(WMCAO_K_WEIGHTS, Sc.b_sensor[0], s,
+              [&] { launch_weights<T, S>(a, Sc.wgt, Sc.n_wgt, V_NODE, Sc.lds_weights, s); });
+    }
+    if (Sc.n_papply > 0)
+        timed(WMCAO_K_SENSOR, Sc.b_sensor[0], s, [&] {
+            launch_sensor<T, S>(a, Sc.papply, Sc.n_papply, SM_PAPPLY, V_PHI, V_NODE, Sc.lds_sensor, s);
+        });
     run_adjoint<T, S>(a, Sc, c64, s);
     run_fdwt<T, S>(a, Sc, SRC_PT, V_FP, y_vec, EPI_APPLY, x_vec, c64, s);
 }
@@ -1718,6 +1745,8 @@ int wmcao_solve_noalloc(wmcao_plan_t plan, const void* slopes, void* coeffs, int
     v.n_sensor = scale(full->n_sensor);
     v.n_proj = scale(full->n_proj);
     v.n_wgt = scale(full->n_wgt);
+    v.n_proj_ap = scale(full->n_proj_ap);
+    v.n_papply = scale(full->n_papply);
     v.n_adj = scale(full->n_adj);
     v.n_vec = scale(full->n_vec);
     v.frames = batch;
