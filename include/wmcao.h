@@ -133,7 +133,9 @@ typedef struct {
  *   tile                  tile edge of the tiled wavelet kernels: 16, 32 or 64;
  *                         0 = library default
  *   lds_budget            bytes of LDS a whole-band wavelet kernel may use
- *                         (0 = library default)
+ *                         (0 = library default): the levels whose low-pass
+ *                         band exceeds it run as tiled launches, for all
+ *                         layers as many as the largest layer needs
  *   streams               1: a solve runs on the caller's stream only; 2: a
  *                         solve (single-plan, or packed when every plan allows
  *                         it) whose half batch holds at least 2^20 coefficients
