@@ -976,6 +976,7 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double cval[2 * WM_MAXCELL], cwx[WM_MAXCELL], cwy[WM_MAXCELL];
     __shared__ double srec[((WM_NSUB_MAX + 1 + PROJ_ROWS_MIN - 1) / PROJ_ROWS_MIN) * SP_K];
+    __shared__ double tsum[SP_K];
     const Item it = items[xcd_item()];
     const JobPlan& J = args.jp[it.jp];
     const PlanDev& P = *J.P;
@@ -1021,13 +1022,18 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
             srec[e] = rec[(e / K) * SP_K + e % K];
     }
     __syncthreads();
+    // lane k of the first wave sums record component k over the bands, in
+    // band order (the same order in every block of the sensor)
+    if (threadIdx.x < K) {
+        double acc = 0.0;
+        for (int b = 0; b < nb; ++b) acc += srec[b * K + threadIdx.x];
+        tsum[threadIdx.x] = acc;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const double* rec = srec;
         const double* blk = w.blocks;
         if (!w.agg) {
-            double t[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int b = 0; b < nb; ++b)
-                for (int k = 0; k < 4; ++k) t[k] += rec[b * K + k];
+            const double t[4] = {tsum[0], tsum[1], tsum[2], tsum[3]};
             double mx = 0.0, my = 0.0, nx = 0.0, ny = 0.0;
             if (w.remove_tt) {
                 const double S = w.S_fine;
@@ -1044,13 +1050,8 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
             const int S = w.S;
             double mx = 0.0, my = 0.0;
             for (int c = 0; c < S; ++c) {
-                double px = 0.0, py = 0.0;
-                for (int b = 0; b < nb; ++b) {
-                    px += rec[b * K + 2 * c];
-                    py += rec[b * K + 2 * c + 1];
-                }
-                cval[2 * c] = px / w.cell_count[c];
-                cval[2 * c + 1] = py / w.cell_count[c];
+                cval[2 * c] = tsum[2 * c] / w.cell_count[c];
+                cval[2 * c + 1] = tsum[2 * c + 1] / w.cell_count[c];
                 mx += cval[2 * c];
                 my += cval[2 * c + 1];
             }
