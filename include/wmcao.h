@@ -167,7 +167,8 @@ typedef struct {
  *                         small differences of the summed P^T image, the other
  *                         two stages run in FP32).
  *   proj_rows             sensor node rows per work item of the projection and
- *                         the noise weighting: 4, 8 or 16 (0 = 8)
+ *                         the noise weighting: 4 .. 48 (0 = 8; the weighting
+ *                         takes at most 8)
  *   vec_chunk             vector elements per work item of the PCG updates:
  *                         1024, 2048, 4096 or 8192 (0 = 2048)
  *   adj_lds               LDS bytes one adjoint-projection work item may use

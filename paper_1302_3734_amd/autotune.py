@@ -31,7 +31,7 @@ from .plan import Plan
 SPACE = {
     "tile": [32, 16, 64],
     "lds_budget": [8 * 1024, 2 * 1024, 32 * 1024],
-    "proj_rows": [8, 4, 16],
+    "proj_rows": [8, 4, 16, 32, 48],
     "adj_lds": [32 * 1024, 16 * 1024, 64 * 1024],
     "vec_chunk": [2048, 1024, 4096],
 }

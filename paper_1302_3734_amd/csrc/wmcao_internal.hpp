@@ -198,8 +198,9 @@ constexpr size_t NOALLOC_BYTES = size_t(32) << 20;   // scratch of the allocatio
 constexpr int FUSE_LDS = 32 * 1024;   // largest low-pass block a synthesis tile rebuilds
 constexpr int TILE_NT = 256;          // threads of a wavelet tile block
 constexpr int VEC_CHUNK = 2048;   // default elements per work item of the vector kernels
-constexpr int PROJ_ROWS = 8;      // default node rows per projection work item (4, 8 or 16)
+constexpr int PROJ_ROWS = 8;      // default node rows per projection work item
 constexpr int PROJ_ROWS_MIN = 4;  // fewest node rows per projection work item
+constexpr int PROJ_ROWS_MAX = 48; // most node rows per projection work item
 constexpr int WGT_ROWS_MAX = 8;   // most node rows per weighting work item
 constexpr int SENSOR_FUSE_NN = 40;   // sensors of at most this many nodes per side project in k_sensor
 

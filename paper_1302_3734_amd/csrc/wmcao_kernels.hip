@@ -46,6 +46,19 @@ __device__ __forceinline__ T* vptr(const JobPlan& J, int v, int frame) {
     return reinterpret_cast<T*>(J.vec[v]) + static_cast<int64_t>(frame) * J.stride[v];
 }
 
+// A device array through a global-memory pointer.  Arrays reached through two
+// or more loaded pointers (plan tables, the Jacobi diagonal) are too deep for
+// the compiler to infer their address space; as flat loads they would also
+// count against the LDS counter, so that every wait for an LDS value would
+// wait for them too.
+template <class T>
+using gptr = const T __attribute__((address_space(1)))*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+    return (gptr<T>)p;
+}
+
 // Low-pass scratch of a frame: its region holds ll_size 8-byte elements
 // whatever type a stage keeps there, so that frames never overlap when stages
 // of different arithmetic run side by side.
@@ -913,13 +926,13 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
         Acc p0 = 0, p1 = 0, p2 = 0, p3 = 0;
         for (int li = gs; li < nsub_rows; li += GS) {
             const int j = js;
-            const int q = w.maskmap[(r0 + li) * ns + j];
+            const int q = as_global(w.maskmap)[(r0 + li) * ns + j];
             if (q < 0) continue;
             const Acc u00 = su[li * nn + j], u10 = su[(li + 1) * nn + j];
             const Acc u01 = su[li * nn + j + 1], u11 = su[(li + 1) * nn + j + 1];
             const Acc sx = 0.5 * ((u10 - u00) + (u11 - u01));
             const Acc sy = 0.5 * ((u01 - u00) + (u11 - u10));
-            const double* bq = w.blocks + 3 * q;
+            const gptr<double> bq = as_global(w.blocks) + 3 * q;
             p0 += sx;
             p1 += sy;
             p2 += bq[0] * sx + bq[1] * sy;
@@ -936,7 +949,7 @@ k_project(const JobArgs args, const Item* __restrict__ items, int in_vec, int su
             double pv[4] = {0.0, 0.0, 0.0, 0.0};
             for (int li = gs; li < nsub_rows; li += GS) {
                 const int j = js;
-                const int k = w.maskmap[(r0 + li) * ns + j] - c;
+                const int k = as_global(w.maskmap)[(r0 + li) * ns + j] - c;
                 if (k != 0 && k != 1) continue;
                 const Acc u00 = su[li * nn + j], u10 = su[(li + 1) * nn + j];
                 const Acc u01 = su[li * nn + j + 1], u11 = su[(li + 1) * nn + j + 1];
@@ -989,13 +1002,14 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     double* su = reinterpret_cast<double*>(smem_raw);
     double* swx = su + (PR + 2) * nn;
     double* swy = swx + (PR + 1) * ns;
-    const double* ug = vptr<double>(J, V_U, it.frame) + w.node_off;
+    const gptr<double> ug = as_global(vptr<double>(J, V_U, it.frame) + w.node_off);
     SO* vout = vptr<SO>(J, out_vec, it.frame) + w.node_off;
+    const gptr<int> maskmap = as_global(w.maskmap);
     if (w.kind == 1) {
         for (int e = threadIdx.x; e < rows * nn; e += blockDim.x) {
             const int node = r0 * nn + e;
-            const int q = w.maskmap[node];
-            vout[node] = static_cast<SO>(q >= 0 ? w.blocks[3 * q] * ug[node] : 0.0);
+            const int q = maskmap[node];
+            vout[node] = static_cast<SO>(q >= 0 ? as_global(w.blocks)[3 * q] * ug[node] : 0.0);
         }
         return;
     }
@@ -1010,14 +1024,14 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
 #pragma unroll
     for (int k = 0; k < WQ; ++k) {
         const int e = min(static_cast<int>(threadIdx.x) + k * static_cast<int>(blockDim.x), nsl - 1);
-        qpre[k] = w.maskmap[(ia + e / ns) * ns + e % ns];
+        qpre[k] = maskmap[(ia + e / ns) * ns + e % ns];
     }
     for (int e = threadIdx.x; e < (ub - ua + 1) * nn; e += blockDim.x) su[e] = ug[ua * nn + e];
     // the band records of this sensor (one per projection band), gathered in parallel
     const int nb = (nn + P.proj_rows - 1) / P.proj_rows;
     const int K = w.agg ? 2 * w.S : 4;
     {
-        const double* rec = vptr<double>(J, V_SPART, it.frame) + w.sp_off;
+        const gptr<double> rec = as_global(vptr<double>(J, V_SPART, it.frame) + w.sp_off);
         for (int e = threadIdx.x; e < nb * K; e += blockDim.x)
             srec[e] = rec[(e / K) * SP_K + e % K];
     }
@@ -1031,7 +1045,8 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const double* blk = w.blocks;
+        const gptr<double> blk = as_global(w.blocks);
+        const auto cell_count = as_global(w.cell_count);
         if (!w.agg) {
             const double t[4] = {tsum[0], tsum[1], tsum[2], tsum[3]};
             double mx = 0.0, my = 0.0, nx = 0.0, ny = 0.0;
@@ -1050,8 +1065,8 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
             const int S = w.S;
             double mx = 0.0, my = 0.0;
             for (int c = 0; c < S; ++c) {
-                cval[2 * c] = tsum[2 * c] / w.cell_count[c];
-                cval[2 * c + 1] = tsum[2 * c + 1] / w.cell_count[c];
+                cval[2 * c] = tsum[2 * c] / cell_count[c];
+                cval[2 * c + 1] = tsum[2 * c + 1] / cell_count[c];
                 mx += cval[2 * c];
                 my += cval[2 * c + 1];
             }
@@ -1076,8 +1091,8 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
                 nx = ny = 0.0;
             }
             for (int c = 0; c < S; ++c) {
-                cval[2 * c] = (cwx[c] - nx) / w.cell_count[c];
-                cval[2 * c + 1] = (cwy[c] - ny) / w.cell_count[c];
+                cval[2 * c] = (cwx[c] - nx) / cell_count[c];
+                cval[2 * c + 1] = (cwy[c] - ny) / cell_count[c];
             }
         }
     }
@@ -1090,7 +1105,7 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
         int q = qpre[0];
 #pragma unroll
         for (int k = 1; k < WQ; ++k) q = kq == k ? qpre[k] : q;
-        if (kq >= WQ) q = w.maskmap[i * ns + j];
+        if (kq >= WQ) q = maskmap[i * ns + j];
         Acc wx = 0, wy = 0;
         if (q >= 0) {
             if (w.agg) {
@@ -1102,7 +1117,7 @@ k_weights(const JobArgs args, const Item* __restrict__ items, int out_vec) {
                 const Acc u01 = su[lu * nn + j + 1], u11 = su[(lu + 1) * nn + j + 1];
                 const Acc sx = 0.5 * ((u10 - u00) + (u11 - u01)) - cval[0];
                 const Acc sy = 0.5 * ((u01 - u00) + (u11 - u10)) - cval[1];
-                const double* bq = w.blocks + 3 * q;
+                const gptr<double> bq = as_global(w.blocks) + 3 * q;
                 wx = bq[0] * sx + bq[1] * sy - cval[2];
                 wy = bq[1] * sx + bq[2] * sy - cval[3];
             }
@@ -1161,8 +1176,8 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
     const int x0 = P.fp_x0[m][l], y0 = P.fp_y0[m][l];
     const int Hf = P.fp_h[m][l], Wf = P.fp_w[m][l], br = P.fp_br[m][l];
     const int r0 = it.slot * br, BR = min(Hf, r0 + br) - r0;
-    const int* rt = P.fp_rc + 2 * P.fp_tab[m][l];
-    const int* ct = rt + 2 * Hf;
+    const gptr<int> rt = as_global(P.fp_rc) + 2 * P.fp_tab[m][l];
+    const gptr<int> ct = rt + 2 * Hf;
     const int alo = ct[2 * Wf + 2 * it.slot], ahi = ct[2 * Wf + 2 * it.slot + 1];
     S* out = vptr<S>(J, out_vec, it.frame) + P.fp_off[m][l] + r0 * Wf;
     if (ahi < alo) {
@@ -1584,6 +1599,53 @@ __device__ __forceinline__ void st4(T* p, int64_t i, int64_t n, const T* v) {
     }
 }
 
+template <bool VEC, class T>
+__device__ __forceinline__ void ld4(gptr<T> p, int64_t i, int64_t n, Acc* v) {
+    if constexpr (VEC) {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        typedef T v4 __attribute__((ext_vector_type(4)));
+        if constexpr (sizeof(T) == 4) {
+            const v4 q = *(const v4 __attribute__((address_space(1)))*)(p + i);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+            const v2 q0 = *(const v2 __attribute__((address_space(1)))*)(p + i);
+            const v2 q1 = *(const v2 __attribute__((address_space(1)))*)(p + i + 2);
+            v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (i + j < n) ? static_cast<Acc>(p[i + j]) : 0.0;
+    }
+}
+
+// z = J^-1 v with the Jacobi preconditioner (PRE), else v.  Under VEC every
+// element of a group exists, so the quotient is taken unconditionally and the
+// diagonal's four values are one load issued with the other operands' (behind
+// a run-time test of its own, the load of the first value sank into that
+// branch and waited for the other loads: two memory round trips per group).
+// Elements past n (scalar groups only) keep v.
+template <bool VEC, bool PRE>
+__device__ __forceinline__ Acc jacobi_z(Acc v, Acc d, bool exists) {
+    if constexpr (!PRE)
+        return v;
+    else if constexpr (VEC)
+        return v / d;
+    else
+        return exists ? v / d : v;
+}
+
+// Run a sweep lambda taking (VEC tag, PRE tag) with both flags as constants.
+template <class F>
+__device__ __forceinline__ void vec_dispatch(bool vec, bool pre, F&& sweep) {
+    if (vec) {
+        if (pre) sweep(std::true_type{}, std::true_type{});
+        else sweep(std::true_type{}, std::false_type{});
+    } else {
+        if (pre) sweep(std::false_type{}, std::true_type{});
+        else sweep(std::false_type{}, std::false_type{});
+    }
+}
+
 // r0 = b (cold: x = 0) or b - A x0 (warm, A x0 in V_Q); p0 = z0 = J^-1 r0;
 // partials of <r0, z0> and <r0, r0> into the parity-0 segments.
 template <class T>
@@ -1605,21 +1667,21 @@ k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
     const int64_t i0 = static_cast<int64_t>(it.b) * chunk;
     const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
     const bool pre_ = P.precond != 0;
-    auto sweep = [&](auto vec_tag) {
-        constexpr bool VEC = decltype(vec_tag)::value;
+    auto sweep = [&](auto vec_tag, auto pre_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value, PRE = decltype(pre_tag)::value;
         for (int k = 4 * threadIdx.x; k < chunk; k += 4 * blockDim.x) {
             const int64_t i = i0 + k;
             if (i >= n_) break;
-            Acc bv[4], qv[4], jv[4];
+            Acc bv[4], qv[4], jv[4] = {};
             T rs[4], ps[4], zero[4] = {0, 0, 0, 0};
             ld4<VEC>(b, i, n_, bv);
-            ld4<VEC>(jac, i, n_, jv);
+            if constexpr (PRE) ld4<VEC>(as_global(jac), i, n_, jv);
             if (warm) ld4<VEC>(q, i, n_, qv);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 rs[j] = static_cast<T>(warm ? bv[j] - qv[j] : bv[j]);
                 const Acc rv = rs[j];
-                const Acc z = (pre_ && i + j < n_) ? rv / jv[j] : rv;
+                const Acc z = jacobi_z<VEC, PRE>(rv, jv[j], i + j < n_);
                 ps[j] = static_cast<T>(z);
                 rz += rv * z;
                 rr += rv * rv;
@@ -1629,10 +1691,7 @@ k_init(const JobArgs args, const Item* __restrict__ items, int warm) {
             if (!warm) st4<VEC>(x, i, n_, zero);
         }
     };
-    if (vec)
-        sweep(std::true_type{});
-    else
-        sweep(std::false_type{});
+    vec_dispatch(vec, pre_, sweep);
     block_sum2_first(rz, rr, red);
     if (threadIdx.x == 0) {
         part_ptr(J, it.frame, PT_RZ0)[it.slot] = rz;
@@ -1695,31 +1754,28 @@ k_update_r(const JobArgs args, const Item* __restrict__ items, int iter, int fre
     const int64_t i0 = static_cast<int64_t>(it.b) * chunk;
     const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
     const bool pre_ = P.precond != 0;
-    auto sweep = [&](auto vec_tag) {
-        constexpr bool VEC = decltype(vec_tag)::value;
+    auto sweep = [&](auto vec_tag, auto pre_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value, PRE = decltype(pre_tag)::value;
         for (int k = 4 * threadIdx.x; k < chunk; k += 4 * blockDim.x) {
             const int64_t i = i0 + k;
             if (i >= n_) break;
-            Acc rv[4], qv[4], jv[4];
+            Acc rv[4], qv[4], jv[4] = {};
             T rs[4];
             ld4<VEC>(r, i, n_, rv);
             ld4<VEC>(q, i, n_, qv);
-            ld4<VEC>(jac, i, n_, jv);
+            if constexpr (PRE) ld4<VEC>(as_global(jac), i, n_, jv);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 rs[j] = static_cast<T>(rv[j] - a * qv[j]);
                 const Acc v = rs[j];
-                const Acc z = (pre_ && i + j < n_) ? v / jv[j] : v;
+                const Acc z = jacobi_z<VEC, PRE>(v, jv[j], i + j < n_);
                 rz += v * z;
                 rr += v * v;
             }
             st4<VEC>(r, i, n_, rs);
         }
     };
-    if (vec)
-        sweep(std::true_type{});
-    else
-        sweep(std::false_type{});
+    vec_dispatch(vec, pre_, sweep);
     block_sum2_first(rz, rr, red);
     if (threadIdx.x == 0) {
         part_ptr(J, it.frame, PT_RZ0 + ((iter + 1) & 1))[it.slot] = rz;
@@ -1766,31 +1822,28 @@ k_update_p(const JobArgs args, const Item* __restrict__ items, int iter) {
     const int64_t i0 = static_cast<int64_t>(it.b) * chunk;
     const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
     const bool pre_ = P.precond != 0;
-    auto sweep = [&](auto vec_tag) {
-        constexpr bool VEC = decltype(vec_tag)::value;
+    auto sweep = [&](auto vec_tag, auto pre_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value, PRE = decltype(pre_tag)::value;
         for (int k = 4 * threadIdx.x; k < chunk; k += 4 * blockDim.x) {
             const int64_t i = i0 + k;
             if (i >= n_) break;
-            Acc pv[4], xv[4], rv[4], jv[4];
+            Acc pv[4], xv[4], rv[4], jv[4] = {};
             T xs[4], ps[4];
             ld4<VEC>(p, i, n_, pv);
             ld4<VEC>(x, i, n_, xv);
             ld4<VEC>(r, i, n_, rv);
-            ld4<VEC>(jac, i, n_, jv);
+            if constexpr (PRE) ld4<VEC>(as_global(jac), i, n_, jv);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 xs[j] = static_cast<T>(xv[j] + a * pv[j]);
-                const Acc z = (pre_ && i + j < n_) ? rv[j] / jv[j] : rv[j];
+                const Acc z = jacobi_z<VEC, PRE>(rv[j], jv[j], i + j < n_);
                 ps[j] = static_cast<T>(z + beta * pv[j]);
             }
             st4<VEC>(x, i, n_, xs);
             st4<VEC>(p, i, n_, ps);
         }
     };
-    if (vec)
-        sweep(std::true_type{});
-    else
-        sweep(std::false_type{});
+    vec_dispatch(vec, pre_, sweep);
 }
 
 // Residual replacement: r = b - A x (A x in V_Q), fresh partials for rho_i.
@@ -1812,31 +1865,28 @@ k_replace_r(const JobArgs args, const Item* __restrict__ items, int iter) {
     const int64_t i0 = static_cast<int64_t>(it.b) * chunk;
     const int64_t n_ = P.n;            // plan fields read once: the stores below may alias them
     const bool pre_ = P.precond != 0;
-    auto sweep = [&](auto vec_tag) {
-        constexpr bool VEC = decltype(vec_tag)::value;
+    auto sweep = [&](auto vec_tag, auto pre_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value, PRE = decltype(pre_tag)::value;
         for (int k = 4 * threadIdx.x; k < chunk; k += 4 * blockDim.x) {
             const int64_t i = i0 + k;
             if (i >= n_) break;
-            Acc bv[4], qv[4], jv[4];
+            Acc bv[4], qv[4], jv[4] = {};
             T rs[4];
             ld4<VEC>(b, i, n_, bv);
             ld4<VEC>(q, i, n_, qv);
-            ld4<VEC>(jac, i, n_, jv);
+            if constexpr (PRE) ld4<VEC>(as_global(jac), i, n_, jv);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 rs[j] = static_cast<T>(bv[j] - qv[j]);
                 const Acc v = rs[j];
-                const Acc z = (pre_ && i + j < n_) ? v / jv[j] : v;
+                const Acc z = jacobi_z<VEC, PRE>(v, jv[j], i + j < n_);
                 rz += v * z;
                 rr += v * v;
             }
             st4<VEC>(r, i, n_, rs);
         }
     };
-    if (vec)
-        sweep(std::true_type{});
-    else
-        sweep(std::false_type{});
+    vec_dispatch(vec, pre_, sweep);
     block_sum2_first(rz, rr, red);
     if (threadIdx.x == 0) {
         part_ptr(J, it.frame, PT_RZ0 + (iter & 1))[it.slot] = rz;

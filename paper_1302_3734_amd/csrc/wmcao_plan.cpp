@@ -1021,8 +1021,9 @@ int wmcao_plan(const wmcao_pupil* pupil, const wmcao_layer* layers, int n_layers
         return fail(WMCAO_ERR_INVALID_ARG, "FP64 plans have FP64 operators");
     if (opts->op_fp64_stages < -1 || opts->op_fp64_stages > 7)
         return fail(WMCAO_ERR_INVALID_ARG, "op_fp64_stages must be -1 or a mask of 1, 2 and 4");
-    if (opts->proj_rows != 0 && opts->proj_rows != 4 && opts->proj_rows != 8 && opts->proj_rows != 16)
-        return fail(WMCAO_ERR_INVALID_ARG, "proj_rows must be 0, 4, 8 or 16");
+    if (opts->proj_rows != 0 && (opts->proj_rows < PROJ_ROWS_MIN || opts->proj_rows > PROJ_ROWS_MAX))
+        return fail(WMCAO_ERR_INVALID_ARG, "proj_rows must be 0 or " + std::to_string(PROJ_ROWS_MIN) +
+                                               " .. " + std::to_string(PROJ_ROWS_MAX));
     if (opts->vec_chunk != 0 && opts->vec_chunk != 1024 && opts->vec_chunk != 2048 &&
         opts->vec_chunk != 4096 && opts->vec_chunk != 8192)
         return fail(WMCAO_ERR_INVALID_ARG, "vec_chunk must be 0, 1024, 2048, 4096 or 8192");

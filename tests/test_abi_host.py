@@ -57,7 +57,8 @@ def _args(n=64, levels=4, order=3, n_sub=16, agg=0, dtype=0, tile=0, sigma=0.1, 
     ({"op_precision": 16}, -1),      # operators are FP32 or FP64
     ({"dtype": 1, "op_precision": 32}, -1),
     ({"op_fp64_stages": 9}, -1),     # a mask of 1, 2 and 4
-    ({"proj_rows": 6}, -1),
+    ({"proj_rows": 3}, -1),           # 4 .. 48 node rows
+    ({"proj_rows": 64}, -1),
     ({"vec_chunk": 3000}, -1),
     ({"adj_lds": 1024}, -1),
 ])

@@ -47,6 +47,9 @@ CASES = [
     ("c2-f32-rows16", WL.config_c2, "f32", {"proj_rows": 16, "adj_lds": 64 * 1024}),
     ("c2-f64-rows4", WL.config_c2, "f64", {"proj_rows": 4, "adj_lds": 16 * 1024, "vec_chunk": 4096}),
     ("max-f64-rows16", tiny_max_config, "f64", {"proj_rows": 16, "vec_chunk": 1024}),
+    ("c2-f32-rows32", WL.config_c2, "f32", {"proj_rows": 32, "adj_lds": 64 * 1024}),
+    ("c2-f64-rows48", WL.config_c2, "f64", {"proj_rows": 48}),
+    ("max-f64-rows48", tiny_max_config, "f64", {"proj_rows": 48}),
     # footprints at the layer edges, read through windows that wrap around them
     ("edge-tiled-f64", tiny_edge_config, "f64", {"tile": 16, "lds_budget": 512}),
     ("edge-tiled-f32-op32", tiny_edge_config, "f32", {"tile": 16, "lds_budget": 256, "op_precision": 32}),
