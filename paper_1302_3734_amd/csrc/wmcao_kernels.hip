@@ -444,6 +444,31 @@ __device__ void pt_gather_window(const PlanDev& P, const S* img, int l, int N, i
     }
 }
 
+// Copy the M0 x M0 top-left block of a band with row stride ld into LDS (row
+// stride M0), converting to C.  Eight elements per thread are loaded before
+// any is stored, so the loads go out together (one element per loop trip
+// waits for each load before the next); past the block's end a thread
+// reloads its own first element of the round (distinct addresses across the
+// wave, rather than every thread reading the last element).
+template <class C, class T>
+__device__ __forceinline__ void load_block(const T* src, int ld, int M0, C* dst) {
+    constexpr int R = 8;
+    const int n = M0 * M0, bd = blockDim.x;
+    for (int e0 = threadIdx.x; e0 < n; e0 += R * bd) {
+        T v[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int e = e0 + k * bd < n ? e0 + k * bd : e0;   // a valid element
+            v[k] = src[static_cast<int64_t>(e / M0) * ld + e % M0];
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int e = e0 + k * bd;
+            if (e < n) dst[e] = static_cast<C>(v[k]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ W^-1 ----
 // Levels J..k0+1 of the synthesis of one layer, with the whole M0 x M0
 // (M0 = N / 2^k0) low-pass block resident in LDS.  Coefficients in T; the
@@ -509,6 +534,19 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
     T rLH[WIT], rHL[WIT], rHH[WIT];
     C rLL[WIT];
     const bool fused = level == Ly.k0 && Ly.fuse;
+    // a fused tile's coarse block (the Mallat top-left H x H of the input),
+    // when it fits four elements per thread, is loaded before the window, so
+    // that both sets of loads are in flight together
+    constexpr int CR = 4;
+    const bool coarse_regs = fused && H * H <= CR * TILE_NT;
+    T cv[CR] = {};
+    if (coarse_regs) {
+#pragma unroll
+        for (int k = 0; k < CR; ++k) {
+            const int e = min(static_cast<int>(threadIdx.x) + k * TILE_NT, H * H - 1);
+            cv[k] = src[static_cast<int64_t>(e / H) * N + e % H];
+        }
+    }
 #pragma unroll
     for (int k = 0; k < WIT; ++k) {
         const int e = min(static_cast<int>(threadIdx.x) + k * TILE_NT, CW * CW - 1);
@@ -530,8 +568,15 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
         extern __shared__ __align__(16) unsigned char smem_raw[];
         C* Ac = reinterpret_cast<C*>(smem_raw);
         const int M0 = H;
-        for (int e = threadIdx.x; e < M0 * M0; e += blockDim.x)
-            Ac[e] = static_cast<C>(src[static_cast<int64_t>(e / M0) * N + (e % M0)]);
+        if (coarse_regs) {
+#pragma unroll
+            for (int k = 0; k < CR; ++k) {
+                const int e = static_cast<int>(threadIdx.x) + k * TILE_NT;
+                if (e < M0 * M0) Ac[e] = static_cast<C>(cv[k]);
+            }
+        } else {
+            load_block(src, N, M0, Ac);
+        }
         __syncthreads();
         for (int lev = P.levels; lev > level; --lev) {
             const int Mc = N >> (lev - 1);
@@ -602,6 +647,28 @@ k_idwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int i
     }
 }
 
+// Element offsets of a thread's share of a PW x PW window at (px0, py0) of
+// an M x M band stored with row stride ld, wrapped periodically (the origin
+// lies in the band, so offsets are non-negative; a window wider than the band
+// wraps more than once).  All offsets are formed before any load is issued,
+// so that the loads go out back to back rather than one per wrap loop.
+template <int PW, int WIN_IT>
+__device__ __forceinline__ void window_offsets(int px0, int py0, int M, int ld, int64_t* off) {
+#pragma unroll
+    for (int k = 0; k < WIN_IT; ++k) {
+        const int e = min(static_cast<int>(threadIdx.x) + k * TILE_NT, PW * PW - 1);
+        int gx = px0 + e / PW, gy = py0 + e % PW;
+        if (M >= PW) {   // one wrap at most (uniform branch)
+            gx -= gx >= M ? M : 0;
+            gy -= gy >= M ? M : 0;
+        } else {
+            gx %= M;
+            gy %= M;
+        }
+        off[k] = static_cast<int64_t>(gx) * ld + gy;
+    }
+}
+
 // --------------------------------------------------------- W (+ P^T, D) ----
 // One analysis level k <= k0 over a (TS/2)^2 tile of each band.  The input
 // window of (TS+4)^2 values (S in HBM) is LL_{k-1} (scratch) or, at k = 1, the layer
@@ -651,33 +718,37 @@ k_fdwt_tile(const JobArgs args, const Item* __restrict__ items, int level, int s
     if (level == 1 && src == SRC_PT) {
         // rows per thread of the PW x PW window, at most 8 per register chunk
         constexpr int RPT = (PW + TILE_NT / PW - 1) / (TILE_NT / PW);
+        // the tile's sensor mask is one value for the whole block: a scalar
+        // load (constant address space), which waits for none of the vector
+        // loads issued above
+        const unsigned tmask = static_cast<unsigned>(
+            ((const int __attribute__((address_space(4)))*)P.tmeta)[P.tmeta_off[it.a] + it.b]);
         pt_gather_window<S, C, (RPT < 8 ? RPT : 8)>(P, vptr<S>(J, in_vec, it.frame), it.a, N, px0,
-                                                    py0, PW, PW, &sA[0][0], PW + 1,
-                                                    static_cast<unsigned>(P.tmeta[P.tmeta_off[it.a] + it.b]));
+                                                    py0, PW, PW, &sA[0][0], PW + 1, tmask);
     } else if (level > 1) {
         // the low-pass band of the level below (scratch)
         const C* ind = ll_ptr<C>(J, it.frame) + Ly.ll_off[level - 1];
+        int64_t off[WIN_IT];
+        window_offsets<PW, WIN_IT>(px0, py0, M, M, off);
+        C v[WIN_IT];
+#pragma unroll
+        for (int k = 0; k < WIN_IT; ++k) v[k] = ind[off[k]];
 #pragma unroll
         for (int k = 0; k < WIN_IT; ++k) {
-            const int e0 = threadIdx.x + k * TILE_NT, e = min(e0, PW * PW - 1);
-            const int a = e / PW, b = e % PW;
-            int gx = px0 + a, gy = py0 + b;   // periodic wrap
-            while (gx >= M) gx -= M;
-            while (gy >= M) gy -= M;
-            const C v = ind[static_cast<int64_t>(gx) * M + gy];
-            if (e0 < PW * PW) sA[a][b] = v;
+            const int e0 = threadIdx.x + k * TILE_NT;
+            if (e0 < PW * PW) sA[e0 / PW][e0 % PW] = v[k];
         }
     } else {
         const S* in = vptr<S>(J, in_vec, it.frame) + Ly.coff;
+        int64_t off[WIN_IT];
+        window_offsets<PW, WIN_IT>(px0, py0, M, N, off);
+        S v[WIN_IT];
+#pragma unroll
+        for (int k = 0; k < WIN_IT; ++k) v[k] = in[off[k]];
 #pragma unroll
         for (int k = 0; k < WIN_IT; ++k) {
-            const int e0 = threadIdx.x + k * TILE_NT, e = min(e0, PW * PW - 1);
-            const int a = e / PW, b = e % PW;
-            int gx = px0 + a, gy = py0 + b;   // periodic wrap
-            while (gx >= M) gx -= M;
-            while (gy >= M) gy -= M;
-            const S v = in[static_cast<int64_t>(gx) * N + gy];
-            if (e0 < PW * PW) sA[a][b] = static_cast<C>(v);
+            const int e0 = threadIdx.x + k * TILE_NT;
+            if (e0 < PW * PW) sA[e0 / PW][e0 % PW] = static_cast<C>(v[k]);
         }
     }
     __syncthreads();
@@ -1278,7 +1349,7 @@ k_adjoint(const JobArgs args, const Item* __restrict__ items, int in_vec, int ou
 template <class S>
 __device__ void project_sensor(const JobPlan& J, const PlanDev& P, int m, int frame, int in_vec,
                                int nn, Acc* U) {
-    const S* pix = vptr<S>(J, in_vec, frame);
+    const gptr<S> pix = as_global(vptr<S>(J, in_vec, frame));
     for (int e = threadIdx.x; e < nn * nn; e += blockDim.x) {
         const int r = e / nn, c = e % nn;
         Acc acc = 0;
@@ -1288,7 +1359,7 @@ __device__ void project_sensor(const JobPlan& J, const PlanDev& P, int m, int fr
             Acc t, sw;
             node_stencil(P.pa[m][l], P.pb[0][m][l], r, N, i0, t);
             node_stencil(P.pa[m][l], P.pb[1][m][l], c, N, j0, sw);
-            const S* q = pix + P.layer[l].coff + static_cast<int64_t>(i0) * N + j0;
+            const gptr<S> q = pix + P.layer[l].coff + static_cast<int64_t>(i0) * N + j0;
             const Acc a0 = static_cast<Acc>(q[0]), a1 = static_cast<Acc>(q[1]);
             const Acc b0 = static_cast<Acc>(q[N]), b1 = static_cast<Acc>(q[N + 1]);
             const Acc x = fma(sw, a1 - a0, a0), y = fma(sw, b1 - b0, b0);
@@ -1320,6 +1391,10 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
     const int m = it.a;
     const WfsInfo& w = P.wfs[m];
     const int ns = w.n_sub, nn = w.nn, Sf = w.S_fine, S = w.S;
+    // the sensor's tables, read as global memory (see as_global)
+    const gptr<int> act = as_global(w.act), cell_of = as_global(w.cell_of);
+    const gptr<int> cell_count = as_global(w.cell_count);
+    const gptr<double> blk = as_global(w.blocks);
     const int tid = threadIdx.x, bd = blockDim.x;
     Acc sx[QM], sy[QM];
 #pragma unroll
@@ -1339,7 +1414,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
 #pragma unroll
         for (int r = 0; r < QM; ++r) {
             const int q = tid + r * bd;
-            if (q < S) sx[r] = (mode != SM_RHS) ? U[w.act[q]] : static_cast<Acc>(in[q]);
+            if (q < S) sx[r] = (mode != SM_RHS) ? U[act[q]] : static_cast<Acc>(in[q]);
         }
         if (mode == SM_FWD) {
             T* out = vptr<T>(J, out_vec, it.frame) + w.soff;
@@ -1356,7 +1431,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
 #pragma unroll
         for (int r = 0; r < QM; ++r) {
             const int q = tid + r * bd;
-            if (q < S) U[w.act[q]] = w.blocks[3 * q] * sx[r];
+            if (q < S) U[act[q]] = blk[3 * q] * sx[r];
         }
         __syncthreads();
         SO* vout = vptr<SO>(J, out_vec, it.frame) + w.node_off;
@@ -1376,7 +1451,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
         for (int r = 0; r < QM; ++r) {
             const int q = tid + r * bd;
             if (q < Sf) {
-                const int pk = w.act[q];
+                const int pk = act[q];
                 const int i = pk / ns, j = pk % ns;
                 const Acc u00 = U[i * nn + j], u10 = U[(i + 1) * nn + j];
                 const Acc u01 = U[i * nn + j + 1], u11 = U[(i + 1) * nn + j + 1];
@@ -1385,7 +1460,6 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
             }
         }
     }
-    const double* blk = w.blocks;
 
     if (w.agg) {
         if (mode != SM_RHS) {
@@ -1394,7 +1468,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
 #pragma unroll
                 for (int r = 0; r < QM; ++r) {
                     const int q = tid + r * bd;
-                    if (q < Sf && w.cell_of[q] == c) {
+                    if (q < Sf && cell_of[q] == c) {
                         px += sx[r];
                         py += sy[r];
                     }
@@ -1402,8 +1476,8 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
                 px = block_sum(px, red);
                 py = block_sum(py, red);
                 if (tid == 0) {
-                    cellx[c] = px / w.cell_count[c];
-                    celly[c] = py / w.cell_count[c];
+                    cellx[c] = px / cell_count[c];
+                    celly[c] = py / cell_count[c];
                 }
             }
         } else if (tid < S) {
@@ -1437,8 +1511,8 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
             }
             if (w.remove_tt) { nx /= S; ny /= S; } else { nx = ny = 0.0; }
             for (int c = 0; c < S; ++c) {
-                cellx[c] = (cwx[c] - nx) / w.cell_count[c];
-                celly[c] = (cwy[c] - ny) / w.cell_count[c];
+                cellx[c] = (cwx[c] - nx) / cell_count[c];
+                celly[c] = (cwy[c] - ny) / cell_count[c];
             }
         }
         __syncthreads();
@@ -1446,7 +1520,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
         for (int r = 0; r < QM; ++r) {
             const int q = tid + r * bd;
             if (q < Sf) {
-                const int c = w.cell_of[q];
+                const int c = cell_of[q];
                 sx[r] = cellx[c];
                 sy[r] = celly[c];
             }
@@ -1510,7 +1584,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
 #pragma unroll
     for (int r = 0; r < QM; ++r) {
         const int q = tid + r * bd;
-        if (q < Sf) U[w.act[q]] = sx[r];
+        if (q < Sf) U[act[q]] = sx[r];
     }
     __syncthreads();
 #pragma unroll
@@ -1532,7 +1606,7 @@ k_sensor(const JobArgs args, const Item* __restrict__ items, int mode, int in_ve
 #pragma unroll
     for (int r = 0; r < QM; ++r) {
         const int q = tid + r * bd;
-        if (q < Sf) U[w.act[q]] = sy[r];
+        if (q < Sf) U[act[q]] = sy[r];
     }
     __syncthreads();
     SO* vout = vptr<SO>(J, out_vec, it.frame) + w.node_off;
