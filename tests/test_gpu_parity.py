@@ -34,6 +34,8 @@ CASES = [
     ("c2-f64", WL.config_c2, "f64", {}),
     ("c2-f32", WL.config_c2, "f32", {}),
     ("c2-f64-lds160", WL.config_c2, "f64", {"lds_budget": 160 * 1024}),
+    # 40..64-wide coarse blocks, rebuilt in each level-k0 synthesis tile
+    ("c2-f32-lds32", WL.config_c2, "f32", {"lds_budget": 32 * 1024}),
     ("c2-f32-tile64", WL.config_c2, "f32", {"tile": 64}),
     # single-precision operators on the small systems too (their default is
     # FP64 operators), at several tiles and with ragged tails
