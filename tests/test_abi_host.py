@@ -93,3 +93,19 @@ def test_null_arguments_rejected():
     assert L.wmcao_serve_launch(None, None, None, 1, None, None, 0, None, None, 1, None) == -1
     assert L.wmcao_sizes(None, None, None, None, None) == -1
     L.wmcao_plan_destroy(None)
+
+
+def test_every_autotuner_candidate_passes_option_checks():
+    """Each work shape the autotuner may try is one the plan accepts: option
+    checks run on the host before the device is touched, so without a GPU a
+    valid plan stops at the device (no HIP device), never at an option."""
+    from paper_1302_3734_amd import autotune
+    L = _abi.lib()
+    for name, cands in autotune.SPACE.items():
+        for v in cands:
+            pupil, Ls, Ws, wav, levels, opts = _args(**{name: v})
+            h = C.c_void_p()
+            rc = L.wmcao_plan(C.byref(pupil), Ls, 1, Ws, 1, wav, levels, C.byref(opts), C.byref(h))
+            if rc == 0:
+                L.wmcao_plan_destroy(h)
+            assert rc != -1, (name, v, L.wmcao_last_error())
